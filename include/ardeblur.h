@@ -1,0 +1,160 @@
+/*
+ * ardeblur.h -- C ABI of the MI355X (gfx950) library for preconditioned
+ * Landweber deblurring under Anti-Reflective (AR) boundary conditions.
+ *
+ * Method: Dell'Acqua, Serra-Capizzano, Tablino-Possio, "Optimal
+ * preconditioning for image deblurring with Anti-Reflective boundary
+ * conditions" (arXiv 1211.0393).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Images are n1 x n2, row-major: i1 (row) is the slow axis, i2 (column)
+ *    the fast, contiguous one (Sec. 1: row-wise ordering from the top-left
+ *    corner).  Element (i1, i2) sits at offset i1 * n2 + i2.
+ *  - Image buffers are DEVICE pointers on the plan's device, owned by the
+ *    caller; the library never frees them.  Their element type is the plan
+ *    dtype (AR_F32 -> float, AR_F64 -> double) unless stated otherwise.
+ *  - The PSF is a HOST array of (2 q1 + 1) x (2 q2 + 1) doubles, row-major,
+ *    psf[(q1 + s1) * (2 q2 + 1) + (q2 + s2)] = h_{s1,s2} (eq.
+ *    (coefficienti_psf)).  It must be finite, nonnegative, sum to 1 within
+ *    1e-12 * (number of taps), and satisfy the support condition of Sec. 2.2
+ *    (q_j <= n_j - 3; n_j >= 3).  It is copied at plan creation.
+ *  - The blur is a true convolution g_i = sum_s h_s f_{i-s}
+ *    (eq. (modello_discreto)) of the AR-extended image (Sec. 2.2).
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Every call is stream-ordered and asynchronous unless it returns host
+ *    scalars (then it synchronizes that stream before returning).
+ *  - Every function returns AR_OK (0) or a negative ar_status; on failure
+ *    ar_last_error() gives a message (thread-local).  No call aborts.
+ *  - A plan may be used by one host thread at a time; its scratch buffers
+ *    are shared by all calls on it, so calls on one plan must not overlap
+ *    on different streams.  Distinct plans are independent.
+ */
+#ifndef ARDEBLUR_H
+#define ARDEBLUR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ar_plan_s *ar_plan_t;
+
+enum ar_dtype { AR_F32 = 0, AR_F64 = 1 };
+
+/* Transpose used by the iteration: the reblurring A' = A(PSF rotated by
+ * 180 degrees) that the paper's experiments use (Sec. 4), or the exact
+ * transpose A^T written in eq. (LandweberMeth). */
+enum ar_tmode { AR_REBLUR = 0, AR_ADJOINT = 1 };
+
+/* Eigenvalue filter giving the spectrum d of the preconditioner D.
+ *  TIKHONOV : d = 1 / (lambda^2 + param)          (eq. (TikFilter))
+ *  THRESHOLD: d = 1 / lambda^2 if |lambda| >= param, else 1
+ *             (truncated-spectrum filter; not in the paper)
+ *  IDENTITY : d = 1 (D = I, plain Landweber)                           */
+enum ar_filter { AR_FILTER_TIKHONOV = 0, AR_FILTER_THRESHOLD = 1, AR_FILTER_IDENTITY = 3 };
+
+enum ar_status {
+  AR_OK = 0,
+  AR_EINVAL = -1,       /* bad argument (null pointer, unknown enum, iters < 0, ...) */
+  AR_ESHAPE = -2,       /* n_j < 3 or q_j > n_j - 3 or sizes too large */
+  AR_EPSF = -3,         /* PSF entry negative / non-finite, or sum != 1 */
+  AR_EALIAS = -4,       /* input and output buffers alias where forbidden */
+  AR_EDEVICE = -5,      /* HIP runtime error (message has the HIP string) */
+  AR_ENOMEM = -6,       /* device allocation failed */
+  AR_ENONFINITE = -7,   /* a residual norm became NaN or Inf during iteration */
+  AR_EUNSUPPORTED = -8  /* valid request this build does not implement */
+};
+
+/* Create a plan for n1 x n2 images and one PSF (S0-S2 of the path):
+ * validates the arguments, copies the PSF to the device, and on the device
+ * builds the blur weights, the symmetrized PSF
+ *   s_{+-i1,+-i2} = (h_{-i1,-i2} + h_{-i1,i2} + h_{i1,-i2} + h_{i1,i2}) / 4
+ * (Theorem 4, eq. (simmetrizzata2d-bis)), its eigenvalues lambda in FP64
+ * on the extended grid of Theorem 2 (column order of T_{n1} (x) T_{n2}),
+ * and the default Tikhonov filter with param = 1e-2.  Device scratch for
+ * the iteration is allocated here and owned by the plan.
+ *   out    : receives the plan (set to NULL on failure)
+ *   dtype  : AR_F32 or AR_F64 (image buffers' element type)
+ *   device : HIP device ordinal the plan lives on
+ * Errors: AR_EINVAL, AR_ESHAPE, AR_EPSF, AR_EDEVICE, AR_ENOMEM. */
+int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_host,
+                   int q1, int q2, int dtype, int device);
+
+/* Release a plan and its device memory (waits for the device).  NULL is a
+ * no-op returning AR_OK. */
+int ar_plan_destroy(ar_plan_t p);
+
+/* y = A_n x: AR extension of x (edges f_{1-i} = 2 f_1 - f_{1+i},
+ * f_{n+i} = 2 f_n - f_{n-i}; corners by double anti-reflection, Sec. 2.2)
+ * followed by the convolution of eq. (modello_discreto).
+ * x, y: device, n1*n2, plan dtype; x == y is rejected (AR_EALIAS). */
+int ar_blur_apply(ar_plan_t p, const void *x, void *y, void *stream);
+
+/* y = A' r (tmode AR_REBLUR: the blur with the PSF rotated by 180 degrees,
+ * Sec. 4) or y = A_n^T r (tmode AR_ADJOINT: exact transpose, i.e. the
+ * correlation with h scattered to the extended grid and folded back with
+ * the transposed AR weights +2 / -1 per axis).
+ * r, y: device, n1*n2, plan dtype; r == y is rejected (AR_EALIAS). */
+int ar_blur_apply_T(ar_plan_t p, const void *r, void *y, int tmode, void *stream);
+
+/* c = T~ x with T~ = T~_{n1} (x) T~_{n2}, the inverse of the AR transform
+ * of Theorem 1: per axis of length m, c_1 = alpha_m x_1, c_m = alpha_m x_m,
+ * c_mid = Q_{m-2} (x_mid - x_1 p - x_m J p), p_j = 1 - j/(m-1), Q the DST-I
+ * matrix of eq. (Qn), alpha_m = sqrt(m (2m-1) / (6 (m-1))).
+ * Coefficients are stored n1 x n2 in the column order of T.
+ * x, c: device, plan dtype; x == c (in place) is allowed. */
+int ar_transform(ar_plan_t p, const void *x, void *c, void *stream);
+
+/* x = T c, the AR transform of Theorem 1 (inverse of ar_transform):
+ * x_1 = c_1 / alpha, x_m = c_m / alpha, x_mid = Q c_mid + x_1 p + x_m J p.
+ * c, x: device, plan dtype; in place allowed. */
+int ar_transform_inv(ar_plan_t p, const void *c, void *x, void *stream);
+
+/* Set the preconditioner spectrum d from lambda (Sec. 4): filter is an
+ * ar_filter, param its parameter (Tikhonov alpha > 0, threshold t > 0,
+ * ignored for IDENTITY).  Computed in FP64 on the device; stored in FP64
+ * and in the plan dtype.  Errors: AR_EINVAL. */
+int ar_precond_set(ar_plan_t p, int filter, double param, void *stream);
+
+/* Copy the FP64 eigenvalues lambda (n1*n2, coefficient layout) of the
+ * symmetrized PSF's AR matrix into the device buffer lambda_dev. */
+int ar_eigenvalues(ar_plan_t p, double *lambda_dev, void *stream);
+
+/* Copy the FP64 filter spectrum d (n1*n2) into the device buffer d_dev. */
+int ar_filter_values(ar_plan_t p, double *d_dev, void *stream);
+
+/* z = D y with D = T diag(d) T~ (Sec. 4; for the Tikhonov filter this is
+ * (P(s)^2 + alpha I)^{-1} y, P(s) the AR matrix of the symmetrized PSF).
+ * y, z: device, plan dtype; y == z allowed. */
+int ar_precond_solve(ar_plan_t p, const void *y, void *z, void *stream);
+
+/* Run `iters` steps of (D-)Landweber (eqs. (LandweberMeth) and
+ * (DLandweberMeth)):  x_{k+1} = x_k + tau D A'(g - A x_k)  with A' chosen
+ * by tmode and D = I when precondition == 0.
+ *   g       : device, n1*n2, plan dtype (observed image)
+ *   x       : device, n1*n2, plan dtype; in: x_0, out: x_iters
+ *   f_true  : device or NULL; when given, RRE_k = ||x_k - f||_F / ||f||_F
+ *             is accumulated in FP64 for k = 1..iters
+ *   resnorm_host : host array of iters doubles or NULL:
+ *             resnorm[k] = ||g - A x_k||_F (FP64 accumulation), k = 0..iters-1
+ *   rre_host     : host array of iters doubles or NULL: rre[k] = RRE(x_{k+1})
+ *   best_it_host : host int or NULL: first k >= 1 minimising RRE(x_k)
+ *                  (needs f_true)
+ * Host outputs imply one synchronization at the end.  If a requested
+ * residual norm is not finite the call returns AR_ENONFINITE (x holds the
+ * last iterate).  g, x, f_true must not alias. */
+int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters, double tau,
+                      int tmode, int precondition, const void *f_true,
+                      double *resnorm_host, double *rre_host, int *best_it_host,
+                      void *stream);
+
+/* Thread-local message describing the last failure ("" if none). */
+const char *ar_last_error(void);
+
+/* Library version string. */
+const char *ar_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARDEBLUR_H */

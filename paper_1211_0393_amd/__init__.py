@@ -1,0 +1,22 @@
+"""MI355X (gfx950) preconditioned Landweber deblurring under Anti-Reflective
+boundary conditions: Python binding of the HIP library libardeblur.so.
+
+The binding only marshals arguments; every step of the method runs in the
+library's HIP kernels.  Build the library with
+``python -m paper_1211_0393_amd.build``."""
+
+from ._lib import (  # noqa: F401
+    AR_ADJOINT,
+    AR_F32,
+    AR_F64,
+    AR_FILTER_IDENTITY,
+    AR_FILTER_THRESHOLD,
+    AR_FILTER_TIKHONOV,
+    AR_REBLUR,
+    ArError,
+    LIB_PATH,
+    Plan,
+    SIGNATURES,
+    load,
+    version,
+)

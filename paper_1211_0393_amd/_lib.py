@@ -1,0 +1,183 @@
+"""ctypes binding of libardeblur.so (argument marshalling only).
+
+Every function mirrors one C entry point of ``include/ardeblur.h`` under the
+same name.  Image arguments are torch tensors on the plan's device (their
+data pointers are passed through); streams default to torch's current
+stream.  Nothing here computes any step of the method: if the library is
+missing the import fails loudly.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libardeblur.so")
+
+AR_F32, AR_F64 = 0, 1
+AR_REBLUR, AR_ADJOINT = 0, 1
+AR_FILTER_TIKHONOV, AR_FILTER_THRESHOLD, AR_FILTER_IDENTITY = 0, 1, 3
+
+STATUS = {
+    0: "AR_OK", -1: "AR_EINVAL", -2: "AR_ESHAPE", -3: "AR_EPSF", -4: "AR_EALIAS",
+    -5: "AR_EDEVICE", -6: "AR_ENOMEM", -7: "AR_ENONFINITE", -8: "AR_EUNSUPPORTED",
+}
+
+# (name, restype, argtypes) of every exported entry point
+_VP, _I, _D = C.c_void_p, C.c_int, C.c_double
+SIGNATURES = [
+    ("ar_plan_create", _I, [C.POINTER(_VP), _I, _I, C.POINTER(_D), _I, _I, _I, _I]),
+    ("ar_plan_destroy", _I, [_VP]),
+    ("ar_blur_apply", _I, [_VP, _VP, _VP, _VP]),
+    ("ar_blur_apply_T", _I, [_VP, _VP, _VP, _I, _VP]),
+    ("ar_transform", _I, [_VP, _VP, _VP, _VP]),
+    ("ar_transform_inv", _I, [_VP, _VP, _VP, _VP]),
+    ("ar_precond_set", _I, [_VP, _I, _D, _VP]),
+    ("ar_eigenvalues", _I, [_VP, _VP, _VP]),
+    ("ar_filter_values", _I, [_VP, _VP, _VP]),
+    ("ar_precond_solve", _I, [_VP, _VP, _VP, _VP]),
+    ("ar_deblur_iterate", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _VP,
+                               C.POINTER(_D), C.POINTER(_D), C.POINTER(_I), _VP]),
+    ("ar_last_error", C.c_char_p, []),
+    ("ar_version", C.c_char_p, []),
+]
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load the shared library (raises if it is not built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is not built; run `python -m paper_1211_0393_amd.build`")
+    lib = C.CDLL(p)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+class ArError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(rc):
+    if rc != 0:
+        raise ArError(rc, load().ar_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """Owns an ``ar_plan_t``; methods are the C entry points."""
+
+    def __init__(self, n1, n2, psf, dtype="f32", device=0):
+        psf = np.ascontiguousarray(psf, dtype=np.float64)
+        if psf.ndim != 2:
+            raise ValueError("psf must be 2-D")
+        self.n1, self.n2 = int(n1), int(n2)
+        self.q1, self.q2 = (psf.shape[0] - 1) // 2, (psf.shape[1] - 1) // 2
+        self.dtype = {"f32": AR_F32, "f64": AR_F64}[dtype]
+        self.device = int(device)
+        self._h = C.c_void_p()
+        lib = load()
+        _check(lib.ar_plan_create(C.byref(self._h), self.n1, self.n2,
+                                  psf.ctypes.data_as(C.POINTER(C.c_double)),
+                                  self.q1, self.q2, self.dtype, self.device))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load().ar_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # --- entry points -------------------------------------------------
+    def ar_blur_apply(self, x, y, stream=None):
+        _check(load().ar_blur_apply(self._h, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def ar_blur_apply_T(self, r, y, tmode=AR_REBLUR, stream=None):
+        _check(load().ar_blur_apply_T(self._h, _ptr(r), _ptr(y), int(tmode), _stream(stream)))
+        return y
+
+    def ar_transform(self, x, c, stream=None):
+        _check(load().ar_transform(self._h, _ptr(x), _ptr(c), _stream(stream)))
+        return c
+
+    def ar_transform_inv(self, c, x, stream=None):
+        _check(load().ar_transform_inv(self._h, _ptr(c), _ptr(x), _stream(stream)))
+        return x
+
+    def ar_precond_set(self, filt=AR_FILTER_TIKHONOV, param=1e-2, stream=None):
+        _check(load().ar_precond_set(self._h, int(filt), float(param), _stream(stream)))
+
+    def ar_eigenvalues(self, lam, stream=None):
+        _check(load().ar_eigenvalues(self._h, _ptr(lam), _stream(stream)))
+        return lam
+
+    def ar_filter_values(self, d, stream=None):
+        _check(load().ar_filter_values(self._h, _ptr(d), _stream(stream)))
+        return d
+
+    def ar_precond_solve(self, y, z, stream=None):
+        _check(load().ar_precond_solve(self._h, _ptr(y), _ptr(z), _stream(stream)))
+        return z
+
+    def ar_deblur_iterate(self, g, x, iters, tau=1.0, tmode=AR_REBLUR, precondition=True,
+                          f_true=None, want_resnorm=False, want_rre=False, stream=None):
+        """Returns (status, resnorm or None, rre or None, best_it or None)."""
+        res = (C.c_double * iters)() if want_resnorm and iters > 0 else None
+        rre = (C.c_double * iters)() if want_rre and iters > 0 else None
+        best = C.c_int(0) if want_rre else None
+        rc = load().ar_deblur_iterate(
+            self._h, _ptr(g), _ptr(x), int(iters), float(tau), int(tmode), int(bool(precondition)),
+            _ptr(f_true),
+            C.cast(res, C.POINTER(C.c_double)) if res is not None else None,
+            C.cast(rre, C.POINTER(C.c_double)) if rre is not None else None,
+            C.byref(best) if best is not None else None,
+            _stream(stream))
+        if rc not in (0, -7):
+            _check(rc)
+        return (rc,
+                np.array(res[:]) if res is not None else None,
+                np.array(rre[:]) if rre is not None else None,
+                best.value if best is not None else None)
+
+
+def version():
+    return load().ar_version().decode()

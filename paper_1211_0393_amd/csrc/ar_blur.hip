@@ -1,0 +1,340 @@
+// AR-BC blur kernels: A x, A' r, A^T r (gfx950).
+//
+// The blur is the convolution g_i = sum_s h_s f_{i-s} (eq. (modello_discreto))
+// of the image extended by anti-reflection (Sec. 2.2).  Each workgroup owns a
+// TH x TW output tile; it stages the (TH + 2 q1) x (TW + 2 q2) input halo in
+// LDS, computing ghost pixels on load from the AR rule (edges: 2 f_1 - f_{1+i};
+// corners: the double anti-reflection 4, -2, -2, +1 obtained by applying the
+// 1-D rule per axis).  Every thread then produces RY x RX outputs with a
+// sliding window over input rows so that one LDS row feeds two output rows;
+// PSF weights are wave-uniform and come through scalar loads.
+//
+// The same kernel computes
+//   * A x          : weights rot180(H), AR extension, outputs on the FOV;
+//   * A' r         : weights H (PSF rotated by 180 degrees, Sec. 4);
+//   * C^T r of A^T : weights H, zero outside the FOV, outputs on the extended
+//                    grid [-q, n-1+q]; a second kernel folds the ghosts back.
+// With `gsub` it writes g - (A x) and per-workgroup FP64 partial sums of the
+// squared residual.
+#include "ar_internal.h"
+
+namespace ar {
+namespace {
+
+constexpr int TX = 16, TY = 16, NT = TX * TY;
+constexpr int RX = 4, RY = 2;
+constexpr int TW = TX * RX;  // 64 output columns per tile
+constexpr int TH = TY * RY;  // 32 output rows per tile
+
+// Bijective remap of the workgroup id so that consecutive logical tiles run
+// on the same XCD (workgroups are dealt round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  const int x = b & 7, i = b >> 3;
+  const int g8 = G >> 3, rem = G & 7;
+  const int start = x * g8 + (x < rem ? x : rem);
+  return start + i;
+}
+
+// AR extension rule along one axis: position i of an axis of length n maps
+// to w0 * f[i0] + w1 * f[i1] (w1 == 0 for an interior position).  Positions
+// beyond one halo width are never consumed by a stored output; they read 0.
+struct Rule { int i0, i1; float w0, w1; };
+
+__device__ __forceinline__ Rule ar_rule(int i, int n, int q) {
+  Rule r;
+  if (i >= 0 && i < n) { r.i0 = i; r.i1 = i; r.w0 = 1.f; r.w1 = 0.f; }
+  else if (i < 0 && i >= -q) { r.i0 = 0; r.i1 = -i; r.w0 = 2.f; r.w1 = -1.f; }        // f_{1-t} = 2 f_1 - f_{1+t}
+  else if (i >= n && i <= n - 1 + q) { r.i0 = n - 1; r.i1 = 2 * n - 2 - i; r.w0 = 2.f; r.w1 = -1.f; }  // f_{n+t} = 2 f_n - f_{n-t}
+  else { r.i0 = 0; r.i1 = 0; r.w0 = 0.f; r.w1 = 0.f; }
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T load_ext(const T *__restrict__ in, int n1, int n2, int q1, int q2,
+                                      int i, int j, bool zero_ext) {
+  if (i >= 0 && i < n1 && j >= 0 && j < n2) return in[(size_t)i * n2 + j];
+  if (zero_ext) return T(0);
+  const Rule a = ar_rule(i, n1, q1), b = ar_rule(j, n2, q2);
+  if (a.w0 == 0.f || b.w0 == 0.f) return T(0);
+  // tensor product of the two 1-D rules: one, two or four terms
+  T v = T(a.w0) * (T(b.w0) * in[(size_t)a.i0 * n2 + b.i0]);
+  if (b.w1 != 0.f) v += T(a.w0) * (T(b.w1) * in[(size_t)a.i0 * n2 + b.i1]);
+  if (a.w1 != 0.f) {
+    v += T(a.w1) * (T(b.w0) * in[(size_t)a.i1 * n2 + b.i0]);
+    if (b.w1 != 0.f) v += T(a.w1) * (T(b.w1) * in[(size_t)a.i1 * n2 + b.i1]);
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  // fixed-order reduction: xor-shuffle inside each wave, then wave 0 adds
+  // the four wave sums in order
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NT / 64; ++k) s += red[k];
+  }
+  return s;
+}
+
+// Q2 >= 0: compile-time column half-width (tap loop fully unrolled).
+// Q2 <  0: generic kernel with a runtime column half-width.
+template <typename T, int Q2>
+__global__ __launch_bounds__(NT) void conv_kernel(
+    const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ w, int n1, int n2,
+    int q1, int q2rt, int o1, int o2, int m1, int m2, int zero_ext, const T *__restrict__ gsub,
+    double *__restrict__ partial, int tiles_x) {
+  constexpr bool GEN = Q2 < 0;
+  const int q2 = GEN ? q2rt : Q2;
+  const int KW = 2 * q2 + 1;
+  const int LW = TW + 2 * q2;
+  const int pitch = (LW + 3) & ~3;
+  const int LH = TH + 2 * q1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *tile = reinterpret_cast<T *>(smem_raw);
+
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int ty_tile = logical / tiles_x, tx_tile = logical - ty_tile * tiles_x;
+  const int r0 = ty_tile * TH, c0 = tx_tile * TW;
+  const int ib1 = o1 + r0 - q1, ib2 = o2 + c0 - q2;
+  const int tid = threadIdx.x;
+  const bool inside = ib1 >= 0 && ib2 >= 0 && ib1 + LH <= n1 && ib2 + LW <= n2;
+  // stage the halo tile: 4 rows x 64 columns of threads per sweep
+  const int lr = tid >> 6, lc = tid & 63;
+  if (inside) {
+    for (int a = lr; a < LH; a += NT / 64) {
+      const T *src = in + (size_t)(ib1 + a) * n2 + ib2;
+      for (int c = lc; c < LW; c += 64) tile[a * pitch + c] = src[c];
+    }
+  } else {
+    for (int a = lr; a < LH; a += NT / 64)
+      for (int c = lc; c < LW; c += 64)
+        tile[a * pitch + c] = load_ext(in, n1, n2, q1, q2, ib1 + a, ib2 + c, zero_ext != 0);
+  }
+  __syncthreads();
+
+  const int tx = tid % TX, ty = tid / TX;
+  const int lx = tx * RX, ly = ty * RY;
+  T acc0[RX], acc1[RX];
+#pragma unroll
+  for (int c = 0; c < RX; ++c) { acc0[c] = T(0); acc1[c] = T(0); }
+
+  const int krows = 2 * q1 + 2;
+  if constexpr (!GEN) {
+    constexpr int KWc = 2 * Q2 + 1;
+    constexpr int NV = RX + 2 * Q2;
+    for (int k = 0; k < krows; ++k) {
+      const T *rowp = tile + (ly + k) * pitch + lx;
+      T v[NV];
+#pragma unroll
+      for (int t = 0; t < NV; ++t) v[t] = rowp[t];
+      if (k <= 2 * q1) {
+        const T *wr = w + k * KWc;
+#pragma unroll
+        for (int b = 0; b < KWc; ++b) {
+          const T wb = wr[b];
+#pragma unroll
+          for (int c = 0; c < RX; ++c) acc0[c] = fma(wb, v[c + b], acc0[c]);
+        }
+      }
+      if (k >= 1) {
+        const T *wr = w + (k - 1) * KWc;
+#pragma unroll
+        for (int b = 0; b < KWc; ++b) {
+          const T wb = wr[b];
+#pragma unroll
+          for (int c = 0; c < RX; ++c) acc1[c] = fma(wb, v[c + b], acc1[c]);
+        }
+      }
+    }
+  } else {
+    for (int k = 0; k < krows; ++k) {
+      const T *rowp = tile + (ly + k) * pitch + lx;
+      if (k <= 2 * q1) {
+        const T *wr = w + k * KW;
+        for (int b = 0; b < KW; ++b) {
+          const T wb = wr[b];
+#pragma unroll
+          for (int c = 0; c < RX; ++c) acc0[c] = fma(wb, rowp[c + b], acc0[c]);
+        }
+      }
+      if (k >= 1) {
+        const T *wr = w + (k - 1) * KW;
+        for (int b = 0; b < KW; ++b) {
+          const T wb = wr[b];
+#pragma unroll
+          for (int c = 0; c < RX; ++c) acc1[c] = fma(wb, rowp[c + b], acc1[c]);
+        }
+      }
+    }
+  }
+
+  double ss = 0.0;
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int oi = r0 + ly + r;
+    if (oi >= m1) continue;
+#pragma unroll
+    for (int c = 0; c < RX; ++c) {
+      const int oj = c0 + lx + c;
+      if (oj >= m2) continue;
+      T val = r == 0 ? acc0[c] : acc1[c];
+      const size_t o = (size_t)oi * m2 + oj;
+      if (gsub) {
+        val = gsub[o] - val;
+        ss += (double)val * (double)val;
+      }
+      out[o] = val;
+    }
+  }
+  if (partial) {
+    // the tile is no longer read: reuse LDS for the reduction
+    double *red = reinterpret_cast<double *>(smem_raw);
+    const double s = block_sum<T>(ss, red);
+    if (tid == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// Fold of the extended-grid correlation back onto the FOV (transpose of the
+// AR extension): along each axis a ghost at 1 - t adds 2x to position 1 and
+// -1x to position 1 + t, a ghost at n + t adds 2x to n and -1x to n - t.
+template <typename T>
+__global__ __launch_bounds__(256) void fold_kernel(const T *__restrict__ ext, T *__restrict__ out,
+                                                   int n1, int n2, int q1, int q2) {
+  const int j2 = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j1 = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (j1 >= n1 || j2 >= n2) return;
+  const int W = n2 + 2 * q2;
+  // per-axis lists (position on the extended grid, weight)
+  int e1[40], e2[40];
+  float w1[40], w2[40];
+  int c1 = 0, c2 = 0;
+  auto build = [](int j, int n, int q, int *e, float *wv, int &cnt) {
+    e[cnt] = j; wv[cnt] = 1.f; ++cnt;
+    if (j == 0)
+      for (int t = 1; t <= q; ++t) { e[cnt] = -t; wv[cnt] = 2.f; ++cnt; }
+    if (j >= 1 && j <= q) { e[cnt] = -j; wv[cnt] = -1.f; ++cnt; }
+    if (j == n - 1)
+      for (int t = 1; t <= q; ++t) { e[cnt] = n - 1 + t; wv[cnt] = 2.f; ++cnt; }
+    if (j >= n - 1 - q && j <= n - 2) { e[cnt] = 2 * n - 2 - j; wv[cnt] = -1.f; ++cnt; }
+  };
+  build(j1, n1, q1, e1, w1, c1);
+  build(j2, n2, q2, e2, w2, c2);
+  T acc = T(0);
+  for (int a = 0; a < c1; ++a) {
+    const T *row = ext + (size_t)(e1[a] + q1) * W + q2;
+    T s = T(0);
+    for (int b = 0; b < c2; ++b) s += T(w2[b]) * row[e2[b]];
+    acc += T(w1[a]) * s;
+  }
+  out[(size_t)j1 * n2 + j2] = acc;
+}
+
+template <typename T, int Q2>
+void *conv_fn() { return reinterpret_cast<void *>(&conv_kernel<T, Q2>); }
+
+template <typename T>
+hipError_t launch_conv_t(const ar_plan_s *p, const void *in, void *out, const void *w, int o1,
+                         int o2, int m1, int m2, bool zero_ext, const void *g, double *partial,
+                         int blocks, int tiles_x, hipStream_t st) {
+  const int q1 = p->q1, q2 = p->q2;
+  const int LW = TW + 2 * q2, pitch = (LW + 3) & ~3, LH = TH + 2 * q1;
+  size_t smem = (size_t)LH * pitch * sizeof(T);
+  if (smem < 64 * sizeof(double)) smem = 64 * sizeof(double);
+  const T *ti = static_cast<const T *>(in);
+  T *to = static_cast<T *>(out);
+  const T *tw = static_cast<const T *>(w);
+  const T *tg = static_cast<const T *>(g);
+  const int ze = zero_ext ? 1 : 0;
+#define AR_CONV_CASE(QQ)                                                                  \
+  case QQ:                                                                                \
+    hipLaunchKernelGGL((conv_kernel<T, QQ>), dim3(blocks), dim3(NT), smem, st, ti, to, tw, \
+                       p->n1, p->n2, q1, q2, o1, o2, m1, m2, ze, tg, partial, tiles_x);   \
+    break;
+  switch (q2) {
+    AR_CONV_CASE(0) AR_CONV_CASE(1) AR_CONV_CASE(2) AR_CONV_CASE(3) AR_CONV_CASE(4)
+    AR_CONV_CASE(5) AR_CONV_CASE(6) AR_CONV_CASE(7) AR_CONV_CASE(8) AR_CONV_CASE(9)
+    AR_CONV_CASE(10) AR_CONV_CASE(11) AR_CONV_CASE(12) AR_CONV_CASE(13) AR_CONV_CASE(14)
+    AR_CONV_CASE(15)
+    default:
+      hipLaunchKernelGGL((conv_kernel<T, -1>), dim3(blocks), dim3(NT), smem, st, ti, to, tw,
+                         p->n1, p->n2, q1, q2, o1, o2, m1, m2, ze, tg, partial, tiles_x);
+  }
+#undef AR_CONV_CASE
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int conv_blocks(const ar_plan_s *p, int m1, int m2) {
+  (void)p;
+  return ((m1 + TH - 1) / TH) * ((m2 + TW - 1) / TW);
+}
+
+int conv_launch(const ar_plan_s *p, const void *in, void *out, const void *w, int o1, int o2,
+                int m1, int m2, bool zero_ext, const void *g_minus, double *partial,
+                int *nblocks_out, hipStream_t st) {
+  const int tiles_x = (m2 + TW - 1) / TW;
+  const int blocks = conv_blocks(p, m1, m2);
+  const size_t LH = TH + 2 * (size_t)p->q1, LW = TW + 2 * (size_t)p->q2;
+  if (LH * ((LW + 3) & ~(size_t)3) * p->esize > 64 * 1024)
+    return fail(AR_EUNSUPPORTED, "PSF too large for the LDS halo tile");
+  if (nblocks_out) *nblocks_out = blocks;
+  hipError_t e = p->dtype == AR_F64
+                     ? launch_conv_t<double>(p, in, out, w, o1, o2, m1, m2, zero_ext, g_minus,
+                                             partial, blocks, tiles_x, st)
+                     : launch_conv_t<float>(p, in, out, w, o1, o2, m1, m2, zero_ext, g_minus,
+                                            partial, blocks, tiles_x, st);
+  if (e != hipSuccess) return hip_fail(e, "conv_kernel launch");
+  return AR_OK;
+}
+
+int fold_launch(const ar_plan_s *p, const void *ext, void *out, hipStream_t st) {
+  if (p->q1 > 36 || p->q2 > 36) return fail(AR_EUNSUPPORTED, "adjoint fold supports q <= 36");
+  dim3 grid((p->n2 + 63) / 64, (p->n1 + 3) / 4);
+  if (p->dtype == AR_F64)
+    hipLaunchKernelGGL(fold_kernel<double>, grid, dim3(256), 0, st,
+                       static_cast<const double *>(ext), static_cast<double *>(out), p->n1,
+                       p->n2, p->q1, p->q2);
+  else
+    hipLaunchKernelGGL(fold_kernel<float>, grid, dim3(256), 0, st,
+                       static_cast<const float *>(ext), static_cast<float *>(out), p->n1, p->n2,
+                       p->q1, p->q2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "fold_kernel launch");
+  return AR_OK;
+}
+
+}  // namespace ar
+
+using namespace ar;
+
+extern "C" int ar_blur_apply(ar_plan_t p, const void *x, void *y, void *stream) {
+  if (!p || !x || !y) return fail(AR_EINVAL, "ar_blur_apply: null argument");
+  if (x == y) return fail(AR_EALIAS, "ar_blur_apply: x and y must not alias");
+  AR_HIP(hipSetDevice(p->device));
+  return conv_launch(p, x, y, p->w_fwd, 0, 0, p->n1, p->n2, false, nullptr, nullptr, nullptr,
+                     static_cast<hipStream_t>(stream));
+}
+
+extern "C" int ar_blur_apply_T(ar_plan_t p, const void *r, void *y, int tmode, void *stream) {
+  if (!p || !r || !y) return fail(AR_EINVAL, "ar_blur_apply_T: null argument");
+  if (r == y) return fail(AR_EALIAS, "ar_blur_apply_T: r and y must not alias");
+  AR_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (tmode == AR_REBLUR)
+    return conv_launch(p, r, y, p->w_rev, 0, 0, p->n1, p->n2, false, nullptr, nullptr, nullptr,
+                       st);
+  if (tmode == AR_ADJOINT) {
+    int rc = conv_launch(p, r, p->ext, p->w_rev, -p->q1, -p->q2, p->n1 + 2 * p->q1,
+                         p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st);
+    if (rc != AR_OK) return rc;
+    return fold_launch(p, p->ext, y, st);
+  }
+  return fail(AR_EINVAL, "ar_blur_apply_T: unknown tmode");
+}

@@ -1,0 +1,757 @@
+// AR transform kernels (gfx950): T~ = T~_{n1} (x) T~_{n2}, T = its inverse,
+// and the preconditioner D = T diag(d) T~ (Theorem 1; Sec. 4).
+//
+// Per axis of length m the transform is an endpoint scaling plus a DST-I of
+// length N = m - 2 applied to the interior after removing (forward) or
+// adding back (inverse) the linear ramp y_1 p + y_m J p, p_j = 1 - j/(m-1).
+// The DST-I Q_N = sqrt(2/(N+1)) [sin(pi j k /(N+1))] is computed from one
+// complex FFT of length M = N + 1 per row: the odd extension z of length 2M
+// is packed as u_t = z_{2t} + i z_{2t+1}, U = DFT_M(u), and with
+// a + ib = U_k, c + id = U_{M-k}, phi = pi k / M,
+//   sum_j x_j sin(pi j k / M) = ((d - b) + cos(phi)(a - c) + sin(phi)(b + d)) / 4.
+// The FFT is a mixed-radix Stockham transform held in LDS (ping-pong
+// buffers); radices with a compiled codelet use straight-line DFTs with
+// compile-time roots, any other prime factor runs as a generic O(R) stage.
+//
+// Row passes (axis i2, contiguous) keep each row contiguous in LDS.  Column
+// passes (axis i1) interleave C columns so that a wavefront touches
+// consecutive LDS words and consecutive global addresses.  The column pass
+// of D fuses forward transform, filter and inverse transform.
+#include <cmath>
+#include <vector>
+
+#include "ar_internal.h"
+
+namespace ar {
+namespace {
+
+// ----------------------------------------------- compile-time roots of unity
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double sin_taylor(double x) {
+  double x2 = x * x, term = x, s = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / double((2 * k) * (2 * k + 1));
+    s += term;
+  }
+  return s;
+}
+constexpr double cos_taylor(double x) {
+  double x2 = x * x, term = 1.0, s = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / double((2 * k - 1) * (2 * k));
+    s += term;
+  }
+  return s;
+}
+// cos(2 pi num / den) with exact reduction to the first octant.
+constexpr double cos2pi(long num, long den) {
+  num %= den;
+  if (num < 0) num += den;
+  const long q = (4 * num) / den, rem = 4 * num - q * den;
+  double c = 0, s = 0;
+  if (2 * rem <= den) {
+    const double th = (kPi / 2) * double(rem) / double(den);
+    c = cos_taylor(th);
+    s = sin_taylor(th);
+  } else {
+    const double th = (kPi / 2) * double(den - rem) / double(den);
+    c = sin_taylor(th);
+    s = cos_taylor(th);
+  }
+  return q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
+}
+constexpr double sin2pi(long num, long den) { return cos2pi(4 * num - den, 4 * den); }
+
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// ----------------------------------------------------------- DFT codelets
+
+// In-place forward DFT of odd length R: pairs v_j and v_{R-j} so that each
+// output pair (k, R-k) needs (R-1)/2 real-by-complex products for the
+// cosine part and as many for the sine part.
+template <int R, typename T>
+__device__ __forceinline__ void dft_odd(V2<T> (&v)[R]) {
+  constexpr int H = (R - 1) / 2;
+  V2<T> a[H], b[H];
+  static_for<H>([&](auto J) {
+    constexpr int j = J + 1;
+    a[J] = cadd(v[j], v[R - j]);
+    b[J] = csub(v[j], v[R - j]);
+  });
+  const V2<T> v0 = v[0];
+  V2<T> s0 = v0;
+  static_for<H>([&](auto J) { s0 = cadd(s0, a[J]); });
+  v[0] = s0;
+  static_for<H>([&](auto K) {
+    constexpr int k = K + 1;
+    V2<T> C = v0, S{T(0), T(0)};
+    static_for<H>([&](auto J) {
+      constexpr int j = J + 1;
+      constexpr int idx = (j * k) % R;
+      constexpr T cv = T(cos2pi(idx, R));
+      constexpr T sv = T(sin2pi(idx, R));
+      C.x = fma(a[J].x, cv, C.x);
+      C.y = fma(a[J].y, cv, C.y);
+      if constexpr (J == 0) {
+        S.x = b[J].x * sv;
+        S.y = b[J].y * sv;
+      } else {
+        S.x = fma(b[J].x, sv, S.x);
+        S.y = fma(b[J].y, sv, S.y);
+      }
+    });
+    // out_k = C - i S, out_{R-k} = C + i S
+    v[k] = {C.x + S.y, C.y - S.x};
+    v[R - k] = {C.x - S.y, C.y + S.x};
+  });
+}
+
+template <int R, typename T>
+__device__ __forceinline__ void dft(V2<T> (&v)[R]) {
+  if constexpr (R == 2) {
+    const V2<T> t = v[0];
+    v[0] = cadd(t, v[1]);
+    v[1] = csub(t, v[1]);
+  } else if constexpr (R == 4) {
+    const V2<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const V2<T> t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = {t1.x + t3.y, t1.y - t3.x};  // t1 - i t3
+    v[3] = {t1.x - t3.y, t1.y + t3.x};  // t1 + i t3
+  } else {
+    static_assert(R % 2 == 1, "odd radix expected");
+    dft_odd<R, T>(v);
+  }
+}
+
+// ------------------------------------------------------------ FFT stages
+
+// Element t of sequence s lives at buf[s * ss + t * es].
+struct Layout {
+  int nseq, ss, es;
+  bool seq_fast;  // thread index -> (s fastest) or (t fastest)
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void stage_fixed(const V2<T> *__restrict__ src, V2<T> *__restrict__ dst,
+                                            int M, int Ns, const V2<T> *__restrict__ tw,
+                                            const Layout L) {
+  const int nb = M / R;
+  const int total = nb * L.nseq;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int s, j;
+    if (L.seq_fast) {
+      j = idx / L.nseq;
+      s = idx - j * L.nseq;
+    } else {
+      s = idx / nb;
+      j = idx - s * nb;
+    }
+    const V2<T> *a = src + s * L.ss;
+    V2<T> *b = dst + s * L.ss;
+    const int k = j % Ns;
+    V2<T> v[R];
+    static_for<R>([&](auto r) { v[r] = a[(j + r * nb) * L.es]; });
+    if (Ns > 1) {
+      const V2<T> *t = tw + k * R;
+      static_for<R - 1>([&](auto r) { v[r + 1] = cmul(v[r + 1], t[r + 1]); });
+    }
+    dft<R, T>(v);
+    const int base = (j - k) * R + k;
+    static_for<R>([&](auto r) { b[(base + r * Ns) * L.es] = v[r]; });
+  }
+}
+
+// Radix without a codelet: twiddle in place, then each output is an O(R)
+// sum over the butterfly's inputs with the roots e^{-2 pi i t / R}.
+template <typename T>
+__device__ void stage_generic(V2<T> *__restrict__ src, V2<T> *__restrict__ dst, int M, int R,
+                              int Ns, const V2<T> *__restrict__ tw,
+                              const V2<T> *__restrict__ roots, const Layout L) {
+  const int nb = M / R;
+  const int total = M * L.nseq;
+  if (Ns > 1) {
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      int s, t;
+      if (L.seq_fast) {
+        t = idx / L.nseq;
+        s = idx - t * L.nseq;
+      } else {
+        s = idx / M;
+        t = idx - s * M;
+      }
+      const int r = t / nb, j = t - r * nb, k = j % Ns;
+      if (r == 0) continue;
+      V2<T> &e = src[s * L.ss + t * L.es];
+      e = cmul(e, tw[k * R + r]);
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int s, o;
+    if (L.seq_fast) {
+      o = idx / L.nseq;
+      s = idx - o * L.nseq;
+    } else {
+      s = idx / M;
+      o = idx - s * M;
+    }
+    const int ro = o / nb, j = o - ro * nb, k = j % Ns;
+    const V2<T> *a = src + s * L.ss;
+    V2<T> acc{T(0), T(0)};
+    int e = 0;
+    for (int r = 0; r < R; ++r) {
+      const V2<T> x = a[(j + r * nb) * L.es];
+      const V2<T> w = roots[e];
+      acc.x = fma(x.x, w.x, fma(-x.y, w.y, acc.x));
+      acc.y = fma(x.x, w.y, fma(x.y, w.x, acc.y));
+      e += ro;
+      if (e >= R) e -= R;
+    }
+    dst[s * L.ss + ((j - k) * R + k + ro * Ns) * L.es] = acc;
+  }
+}
+
+// Runs all stages; returns the buffer holding the result.
+template <typename T>
+__device__ V2<T> *fft_run(V2<T> *A, V2<T> *B, const FftDesc &fd, const V2<T> *__restrict__ tw,
+                          const V2<T> *__restrict__ gen, const Layout L) {
+  const int M = fd.M;
+  for (int st = 0; st < fd.nstages; ++st) {
+    const int R = fd.radix[st], Ns = fd.ns[st];
+    const V2<T> *t = tw + fd.tw_off[st];
+    switch (R) {
+      case 2: stage_fixed<T, 2>(A, B, M, Ns, t, L); break;
+      case 3: stage_fixed<T, 3>(A, B, M, Ns, t, L); break;
+      case 4: stage_fixed<T, 4>(A, B, M, Ns, t, L); break;
+      case 5: stage_fixed<T, 5>(A, B, M, Ns, t, L); break;
+      case 7: stage_fixed<T, 7>(A, B, M, Ns, t, L); break;
+      case 11: stage_fixed<T, 11>(A, B, M, Ns, t, L); break;
+      case 13: stage_fixed<T, 13>(A, B, M, Ns, t, L); break;
+      case 17: stage_fixed<T, 17>(A, B, M, Ns, t, L); break;
+      case 19: stage_fixed<T, 19>(A, B, M, Ns, t, L); break;
+      case 23: stage_fixed<T, 23>(A, B, M, Ns, t, L); break;
+      case 29: stage_fixed<T, 29>(A, B, M, Ns, t, L); break;
+      case 31: stage_fixed<T, 31>(A, B, M, Ns, t, L); break;
+      default: stage_generic<T>(A, B, M, R, Ns, t, gen + fd.gen_off[st], L); break;
+    }
+    __syncthreads();
+    V2<T> *tmp = A;
+    A = B;
+    B = tmp;
+  }
+  return A;
+}
+
+// u_t = z_{2t} + i z_{2t+1} from the real interior x_1..x_N held in `re`
+// (x_j at re[s*rss + j*res], j = 1..N; the endpoints are ignored).  When
+// `ramp`, x_j is replaced by x_j - e0 p_j - e1 J p_j with e0 = re[.., 0],
+// e1 = re[.., m-1].
+template <typename T>
+__device__ __forceinline__ T odd_ext(const T *row, int res, int tpos, int M) {
+  if (tpos == 0 || tpos == M) return T(0);
+  if (tpos < M) return row[tpos * res];
+  return -row[(2 * M - tpos) * res];
+}
+
+template <typename T>
+__device__ void pack_u(const T *__restrict__ re, int rss, int res, V2<T> *__restrict__ u,
+                       const Layout L, int M, bool ramp, const T *__restrict__ e0,
+                       const T *__restrict__ e1) {
+  const int total = M * L.nseq;
+  const T invM = T(1) / T(M);
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int s, t;
+    if (L.seq_fast) {
+      t = idx / L.nseq;
+      s = idx - t * L.nseq;
+    } else {
+      s = idx / M;
+      t = idx - s * M;
+    }
+    const T *row = re + s * rss;
+    T zr = odd_ext(row, res, 2 * t, M);
+    T zi = odd_ext(row, res, 2 * t + 1, M);
+    if (ramp) {
+      // subtract the ramp from the odd extension: x_j - e0 (M-j)/M - e1 j/M,
+      // applied with the sign of the extension (x_{2M-j} enters negated)
+      const T a0 = e0[s], a1 = e1[s];
+      auto rampv = [&](int tp) -> T {
+        if (tp == 0 || tp == M) return T(0);
+        const int j = tp < M ? tp : 2 * M - tp;
+        const T r = a0 * (T(M - j) * invM) + a1 * (T(j) * invM);
+        return tp < M ? r : -r;
+      };
+      zr -= rampv(2 * t);
+      zi -= rampv(2 * t + 1);
+    }
+    u[s * L.ss + t * L.es] = {zr, zi};
+  }
+}
+
+// DST value k (1..M-1) of a packed sequence whose DFT is U.
+template <typename T>
+__device__ __forceinline__ T dst_value(const V2<T> *__restrict__ U, int es, int k, int M,
+                                       const V2<T> *__restrict__ post, T scale) {
+  const V2<T> A = U[k * es], C = U[(M - k) * es];
+  const V2<T> cs = post[k];
+  return scale * ((C.y - A.y) + cs.x * (A.x - C.x) + cs.y * (A.y + C.y));
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  const int x = b & 7, i = b >> 3;
+  const int g8 = G >> 3, rem = G & 7;
+  return x * g8 + (x < rem ? x : rem) + i;
+}
+
+// ------------------------------------------------------------- row pass
+
+template <typename T>
+__device__ __forceinline__ double block_sum256(double v, double *red) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+  return s;
+}
+
+// MODE: ROW_FWD, ROW_INV, ROW_INV_UPDATE (x += tau * T_{n2}-pass output).
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void rows_kernel(
+    const T *__restrict__ in, T *__restrict__ out, int n1, int m, FftDesc fd,
+    const V2<T> *__restrict__ tw, const V2<T> *__restrict__ gen, const V2<T> *__restrict__ post,
+    T alpha, T scale, int B, int Mp, T tau, const T *__restrict__ f_true,
+    double *__restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V2<T> *bufA = reinterpret_cast<V2<T> *>(smem_raw);
+  V2<T> *bufB = bufA + (size_t)B * Mp;
+  T *e0 = reinterpret_cast<T *>(bufB + (size_t)B * Mp);
+  T *e1 = e0 + B;
+  const int M = fd.M;
+  const int row0 = xcd_remap(blockIdx.x, gridDim.x) * B;
+  const int rs = 2 * Mp;  // real staging stride (in T) inside bufB
+  T *re = reinterpret_cast<T *>(bufB);
+  for (int idx = threadIdx.x; idx < B * m; idx += blockDim.x) {
+    const int s = idx / m, t = idx - s * m;
+    const int r = row0 + s;
+    re[s * rs + t] = r < n1 ? in[(size_t)r * m + t] : T(0);
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < B; s += blockDim.x) {
+    e0[s] = re[s * rs];
+    e1[s] = re[s * rs + m - 1];
+  }
+  __syncthreads();
+  const Layout L{B, Mp, 1, false};
+  pack_u<T>(re, rs, 1, bufA, L, M, MODE == ROW_FWD, e0, e1);
+  __syncthreads();
+  V2<T> *U = fft_run<T>(bufA, bufB, fd, tw, gen, L);
+  const T invM = T(1) / T(M);
+  double ss = 0.0;
+  for (int idx = threadIdx.x; idx < B * m; idx += blockDim.x) {
+    const int s = idx / m, t = idx - s * m;
+    const int r = row0 + s;
+    if (r >= n1) continue;
+    T val;
+    if (MODE == ROW_FWD) {
+      if (t == 0) val = alpha * e0[s];
+      else if (t == m - 1) val = alpha * e1[s];
+      else val = dst_value<T>(U + s * Mp, 1, t, M, post, scale);
+    } else {
+      const T y0 = e0[s] / alpha, y1 = e1[s] / alpha;
+      if (t == 0) val = y0;
+      else if (t == m - 1) val = y1;
+      else
+        val = dst_value<T>(U + s * Mp, 1, t, M, post, scale) + y0 * (T(M - t) * invM) +
+              y1 * (T(t) * invM);
+    }
+    const size_t o = (size_t)r * m + t;
+    if (MODE == ROW_INV_UPDATE) {
+      const T xn = out[o] + tau * val;
+      out[o] = xn;
+      if (f_true) {
+        const double df = (double)xn - (double)f_true[o];
+        ss += df * df;
+      }
+    } else {
+      out[o] = val;
+    }
+  }
+  if (MODE == ROW_INV_UPDATE && partial) {
+    double *red = reinterpret_cast<double *>(smem_raw);  // FFT buffers are dead now
+    const double s = block_sum256<T>(ss, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------- column pass
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void cols_kernel(
+    const T *__restrict__ in, T *__restrict__ out, int m, int n2, FftDesc fd,
+    const V2<T> *__restrict__ tw, const V2<T> *__restrict__ gen, const V2<T> *__restrict__ post,
+    T alpha, T scale, int C, const T *__restrict__ dflt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int M = fd.M;
+  const int Mp = M;  // interleaved layout: sequence stride 1, element stride C
+  V2<T> *bufA = reinterpret_cast<V2<T> *>(smem_raw);
+  V2<T> *bufB = bufA + (size_t)C * Mp;
+  T *e0 = reinterpret_cast<T *>(bufB + (size_t)C * Mp);
+  T *e1 = e0 + C;
+  const int col0 = xcd_remap(blockIdx.x, gridDim.x) * C;
+  // real staging: element t of column s at re[t * C + s] (fits: C*m <= 2*C*M)
+  T *re = reinterpret_cast<T *>(bufB);
+  for (int idx = threadIdx.x; idx < C * m; idx += blockDim.x) {
+    const int t = idx / C, s = idx - t * C;
+    const int c = col0 + s;
+    re[t * C + s] = c < n2 ? in[(size_t)t * n2 + c] : T(0);
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < C; s += blockDim.x) {
+    e0[s] = re[s];
+    e1[s] = re[(m - 1) * C + s];
+  }
+  __syncthreads();
+  const Layout L{C, 1, C, true};
+  const T invM = T(1) / T(M);
+  pack_u<T>(re, 1, C, bufA, L, M, MODE != COL_INV, e0, e1);
+  __syncthreads();
+  V2<T> *U = fft_run<T>(bufA, bufB, fd, tw, gen, L);
+  if (MODE == COL_FWD) {
+    for (int idx = threadIdx.x; idx < C * m; idx += blockDim.x) {
+      const int t = idx / C, s = idx - t * C;
+      const int c = col0 + s;
+      if (c >= n2) continue;
+      T val;
+      if (t == 0) val = alpha * e0[s];
+      else if (t == m - 1) val = alpha * e1[s];
+      else val = dst_value<T>(U + s, C, t, M, post, scale);
+      out[(size_t)t * n2 + c] = val;
+    }
+    return;
+  }
+  if (MODE == COL_FWD_D_INV) {
+    // filtered coefficients into the other buffer as real staging
+    V2<T> *other = (U == bufA) ? bufB : bufA;
+    T *re2 = reinterpret_cast<T *>(other);
+    for (int idx = threadIdx.x; idx < C * m; idx += blockDim.x) {
+      const int t = idx / C, s = idx - t * C;
+      const int c = col0 + s;
+      if (t == 0 || t == m - 1) continue;
+      const T dv = c < n2 ? dflt[(size_t)t * n2 + c] : T(0);
+      re2[t * C + s] = dv * dst_value<T>(U + s, C, t, M, post, scale);
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < C; s += blockDim.x) {
+      const int c = col0 + s;
+      const T d0 = c < n2 ? dflt[c] : T(0);
+      const T d1 = c < n2 ? dflt[(size_t)(m - 1) * n2 + c] : T(0);
+      e0[s] = alpha * e0[s] * d0;  // filtered c_0, c_{m-1}
+      e1[s] = alpha * e1[s] * d1;
+    }
+    __syncthreads();
+    pack_u<T>(re2, 1, C, U, L, M, false, e0, e1);
+    __syncthreads();
+    U = fft_run<T>(U, other, fd, tw, gen, L);
+  }
+  // inverse output: y_0 = c_0 / alpha, y_{m-1} = c_{m-1} / alpha, interior DST + ramp
+  for (int idx = threadIdx.x; idx < C * m; idx += blockDim.x) {
+    const int t = idx / C, s = idx - t * C;
+    const int c = col0 + s;
+    if (c >= n2) continue;
+    const T y0 = e0[s] / alpha, y1 = e1[s] / alpha;
+    T val;
+    if (t == 0) val = y0;
+    else if (t == m - 1) val = y1;
+    else
+      val = dst_value<T>(U + s, C, t, M, post, scale) + y0 * (T(M - t) * invM) +
+            y1 * (T(t) * invM);
+    out[(size_t)t * n2 + c] = val;
+  }
+}
+
+// ------------------------------------------------------- plan-time tables
+
+template <typename T>
+__global__ void tables_kernel(V2<T> *tw, const int *tw_ns, const int *tw_r, const int *tw_base,
+                              int nst, V2<T> *post, int M, V2<T> *gen, const int *gen_r,
+                              const int *gen_base, int ngen) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  for (int s = 0; s < nst; ++s) {
+    const int Ns = tw_ns[s], R = tw_r[s], NR = Ns * R;
+    for (int e = tid; e < NR; e += nth) {
+      const int k = e / R, r = e - k * R;
+      const long kr = ((long)k * r) % NR;
+      double sv, cv;
+      sincospi(-2.0 * (double)kr / (double)NR, &sv, &cv);
+      tw[tw_base[s] + e] = {T(cv), T(sv)};
+    }
+  }
+  for (int k = tid; k <= M; k += nth) {
+    double sv, cv;
+    sincospi((double)k / (double)M, &sv, &cv);
+    post[k] = {T(cv), T(sv)};
+  }
+  for (int g = 0; g < ngen; ++g) {
+    const int R = gen_r[g];
+    for (int t = tid; t < R; t += nth) {
+      double sv, cv;
+      sincospi(-2.0 * (double)t / (double)R, &sv, &cv);
+      gen[gen_base[g] + t] = {T(cv), T(sv)};
+    }
+  }
+}
+
+FftDesc make_desc(const FftPlan &fp) {
+  FftDesc d{};
+  d.M = fp.M;
+  d.nstages = fp.nstages;
+  for (int s = 0; s < kMaxStages; ++s) {
+    d.radix[s] = fp.radix[s];
+    d.ns[s] = fp.ns[s];
+    d.tw_off[s] = fp.tw_off[s];
+    d.gen_off[s] = fp.gen_off[s];
+  }
+  return d;
+}
+
+// rows per workgroup / columns per workgroup
+int rows_per_block(int M, size_t esize) {
+  const size_t cplx = 2 * esize;
+  int B = 2048 / (M > 0 ? M : 1);
+  if (B < 1) B = 1;
+  if (B > 64) B = 64;
+  while (B > 1 && 2 * (size_t)B * M * cplx > 63 * 1024) --B;
+  return B;
+}
+int cols_per_block(int M, size_t esize) {
+  const size_t cplx = 2 * esize;
+  int C = 4096 / (M > 0 ? M : 1);
+  if (C < 1) C = 1;
+  if (C > 64) C = 64;
+  while (C > 1 && 2 * (size_t)C * M * cplx > 63 * 1024) --C;
+  return C;
+}
+
+}  // namespace
+
+bool radix_has_codelet(int r) {
+  switch (r) {
+    case 2: case 3: case 4: case 5: case 7: case 11: case 13: case 17: case 19: case 23:
+    case 29: case 31:
+      return true;
+    default:
+      return false;
+  }
+}
+
+int fft_plan_build(FftPlan &fp, int m, int dtype, hipStream_t st) {
+  fp.m = m;
+  fp.M = m - 1;
+  int M = fp.M;
+  std::vector<int> rad;
+  // powers of two as radix 4 (and one 2), odd primes ascending; primes
+  // without a codelet become generic stages
+  while (M % 4 == 0) { rad.push_back(4); M /= 4; }
+  while (M % 2 == 0) { rad.push_back(2); M /= 2; }
+  for (int p = 3; (long)p * p <= M; p += 2)
+    while (M % p == 0) { rad.push_back(p); M /= p; }
+  if (M > 1) rad.push_back(M);
+  if ((int)rad.size() > kMaxStages) return fail(AR_EUNSUPPORTED, "too many FFT stages");
+  fp.nstages = (int)rad.size();
+  std::vector<int> tw_ns, tw_r, tw_base, gen_r, gen_base;
+  size_t twc = 0, genc = 0;
+  int ns = 1;
+  for (int s = 0; s < fp.nstages; ++s) {
+    fp.radix[s] = rad[s];
+    fp.ns[s] = ns;
+    fp.tw_off[s] = (int)twc;
+    tw_ns.push_back(ns);
+    tw_r.push_back(rad[s]);
+    tw_base.push_back((int)twc);
+    twc += (size_t)ns * rad[s];
+    if (!radix_has_codelet(rad[s])) {
+      fp.gen_off[s] = (int)genc;
+      gen_r.push_back(rad[s]);
+      gen_base.push_back((int)genc);
+      genc += rad[s];
+    }
+    ns *= rad[s];
+  }
+  fp.tw_count = twc;
+  fp.gen_count = genc;
+  const size_t cb = dtype == AR_F64 ? sizeof(double2) : sizeof(float2);
+  AR_HIP(hipMalloc(&fp.tw, (twc > 0 ? twc : 1) * cb));
+  AR_HIP(hipMalloc(&fp.post, (size_t)(fp.M + 1) * cb));
+  AR_HIP(hipMalloc(&fp.gen, (genc > 0 ? genc : 1) * cb));
+  // small integer tables for the table kernel
+  const int nst = fp.nstages, ngen = (int)gen_r.size();
+  std::vector<int> ints;
+  ints.insert(ints.end(), tw_ns.begin(), tw_ns.end());
+  ints.insert(ints.end(), tw_r.begin(), tw_r.end());
+  ints.insert(ints.end(), tw_base.begin(), tw_base.end());
+  ints.insert(ints.end(), gen_r.begin(), gen_r.end());
+  ints.insert(ints.end(), gen_base.begin(), gen_base.end());
+  int *dints = nullptr;
+  AR_HIP(hipMalloc(&dints, (ints.size() + 1) * sizeof(int)));
+  AR_HIP(hipMemcpyAsync(dints, ints.data(), ints.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  const int *p_ns = dints, *p_r = dints + nst, *p_b = dints + 2 * nst;
+  const int *p_gr = dints + 3 * nst, *p_gb = dints + 3 * nst + ngen;
+  if (dtype == AR_F64)
+    hipLaunchKernelGGL(tables_kernel<double>, dim3(64), dim3(256), 0, st,
+                       static_cast<V2<double> *>(fp.tw), p_ns, p_r, p_b, nst,
+                       static_cast<V2<double> *>(fp.post), fp.M,
+                       static_cast<V2<double> *>(fp.gen), p_gr, p_gb, ngen);
+  else
+    hipLaunchKernelGGL(tables_kernel<float>, dim3(64), dim3(256), 0, st,
+                       static_cast<V2<float> *>(fp.tw), p_ns, p_r, p_b, nst,
+                       static_cast<V2<float> *>(fp.post), fp.M, static_cast<V2<float> *>(fp.gen),
+                       p_gr, p_gb, ngen);
+  AR_HIP(hipGetLastError());
+  AR_HIP(hipStreamSynchronize(st));
+  AR_HIP(hipFree(dints));
+  return AR_OK;
+}
+
+void fft_plan_free(FftPlan &fp) {
+  if (fp.tw) (void)hipFree(fp.tw);
+  if (fp.post) (void)hipFree(fp.post);
+  if (fp.gen) (void)hipFree(fp.gen);
+  fp.tw = fp.post = fp.gen = nullptr;
+}
+
+int rows_blocks(const ar_plan_s *p) {
+  const int B = rows_per_block(p->fft_row.M, p->esize);
+  return (p->n1 + B - 1) / B;
+}
+
+template <typename T>
+static int rows_launch_t(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
+                         const void *f_true, double *partial, hipStream_t st) {
+  const FftPlan &fp = p->fft_row;
+  const int m = p->n2, M = fp.M;
+  const int B = rows_per_block(M, sizeof(T));
+  const int blocks = (p->n1 + B - 1) / B;
+  const size_t smem = 2 * (size_t)B * M * sizeof(V2<T>) + 2 * (size_t)B * sizeof(T) + 64;
+  const FftDesc fd = make_desc(fp);
+  const T alpha = T(std::sqrt((double)m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))));
+  const T scale = T(std::sqrt(2.0 / M) / 4.0);
+  auto tw = static_cast<const V2<T> *>(fp.tw);
+  auto gen = static_cast<const V2<T> *>(fp.gen);
+  auto post = static_cast<const V2<T> *>(fp.post);
+  auto ti = static_cast<const T *>(in);
+  auto to = static_cast<T *>(out);
+  auto tf = static_cast<const T *>(f_true);
+  switch (mode) {
+    case ROW_FWD:
+      hipLaunchKernelGGL((rows_kernel<T, ROW_FWD>), dim3(blocks), dim3(256), smem, st, ti, to,
+                         p->n1, m, fd, tw, gen, post, alpha, scale, B, M, T(tau), tf, partial);
+      break;
+    case ROW_INV:
+      hipLaunchKernelGGL((rows_kernel<T, ROW_INV>), dim3(blocks), dim3(256), smem, st, ti, to,
+                         p->n1, m, fd, tw, gen, post, alpha, scale, B, M, T(tau), tf, partial);
+      break;
+    default:
+      hipLaunchKernelGGL((rows_kernel<T, ROW_INV_UPDATE>), dim3(blocks), dim3(256), smem, st,
+                         ti, to, p->n1, m, fd, tw, gen, post, alpha, scale, B, M, T(tau), tf,
+                         partial);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "rows_kernel launch");
+  return AR_OK;
+}
+
+int rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
+                const void *f_true, double *partial, int *nblocks_out, hipStream_t st) {
+  if (nblocks_out) *nblocks_out = rows_blocks(p);
+  return p->dtype == AR_F64 ? rows_launch_t<double>(p, in, out, mode, tau, f_true, partial, st)
+                            : rows_launch_t<float>(p, in, out, mode, tau, f_true, partial, st);
+}
+
+template <typename T>
+static int cols_launch_t(const ar_plan_s *p, const void *in, void *out, int mode,
+                         hipStream_t st) {
+  const FftPlan &fp = p->fft_col;
+  const int m = p->n1, M = fp.M;
+  const int C = cols_per_block(M, sizeof(T));
+  const int blocks = (p->n2 + C - 1) / C;
+  const size_t smem = 2 * (size_t)C * M * sizeof(V2<T>) + 2 * (size_t)C * sizeof(T) + 64;
+  const FftDesc fd = make_desc(fp);
+  const T alpha = T(std::sqrt((double)m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))));
+  const T scale = T(std::sqrt(2.0 / M) / 4.0);
+  auto tw = static_cast<const V2<T> *>(fp.tw);
+  auto gen = static_cast<const V2<T> *>(fp.gen);
+  auto post = static_cast<const V2<T> *>(fp.post);
+  auto ti = static_cast<const T *>(in);
+  auto to = static_cast<T *>(out);
+  auto td = static_cast<const T *>(p->d);
+  switch (mode) {
+    case COL_FWD:
+      hipLaunchKernelGGL((cols_kernel<T, COL_FWD>), dim3(blocks), dim3(256), smem, st, ti, to, m,
+                         p->n2, fd, tw, gen, post, alpha, scale, C, td);
+      break;
+    case COL_INV:
+      hipLaunchKernelGGL((cols_kernel<T, COL_INV>), dim3(blocks), dim3(256), smem, st, ti, to, m,
+                         p->n2, fd, tw, gen, post, alpha, scale, C, td);
+      break;
+    default:
+      hipLaunchKernelGGL((cols_kernel<T, COL_FWD_D_INV>), dim3(blocks), dim3(256), smem, st, ti,
+                         to, m, p->n2, fd, tw, gen, post, alpha, scale, C, td);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "cols_kernel launch");
+  return AR_OK;
+}
+
+int cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
+  return p->dtype == AR_F64 ? cols_launch_t<double>(p, in, out, mode, st)
+                            : cols_launch_t<float>(p, in, out, mode, st);
+}
+
+}  // namespace ar
+
+using namespace ar;
+
+extern "C" int ar_transform(ar_plan_t p, const void *x, void *c, void *stream) {
+  if (!p || !x || !c) return fail(AR_EINVAL, "ar_transform: null argument");
+  AR_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = rows_launch(p, x, c, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
+  if (rc != AR_OK) return rc;
+  return cols_launch(p, c, c, COL_FWD, st);
+}
+
+extern "C" int ar_transform_inv(ar_plan_t p, const void *c, void *x, void *stream) {
+  if (!p || !x || !c) return fail(AR_EINVAL, "ar_transform_inv: null argument");
+  AR_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = cols_launch(p, c, x, COL_INV, st);
+  if (rc != AR_OK) return rc;
+  return rows_launch(p, x, x, ROW_INV, 0.0, nullptr, nullptr, nullptr, st);
+}
+
+extern "C" int ar_precond_solve(ar_plan_t p, const void *y, void *z, void *stream) {
+  if (!p || !y || !z) return fail(AR_EINVAL, "ar_precond_solve: null argument");
+  AR_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = rows_launch(p, y, z, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
+  if (rc != AR_OK) return rc;
+  rc = cols_launch(p, z, z, COL_FWD_D_INV, st);
+  if (rc != AR_OK) return rc;
+  return rows_launch(p, z, z, ROW_INV, 0.0, nullptr, nullptr, nullptr, st);
+}

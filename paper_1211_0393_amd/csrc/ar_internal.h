@@ -1,0 +1,136 @@
+// Internal declarations of the AR deblurring library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <type_traits>
+#include <utility>
+
+#include "ardeblur.h"
+
+namespace ar {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string &msg);
+int fail(int status, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define AR_HIP(call)                                              \
+  do {                                                            \
+    hipError_t e_ = (call);                                       \
+    if (e_ != hipSuccess) return ::ar::hip_fail(e_, #call);       \
+  } while (0)
+
+// ---------------------------------------------------------------- complex
+
+template <typename T> struct V2 { T x, y; };
+template <typename T> struct V2Native;
+template <> struct V2Native<float> { using type = float2; };
+template <> struct V2Native<double> { using type = double2; };
+
+template <typename T>
+__device__ __forceinline__ V2<T> cmul(V2<T> a, V2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ V2<T> cadd(V2<T> a, V2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ V2<T> csub(V2<T> a, V2<T> b) { return {a.x - b.x, a.y - b.y}; }
+
+// ---------------------------------------------------------------- FFT plan
+
+constexpr int kMaxStages = 24;
+
+// Complex FFT of length M = m - 1 used for the DST-I of length m - 2 along
+// one image axis of length m.  Stage s has radix radix[s]; ns[s] is the
+// product of the radices before it (Stockham stride).  Twiddles are stored
+// per stage as e^{-2 pi i k r / (ns R)} at tw + tw_off[s] + k * R + r.
+// A radix that has no compiled codelet is run as a generic stage whose
+// roots e^{-2 pi i t / R} sit at gen + gen_off[s].
+struct FftPlan {
+  int m = 0, M = 0, nstages = 0;
+  int radix[kMaxStages] = {};
+  int ns[kMaxStages] = {};
+  int tw_off[kMaxStages] = {};
+  int gen_off[kMaxStages] = {};
+  void *tw = nullptr;    // V2<T>[]
+  void *gen = nullptr;   // V2<T>[]
+  void *post = nullptr;  // V2<T>[M+1]: (cos, sin)(pi k / M)
+  size_t tw_count = 0, gen_count = 0;
+};
+
+// Device-side view passed to kernels by value.
+struct FftDesc {
+  int M, nstages;
+  int radix[kMaxStages];
+  int ns[kMaxStages];
+  int tw_off[kMaxStages];
+  int gen_off[kMaxStages];
+};
+
+bool radix_has_codelet(int r);
+
+}  // namespace ar
+
+// ---------------------------------------------------------------- the plan
+
+struct ar_plan_s {
+  int n1 = 0, n2 = 0, q1 = 0, q2 = 0, dtype = AR_F32, device = 0;
+  size_t esize = 4;          // bytes per image element
+  // device PSF data
+  double *H64 = nullptr;     // (2q1+1)(2q2+1) FP64 PSF as given
+  double *S64 = nullptr;     // symmetrized PSF, FP64
+  void *w_fwd = nullptr;     // correlation weights of A: rot180(H), dtype
+  void *w_rev = nullptr;     // correlation weights of A' and of A^T's correlation: H, dtype
+  double *lambda = nullptr;  // n1*n2 FP64 eigenvalues
+  double *d64 = nullptr;     // n1*n2 FP64 filter
+  void *d = nullptr;         // n1*n2 filter in dtype
+  ar::FftPlan fft_row;       // axis i2, length n2
+  ar::FftPlan fft_col;       // axis i1, length n1
+  // scratch owned by the plan
+  void *r = nullptr, *y = nullptr, *c = nullptr;  // n1*n2 dtype each
+  void *ext = nullptr;       // (n1+2q1)(n2+2q2) dtype, adjoint correlation
+  double *partials = nullptr;  // per-iteration partial sums
+  size_t partials_cap = 0;     // doubles
+  double *scalars = nullptr;   // reduced per-iteration scalars
+  size_t scalars_cap = 0;
+  int filter = AR_FILTER_TIKHONOV;
+  double filter_param = 1e-2;
+};
+
+namespace ar {
+
+// ---------------------------------------------------------------- launchers
+
+// blur kernels (ar_blur.hip)
+int conv_launch(const ar_plan_s *p, const void *in, void *out, const void *w, int o1, int o2,
+                int m1, int m2, bool zero_ext, const void *g_minus, double *partial,
+                int *nblocks_out, hipStream_t st);
+int conv_blocks(const ar_plan_s *p, int m1, int m2);
+int fold_launch(const ar_plan_s *p, const void *ext, void *out, hipStream_t st);
+
+// transform kernels (ar_fft.hip)
+enum RowMode { ROW_FWD = 0, ROW_INV = 1, ROW_INV_UPDATE = 2 };
+enum ColMode { COL_FWD = 0, COL_INV = 1, COL_FWD_D_INV = 2 };
+int fft_plan_build(ar::FftPlan &fp, int m, int dtype, hipStream_t st);
+void fft_plan_free(ar::FftPlan &fp);
+int rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
+                const void *f_true, double *partial, int *nblocks_out, hipStream_t st);
+int rows_blocks(const ar_plan_s *p);
+int cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st);
+
+// plan-time and helper kernels (ar_plan.hip)
+int spectrum_launch(ar_plan_s *p, hipStream_t st);
+int filter_launch(ar_plan_s *p, int filter, double param, hipStream_t st);
+int axpy_launch(const ar_plan_s *p, void *x, const void *yv, double tau, const void *f_true,
+                double *partial, int *nblocks_out, hipStream_t st);
+int axpy_blocks(const ar_plan_s *p);
+int reduce_rows_launch(const double *partials, int rows, int cols, double *out, hipStream_t st);
+int sumsq_launch(const ar_plan_s *p, const void *x, double *partial, int *nblocks_out,
+                 hipStream_t st);
+
+}  // namespace ar

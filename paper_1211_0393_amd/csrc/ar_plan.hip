@@ -1,0 +1,385 @@
+// Plan creation (S0-S2 of the path), FP64 spectrum and filter kernels,
+// deterministic reductions and small helper kernels (gfx950).
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ar_internal.h"
+
+namespace ar {
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int status, const std::string &msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  (void)hipGetLastError();  // clear the sticky non-fatal error state
+  return e == hipErrorOutOfMemory ? AR_ENOMEM : AR_EDEVICE;
+}
+
+namespace {
+
+// ------------------------------------------------ PSF preparation (device)
+
+// Symmetrized PSF s = (h + flip_1 h + flip_2 h + flip_1 flip_2 h) / 4
+// (Theorem 4, eq. (simmetrizzata2d-bis)) and the correlation weights of the
+// blur kernels: A uses rot180(H) (convolution written as a correlation),
+// A' uses H itself (the PSF rotated by 180 degrees, convolved).
+template <typename T>
+__global__ void psf_prep_kernel(const double *__restrict__ H, double *__restrict__ S,
+                                T *__restrict__ w_fwd, T *__restrict__ w_rev, int q1, int q2) {
+  const int K1 = 2 * q1 + 1, K2 = 2 * q2 + 1;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K1 * K2; e += gridDim.x * blockDim.x) {
+    const int a = e / K2, b = e - a * K2;  // a = q1 + s1, b = q2 + s2
+    const int fa = K1 - 1 - a, fb = K2 - 1 - b;
+    S[e] = (H[fa * K2 + fb] + H[fa * K2 + b] + H[a * K2 + fb] + H[a * K2 + b]) * 0.25;
+    w_fwd[e] = T(H[fa * K2 + fb]);
+    w_rev[e] = T(H[e]);
+  }
+}
+
+// cos(a x_k) for the AR grid of an axis of length n: x_0 = x_{n-1} = 0 and
+// x_k = k pi/(n-1) otherwise (Theorem 2 and the extended grid after it).
+__device__ __forceinline__ double grid_cos(int a, int k, int n) {
+  if (k == 0 || k == n - 1 || a == 0) return 1.0;
+  const long period = 2L * (n - 1);
+  const long num = ((long)a * k) % period;  // cos(pi num / (n-1))
+  return cospi((double)num / (double)(n - 1));
+}
+
+// Cq[a][k2] = w_b-weighted sum over b >= 0 of s[a][b] cos(b x_{k2}),
+// w_0 = 1, w_b = 2: the inner sum of eq. (funzione_generatrice).
+__global__ void symbol_inner_kernel(const double *__restrict__ S, double *__restrict__ Cq,
+                                    int q1, int q2, int n2) {
+  const int K2 = 2 * q2 + 1;
+  const int total = (q1 + 1) * n2;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int a = e / n2, k2 = e - a * n2;
+    const double *row = S + (size_t)(q1 + a) * K2 + q2;
+    double acc = row[0];
+    for (int b = 1; b <= q2; ++b) acc = fma(2.0 * row[b], grid_cos(b, k2, n2), acc);
+    Cq[e] = acc;
+  }
+}
+
+// lambda[k1][k2] = sum_a w_a cos(a x_{k1}) Cq[a][k2]  (FP64)
+__global__ void symbol_outer_kernel(const double *__restrict__ Cq, double *__restrict__ lam,
+                                    int q1, int n1, int n2) {
+  const size_t total = (size_t)n1 * n2;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int k1 = (int)(e / n2), k2 = (int)(e - (size_t)k1 * n2);
+    double acc = Cq[k2];
+    for (int a = 1; a <= q1; ++a) acc = fma(2.0 * grid_cos(a, k1, n1), Cq[(size_t)a * n2 + k2], acc);
+    lam[e] = acc;
+  }
+}
+
+// Eigenvalue filter (Sec. 4, eq. (TikFilter)); FP64 arithmetic, stored in
+// FP64 and in the image dtype.
+template <typename T>
+__global__ void filter_kernel(const double *__restrict__ lam, double *__restrict__ d64,
+                              T *__restrict__ d, size_t total, int kind, double param) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double l = lam[e];
+    double v;
+    if (kind == AR_FILTER_TIKHONOV) v = 1.0 / (l * l + param);
+    else if (kind == AR_FILTER_THRESHOLD) v = fabs(l) >= param ? 1.0 / (l * l) : 1.0;
+    else v = 1.0;
+    d64[e] = v;
+    d[e] = T(v);
+  }
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+  return s;
+}
+
+constexpr int kElemBlocks = 1024;
+
+// x += tau * y, with optional FP64 partial sums of (x - f)^2 (plain Landweber update)
+template <typename T>
+__global__ __launch_bounds__(256) void axpy_kernel(T *__restrict__ x, const T *__restrict__ y,
+                                                   T tau, size_t total,
+                                                   const T *__restrict__ f,
+                                                   double *__restrict__ partial) {
+  __shared__ double red[4];
+  double ss = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const T xn = x[e] + tau * y[e];
+    x[e] = xn;
+    if (f) {
+      const double df = (double)xn - (double)f[e];
+      ss += df * df;
+    }
+  }
+  if (partial) {
+    const double s = block_sum(ss, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_kernel(const T *__restrict__ x, size_t total,
+                                                    double *__restrict__ partial) {
+  __shared__ double red[4];
+  double ss = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double v = (double)x[e];
+    ss += v * v;
+  }
+  const double s = block_sum(ss, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out[r] = sum_c partials[r * cols + c], fixed order (bitwise reproducible)
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const double *__restrict__ partials,
+                                                          int cols, double *__restrict__ out) {
+  __shared__ double red[4];
+  const double *row = partials + (size_t)blockIdx.x * cols;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < cols; c += blockDim.x) s += row[c];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+int elem_blocks(size_t total) {
+  size_t b = (total + 255) / 256;
+  if (b > kElemBlocks) b = kElemBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+int spectrum_launch(ar_plan_s *p, hipStream_t st) {
+  if (p->dtype == AR_F64)
+    hipLaunchKernelGGL(psf_prep_kernel<double>, dim3(4), dim3(256), 0, st, p->H64, p->S64,
+                       static_cast<double *>(p->w_fwd), static_cast<double *>(p->w_rev), p->q1,
+                       p->q2);
+  else
+    hipLaunchKernelGGL(psf_prep_kernel<float>, dim3(4), dim3(256), 0, st, p->H64, p->S64,
+                       static_cast<float *>(p->w_fwd), static_cast<float *>(p->w_rev), p->q1,
+                       p->q2);
+  AR_HIP(hipGetLastError());
+  double *Cq = nullptr;
+  AR_HIP(hipMalloc((void **)&Cq, (size_t)(p->q1 + 1) * p->n2 * sizeof(double)));
+  hipLaunchKernelGGL(symbol_inner_kernel, dim3(64), dim3(256), 0, st, p->S64, Cq, p->q1, p->q2,
+                     p->n2);
+  AR_HIP(hipGetLastError());
+  hipLaunchKernelGGL(symbol_outer_kernel, dim3(1024), dim3(256), 0, st, Cq, p->lambda, p->q1,
+                     p->n1, p->n2);
+  AR_HIP(hipGetLastError());
+  AR_HIP(hipStreamSynchronize(st));
+  AR_HIP(hipFree(Cq));
+  return AR_OK;
+}
+
+int filter_launch(ar_plan_s *p, int filter, double param, hipStream_t st) {
+  const size_t total = (size_t)p->n1 * p->n2;
+  if (p->dtype == AR_F64)
+    hipLaunchKernelGGL(filter_kernel<double>, dim3(elem_blocks(total)), dim3(256), 0, st,
+                       p->lambda, p->d64, static_cast<double *>(p->d), total, filter, param);
+  else
+    hipLaunchKernelGGL(filter_kernel<float>, dim3(elem_blocks(total)), dim3(256), 0, st,
+                       p->lambda, p->d64, static_cast<float *>(p->d), total, filter, param);
+  AR_HIP(hipGetLastError());
+  p->filter = filter;
+  p->filter_param = param;
+  return AR_OK;
+}
+
+int axpy_blocks(const ar_plan_s *p) { return elem_blocks((size_t)p->n1 * p->n2); }
+
+int axpy_launch(const ar_plan_s *p, void *x, const void *yv, double tau, const void *f_true,
+                double *partial, int *nblocks_out, hipStream_t st) {
+  const size_t total = (size_t)p->n1 * p->n2;
+  const int blocks = elem_blocks(total);
+  if (nblocks_out) *nblocks_out = blocks;
+  if (p->dtype == AR_F64)
+    hipLaunchKernelGGL(axpy_kernel<double>, dim3(blocks), dim3(256), 0, st,
+                       static_cast<double *>(x), static_cast<const double *>(yv), tau, total,
+                       static_cast<const double *>(f_true), partial);
+  else
+    hipLaunchKernelGGL(axpy_kernel<float>, dim3(blocks), dim3(256), 0, st,
+                       static_cast<float *>(x), static_cast<const float *>(yv), (float)tau,
+                       total, static_cast<const float *>(f_true), partial);
+  AR_HIP(hipGetLastError());
+  return AR_OK;
+}
+
+int sumsq_launch(const ar_plan_s *p, const void *x, double *partial, int *nblocks_out,
+                 hipStream_t st) {
+  const size_t total = (size_t)p->n1 * p->n2;
+  const int blocks = elem_blocks(total);
+  if (nblocks_out) *nblocks_out = blocks;
+  if (p->dtype == AR_F64)
+    hipLaunchKernelGGL(sumsq_kernel<double>, dim3(blocks), dim3(256), 0, st,
+                       static_cast<const double *>(x), total, partial);
+  else
+    hipLaunchKernelGGL(sumsq_kernel<float>, dim3(blocks), dim3(256), 0, st,
+                       static_cast<const float *>(x), total, partial);
+  AR_HIP(hipGetLastError());
+  return AR_OK;
+}
+
+int reduce_rows_launch(const double *partials, int rows, int cols, double *out, hipStream_t st) {
+  if (rows <= 0) return AR_OK;
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(rows), dim3(256), 0, st, partials, cols, out);
+  AR_HIP(hipGetLastError());
+  return AR_OK;
+}
+
+}  // namespace ar
+
+using namespace ar;
+
+// Largest axis length the LDS-resident transform supports: two complex
+// buffers of n - 1 points per workgroup within 63 KiB of LDS.
+static int max_axis(int dtype) { return dtype == AR_F64 ? 2017 : 4033; }
+
+static void plan_free(ar_plan_s *p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  void *bufs[] = {p->H64, p->S64, p->w_fwd, p->w_rev, p->lambda, p->d64, p->d,
+                  p->r,   p->y,   p->c,     p->ext,   p->partials, p->scalars};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  fft_plan_free(p->fft_row);
+  fft_plan_free(p->fft_col);
+  delete p;
+}
+
+extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_host, int q1,
+                              int q2, int dtype, int device) {
+  if (!out) return fail(AR_EINVAL, "ar_plan_create: out is NULL");
+  *out = nullptr;
+  if (!psf_host) return fail(AR_EINVAL, "ar_plan_create: psf is NULL");
+  if (dtype != AR_F32 && dtype != AR_F64) return fail(AR_EINVAL, "ar_plan_create: bad dtype");
+  if (q1 < 0 || q2 < 0) return fail(AR_ESHAPE, "ar_plan_create: negative PSF half-width");
+  if (n1 < 3 || n2 < 3) return fail(AR_ESHAPE, "ar_plan_create: need n1, n2 >= 3");
+  if (q1 > n1 - 3 || q2 > n2 - 3)
+    return fail(AR_ESHAPE, "ar_plan_create: AR algebra needs q_j <= n_j - 3");
+  if (n1 > max_axis(dtype) || n2 > max_axis(dtype))
+    return fail(AR_ESHAPE, "ar_plan_create: axis longer than the LDS-resident transform supports");
+  const int K1 = 2 * q1 + 1, K2 = 2 * q2 + 1, P = K1 * K2;
+  double sum = 0.0;
+  for (int e = 0; e < P; ++e) {
+    const double v = psf_host[e];
+    if (!std::isfinite(v) || v < 0.0)
+      return fail(AR_EPSF, "ar_plan_create: PSF entries must be finite and nonnegative");
+    sum += v;
+  }
+  if (std::fabs(sum - 1.0) > 1e-12 * P) return fail(AR_EPSF, "ar_plan_create: PSF must sum to 1");
+  int ndev = 0;
+  AR_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(AR_EINVAL, "ar_plan_create: bad device");
+  AR_HIP(hipSetDevice(device));
+
+  ar_plan_s *p = new ar_plan_s();
+  p->n1 = n1;
+  p->n2 = n2;
+  p->q1 = q1;
+  p->q2 = q2;
+  p->dtype = dtype;
+  p->device = device;
+  p->esize = dtype == AR_F64 ? 8 : 4;
+  const size_t npx = (size_t)n1 * n2;
+  const size_t next = (size_t)(n1 + 2 * q1) * (n2 + 2 * q2);
+  int rc = AR_OK;
+  auto alloc = [&](void **ptr, size_t bytes) -> bool {
+    hipError_t e = hipMalloc(ptr, bytes > 0 ? bytes : 8);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "hipMalloc");
+      return false;
+    }
+    return true;
+  };
+  bool ok = alloc((void **)&p->H64, P * sizeof(double)) && alloc((void **)&p->S64, P * sizeof(double)) &&
+            alloc(&p->w_fwd, P * p->esize) && alloc(&p->w_rev, P * p->esize) &&
+            alloc((void **)&p->lambda, npx * sizeof(double)) &&
+            alloc((void **)&p->d64, npx * sizeof(double)) && alloc(&p->d, npx * p->esize) &&
+            alloc(&p->r, npx * p->esize) && alloc(&p->y, npx * p->esize) &&
+            alloc(&p->c, npx * p->esize) && alloc(&p->ext, next * p->esize);
+  if (!ok) {
+    plan_free(p);
+    return rc;
+  }
+  hipStream_t st = nullptr;
+  hipError_t e = hipMemcpy(p->H64, psf_host, P * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    rc = hip_fail(e, "hipMemcpy(psf)");
+    plan_free(p);
+    return rc;
+  }
+  if ((rc = spectrum_launch(p, st)) != AR_OK || (rc = filter_launch(p, AR_FILTER_TIKHONOV, 1e-2, st)) != AR_OK ||
+      (rc = fft_plan_build(p->fft_row, n2, dtype, st)) != AR_OK ||
+      (rc = fft_plan_build(p->fft_col, n1, dtype, st)) != AR_OK) {
+    plan_free(p);
+    return rc;
+  }
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    rc = hip_fail(e, "plan setup");
+    plan_free(p);
+    return rc;
+  }
+  *out = p;
+  return AR_OK;
+}
+
+extern "C" int ar_plan_destroy(ar_plan_t p) {
+  plan_free(p);
+  return AR_OK;
+}
+
+extern "C" int ar_precond_set(ar_plan_t p, int filter, double param, void *stream) {
+  if (!p) return fail(AR_EINVAL, "ar_precond_set: null plan");
+  if (filter != AR_FILTER_TIKHONOV && filter != AR_FILTER_THRESHOLD && filter != AR_FILTER_IDENTITY)
+    return fail(AR_EINVAL, "ar_precond_set: unknown filter");
+  if (filter != AR_FILTER_IDENTITY && !(param > 0.0 && std::isfinite(param)))
+    return fail(AR_EINVAL, "ar_precond_set: filter parameter must be finite and > 0");
+  AR_HIP(hipSetDevice(p->device));
+  return filter_launch(p, filter, param, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int ar_eigenvalues(ar_plan_t p, double *lambda_dev, void *stream) {
+  if (!p || !lambda_dev) return fail(AR_EINVAL, "ar_eigenvalues: null argument");
+  AR_HIP(hipSetDevice(p->device));
+  AR_HIP(hipMemcpyAsync(lambda_dev, p->lambda, (size_t)p->n1 * p->n2 * sizeof(double),
+                        hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  return AR_OK;
+}
+
+extern "C" int ar_filter_values(ar_plan_t p, double *d_dev, void *stream) {
+  if (!p || !d_dev) return fail(AR_EINVAL, "ar_filter_values: null argument");
+  AR_HIP(hipSetDevice(p->device));
+  AR_HIP(hipMemcpyAsync(d_dev, p->d64, (size_t)p->n1 * p->n2 * sizeof(double),
+                        hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  return AR_OK;
+}
+
+extern "C" const char *ar_last_error(void) { return ar::g_last_error.c_str(); }
+
+extern "C" const char *ar_version(void) { return "ardeblur 0.1 gfx950"; }

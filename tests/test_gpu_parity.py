@@ -1,0 +1,348 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Tolerances (Frobenius-relative unless stated):
+  * FP64 plans: 1e-12 for every operator and per iterate;
+  * FP32 blur / reblur / adjoint: 1e-6 (each output is a <= 961-term FP32
+    dot product of O(1) values, rounding ~ sqrt(P) * 6e-8);
+  * FP32 transforms: 5e-6 (FFT rounding ~ log2(M) * 6e-8 times the
+    conditioning of T, which is ~46 per axis at m = 1024 for the inverse);
+  * FP32 preconditioner solve: 2e-5 (the transform error is further scaled
+    by the spread of d, up to 1/alpha);
+  * FP32 iterate: 1e-5 one-step parity (the oracle's step applied to the
+    GPU's own x_k), as the method's statement of FP32 step accuracy.
+Inputs are rounded to the plan dtype first; the oracle gets exactly those
+values in FP64."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_1211_0393_amd as P  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dt):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype=dt)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+TDT = {"f32": torch.float32, "f64": torch.float64}
+NDT = {"f32": np.float32, "f64": np.float64}
+TOL_BLUR = {"f32": 1e-6, "f64": 1e-13}
+TOL_T = {"f32": 5e-6, "f64": 1e-12}
+TOL_D = {"f32": 2e-5, "f64": 1e-12}
+TOL_IT = {"f32": 1e-5, "f64": 1e-12}
+
+
+def image(n1, n2, seed, dt):
+    return synth.phantom(n1, n2, 5, 3, seed=seed).astype(NDT[dt]).astype(np.float64)
+
+
+BLUR_CASES = [
+    (3, 3, 0, 0), (4, 5, 1, 1), (8, 8, 2, 3), (17, 33, 4, 7), (31, 97, 7, 7),
+    (63, 64, 7, 7), (65, 130, 5, 9), (128, 96, 15, 15), (37, 300, 0, 12),
+    (300, 37, 12, 0), (200, 157, 16, 20), (97, 65, 3, 31),
+]
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("n1,n2,q1,q2", BLUR_CASES)
+def test_blur_operators(n1, n2, q1, q2, dt):
+    say(f"blur case n=({n1},{n2}) q=({q1},{q2}) {dt}")
+    H = synth.psf_random(q1, q2, seed=n1 + 31 * n2 + q1)
+    X = image(n1, n2, seed=n1 * n2, dt=dt)
+    with P.Plan(n1, n2, H, dtype=dt) as plan:
+        x = dev(X, TDT[dt])
+        y = torch.empty_like(x)
+        plan.ar_blur_apply(x, y)
+        e = rel(host(y), O.blur(X, H))
+        assert e <= TOL_BLUR[dt], e
+        plan.ar_blur_apply_T(x, y, P.AR_REBLUR)
+        e = rel(host(y), O.reblur(X, H))
+        assert e <= TOL_BLUR[dt], e
+        plan.ar_blur_apply_T(x, y, P.AR_ADJOINT)
+        e = rel(host(y), O.blur_adjoint(X, H))
+        assert e <= 2 * TOL_BLUR[dt], e
+
+
+def test_blur_full_size_1024_motion():
+    F, H, E, p = synth.workload("ar1024_f32_motion15")
+    X = F.astype(np.float32).astype(np.float64)
+    with P.Plan(1024, 1024, H, dtype="f32") as plan:
+        x = dev(X, torch.float32)
+        y = torch.empty_like(x)
+        plan.ar_blur_apply(x, y)
+        Y = host(y)
+        ref = O.blur(X, H)
+        assert rel(Y, ref) <= 1e-6
+        assert np.max(np.abs(Y - ref)) <= 2e-6 * np.max(np.abs(ref))
+        plan.ar_blur_apply_T(x, y, P.AR_REBLUR)
+        assert rel(host(y), O.reblur(X, H)) <= 1e-6
+
+
+def test_blur_alias_rejected():
+    H = synth.psf_random(1, 1, seed=0)
+    with P.Plan(16, 16, H) as plan:
+        x = torch.zeros(16, 16, device=DEV)
+        with pytest.raises(P.ArError) as ei:
+            plan.ar_blur_apply(x, x)
+        assert ei.value.status == -4
+
+
+TRANSFORM_SIZES = [
+    (3, 3), (4, 5), (7, 8), (16, 17), (63, 64), (65, 66), (128, 192), (255, 256),
+    (384, 129), (512, 100), (1023, 33), (1024, 1024), (1025, 40), (2048, 24), (24, 2048),
+]
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("n1,n2", TRANSFORM_SIZES)
+def test_transform_pair(n1, n2, dt):
+    if dt == "f64" and max(n1, n2) > 2017:
+        pytest.skip("FP64 axis limit of the LDS-resident transform")
+    say(f"transform case n=({n1},{n2}) {dt}")
+    H = np.ones((1, 1))
+    rng = np.random.default_rng(n1 * 7 + n2)
+    X = rng.standard_normal((n1, n2)).astype(NDT[dt]).astype(np.float64)
+    with P.Plan(n1, n2, H, dtype=dt) as plan:
+        x = dev(X, TDT[dt])
+        c = torch.empty_like(x)
+        plan.ar_transform(x, c)
+        Cg = host(c)
+        e = rel(Cg, O.ar_fwd(X))
+        say(f"  fwd rel err {e:.2e}")
+        assert e <= TOL_T[dt], e
+        Cq = Cg.astype(NDT[dt]).astype(np.float64)
+        xr = torch.empty_like(x)
+        plan.ar_transform_inv(dev(Cq, TDT[dt]), xr)
+        e = rel(host(xr), O.ar_inv(Cq))
+        say(f"  inv rel err {e:.2e}")
+        assert e <= TOL_T[dt], e
+        # in place
+        y = dev(X, TDT[dt])
+        plan.ar_transform(y, y)
+        assert np.array_equal(host(y), Cg)
+
+
+@pytest.mark.parametrize("n1,n2,q1,q2", [(5, 6, 1, 2), (64, 64, 4, 4), (97, 130, 7, 3), (512, 384, 10, 10)])
+def test_eigenvalues_and_filters(n1, n2, q1, q2):
+    H = synth.psf_random(q1, q2, seed=q1 * 3 + q2)
+    ref = O.eigenvalues(H, n1, n2)
+    with P.Plan(n1, n2, H, dtype="f32") as plan:
+        lam = torch.empty(n1, n2, dtype=torch.float64, device=DEV)
+        plan.ar_eigenvalues(lam)
+        L = host(lam)
+        assert np.max(np.abs(L - ref)) <= 1e-13
+        d = torch.empty_like(lam)
+        for filt, param, fn in [(P.AR_FILTER_TIKHONOV, 5e-3, lambda l: O.tikhonov(l, 5e-3)),
+                                (P.AR_FILTER_THRESHOLD, 0.05, lambda l: O.threshold_filter(l, 0.05)),
+                                (P.AR_FILTER_IDENTITY, 0.0, lambda l: np.ones_like(l))]:
+            plan.ar_precond_set(filt, param)
+            plan.ar_filter_values(d)
+            # the filter is evaluated on the device's own lambda in FP64
+            assert rel(host(d), fn(L)) <= 1e-15
+        with pytest.raises(P.ArError):
+            plan.ar_precond_set(P.AR_FILTER_TIKHONOV, -1.0)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("n1,n2,q1,q2,alpha", [(9, 10, 2, 3, 1e-2), (64, 64, 4, 4, 1e-2),
+                                               (130, 97, 5, 7, 5e-3), (256, 256, 7, 7, 5e-3)])
+def test_precond_solve(n1, n2, q1, q2, alpha, dt):
+    say(f"precond case n=({n1},{n2}) q=({q1},{q2}) {dt}")
+    H = synth.psf_random(q1, q2, seed=n1 + q2)
+    rng = np.random.default_rng(n2)
+    Y = O.reblur(rng.standard_normal((n1, n2)), H).astype(NDT[dt]).astype(np.float64)
+    with P.Plan(n1, n2, H, dtype=dt) as plan:
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, alpha)
+        d64 = torch.empty(n1, n2, dtype=torch.float64, device=DEV)
+        plan.ar_filter_values(d64)
+        dref = O.tikhonov(O.eigenvalues(H, n1, n2), alpha)
+        assert rel(host(d64), dref) <= 1e-13
+        y = dev(Y, TDT[dt])
+        z = torch.empty_like(y)
+        plan.ar_precond_solve(y, z)
+        e = rel(host(z), O.precond_apply(Y, dref))
+        say(f"  rel err {e:.2e}")
+        assert e <= TOL_D[dt], e
+
+
+def _gpu_iterate(plan, G, X0, iters, dt, **kw):
+    g = dev(G, TDT[dt])
+    x = dev(X0, TDT[dt])
+    rc, res, rre, best = plan.ar_deblur_iterate(g, x, iters, **kw)
+    return rc, host(x), res, rre, best
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("tmode", [P.AR_REBLUR, P.AR_ADJOINT])
+@pytest.mark.parametrize("precondition", [True, False])
+@pytest.mark.parametrize("n1,n2,q1,q2", [(33, 40, 3, 4), (100, 120, 7, 7)])
+def test_iterate_one_step(n1, n2, q1, q2, precondition, tmode, dt):
+    say(f"iterate case n=({n1},{n2}) q=({q1},{q2}) pre={precondition} tmode={tmode} {dt}")
+    H = synth.psf_gauss_shifted(q1, q2, 1.5, 1.0, shift=(0.3, -0.2))
+    F = image(n1, n2, seed=5, dt=dt)
+    E = synth.noise_field(n1, n2, seed=6)
+    G = O.observe(F, H, E, 0.005).astype(NDT[dt]).astype(np.float64)
+    alpha = 0.05
+    tm = "reblur" if tmode == P.AR_REBLUR else "adjoint"
+    d = O.tikhonov(O.eigenvalues(H, n1, n2), alpha) if precondition else None
+    with P.Plan(n1, n2, H, dtype=dt) as plan:
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, alpha)
+        X = np.zeros((n1, n2))
+        for k in [0, 1, 2, 7]:
+            rc, Xg, res, rre, best = _gpu_iterate(plan, G, X, 1, dt, tmode=tmode,
+                                                  precondition=precondition,
+                                                  want_resnorm=True)
+            assert rc == 0
+            Xo, rn = O.landweber_step(X, G, H, d=d, tmode=tm)
+            e = rel(Xg, Xo)
+            say(f"  k={k} one-step rel err {e:.2e}")
+            assert e <= TOL_IT[dt], e
+            assert abs(res[0] - rn) <= (1e-5 if dt == "f32" else 1e-12) * rn
+            X = Xg.astype(NDT[dt]).astype(np.float64)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_iterate_trajectory_and_scalars(dt):
+    """K iterations in one call against the oracle's trajectory: FP64 stays
+    within 1e-12 at every iterate; FP32 drift is reported and bounded."""
+    n, K = 64, 12
+    F, H, E, p = synth.workload("ar64_f64_gauss9")
+    F = F.astype(NDT[dt]).astype(np.float64)
+    G = O.observe(F, H, E, p["nu"]).astype(NDT[dt]).astype(np.float64)
+    with P.Plan(n, n, H, dtype=dt) as plan:
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, 0.1)
+        ref = O.iterate(G, H, K, alpha=0.1, F_true=F)
+        g, f = dev(G, TDT[dt]), dev(F, TDT[dt])
+        x = torch.zeros_like(g)
+        rc, res, rre, best = plan.ar_deblur_iterate(g, x, K, f_true=f, want_resnorm=True,
+                                                    want_rre=True)
+        assert rc == 0
+        drift = rel(host(x), ref["x"])
+        say(f"  {dt} drift after {K}: {drift:.2e}")
+        tol = 1e-12 if dt == "f64" else 5e-5
+        assert drift <= tol
+        assert np.max(np.abs(res - ref["resnorm"]) / ref["resnorm"]) <= tol
+        assert np.max(np.abs(rre - ref["rre"]) / ref["rre"]) <= tol
+        assert best == ref["best_it"]
+
+
+def test_iterate_64_f64_fifty_steps():
+    """The 64x64 FP64 workload (9x9 shifted Gaussian, alpha = 1e-2, 50
+    steps) against the oracle at every iterate (1e-12); with this alpha the
+    iteration is unstable, so the comparison is relative per iterate."""
+    F, H, E, p = synth.workload("ar64_f64_gauss9")
+    G = O.observe(F, H, E, p["nu"])
+    with P.Plan(64, 64, H, dtype="f64") as plan:
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, p["alpha"])
+        d = O.tikhonov(O.eigenvalues(H, 64, 64), p["alpha"])
+        X = np.zeros((64, 64))
+        g = dev(G, torch.float64)
+        x = torch.zeros_like(g)
+        worst = 0.0
+        for k in range(p["iters"]):
+            rc, _, _, _ = plan.ar_deblur_iterate(g, x, 1)
+            assert rc == 0
+            Xg = host(x)
+            X, _ = O.landweber_step(X, G, H, d=d)
+            worst = max(worst, rel(Xg, X))
+        say(f"  worst per-iterate drift {worst:.2e}")
+        assert worst <= 1e-12
+
+
+def test_iterate_full_size_1024():
+    """The 1024^2 FP32 workload (15x15 motion PSF, alpha = 5e-3): one-step
+    parity at k = 0, 1, 10 in the launch configuration the benchmark uses."""
+    F, H, E, p = synth.workload("ar1024_f32_motion15")
+    G = O.observe(F, H, E, p["nu"]).astype(np.float32).astype(np.float64)
+    d = O.tikhonov(O.eigenvalues(H, 1024, 1024), p["alpha"])
+    with P.Plan(1024, 1024, H, dtype="f32") as plan:
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, p["alpha"])
+        g = dev(G, torch.float32)
+        x = torch.zeros_like(g)
+        X = np.zeros((1024, 1024))
+        done = 0
+        for k in [0, 1, 10]:
+            if k > done:
+                plan.ar_deblur_iterate(g, x, k - done)
+                done = k
+            X = host(x)
+            plan.ar_deblur_iterate(g, x, 1)
+            done += 1
+            Xo, _ = O.landweber_step(X, G, H, d=d)
+            e = rel(host(x), Xo)
+            say(f"  1024 k={k} one-step rel err {e:.2e}")
+            assert e <= 1e-5
+
+
+def test_iterate_deterministic_and_zero_iters():
+    H = synth.psf_motion(7)
+    n = 200
+    rng = np.random.default_rng(0)
+    G = rng.uniform(0, 1, (n, n))
+    with P.Plan(n, n, H) as plan:
+        outs = []
+        for _ in range(2):
+            g = dev(G, torch.float32)
+            x = torch.zeros_like(g)
+            rc, res, _, _ = plan.ar_deblur_iterate(g, x, 5, want_resnorm=True)
+            outs.append((host(x), res))
+        assert np.array_equal(outs[0][0], outs[1][0])
+        assert np.array_equal(outs[0][1], outs[1][1])
+        g = dev(G, torch.float32)
+        x = torch.ones_like(g)
+        rc, res, _, _ = plan.ar_deblur_iterate(g, x, 0, want_resnorm=True)
+        assert rc == 0 and np.all(host(x) == 1.0)
+
+
+def test_iterate_nonfinite_reported():
+    H = synth.psf_random(2, 2, seed=1)
+    G = np.ones((32, 32))
+    G[5, 7] = np.nan
+    with P.Plan(32, 32, H) as plan:
+        g = dev(G, torch.float32)
+        x = torch.zeros_like(g)
+        rc, res, _, _ = plan.ar_deblur_iterate(g, x, 3, want_resnorm=True)
+        assert rc == -7
+        assert not np.isfinite(res).all()
+
+
+def test_batch_sizes_transform_and_blur():
+    """The square sizes of the batched workload (prime n - 1 for 128, 192,
+    384) with their PSF sizes."""
+    for i in range(6):
+        F, H, E, prm = synth.batch_problem(i)
+        n = prm["n"]
+        say(f"batch problem {i}: n={n} psf={H.shape}")
+        X = F.astype(np.float32).astype(np.float64)
+        with P.Plan(n, n, H) as plan:
+            x = dev(X, torch.float32)
+            y = torch.empty_like(x)
+            plan.ar_blur_apply(x, y)
+            assert rel(host(y), O.blur(X, H)) <= 1e-6
+            plan.ar_precond_set(P.AR_FILTER_TIKHONOV, prm["alpha"])
+            plan.ar_precond_solve(x, y)
+            d = O.tikhonov(O.eigenvalues(H, n, n), prm["alpha"])
+            assert rel(host(y), O.precond_apply(X, d)) <= 2e-5

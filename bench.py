@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark: D-Landweber under AR boundary conditions on one MI355X.
+
+A step is one pass of the whole hot path over the 1024x1024 workload:
+residual r = g - A x (AR blur, FP64 norm partials), y = A' r (reblur),
+c = T~ y along rows, the fused column pass T~ / filter d / T, and the row
+pass T fused with x += tau w, i.e. one preconditioned Landweber iteration
+including its per-iteration FP64 residual norm.  The timed region runs
+exactly K steps from x_0 = 0 with all inputs resident on the GPU; the
+per-iteration norms are copied to the host once at the end (inside the
+timed region).
+
+Prints one JSON line (see the repository's design notes for the roofline
+and the CPU baseline definitions).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32x|f32]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "Mpixel-iters/s at 1024² FP32 + GPU time to best rel. error, learned vs plain"
+WORKLOAD = "ar1024_f32_motion15"
+
+# MI355X published peaks used for the roofline (dense, per GPU)
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = 78.6   # FP64 vector, and FP32 vector without packed FP32
+                          # (256 CUs x 64 FMA lanes/clk x 2 flop x 2.4 GHz)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--dtype", default="f32x", choices=["f32x", "f32"])
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    return ap.parse_args()
+
+
+def make_inputs(torch, P, dt):
+    import synth
+    F, H, E, p = synth.workload(WORKLOAD)
+    n = p["n"]
+    tdt = torch.float32
+    f = torch.from_numpy(F).to("cuda:0", tdt)
+    e = torch.from_numpy(E).to("cuda:0", tdt)
+    plan = P.Plan(n, n, H, dtype=dt)
+    b = torch.empty_like(f)
+    plan.ar_blur_apply(f, b)                       # noise-free data A f on the GPU
+    g = b + (p["nu"] * torch.linalg.vector_norm(b.double()) /
+             torch.linalg.vector_norm(e.double())).float() * e
+    plan.ar_precond_set(P.AR_FILTER_TIKHONOV, p["alpha"])
+    torch.cuda.synchronize()
+    return plan, f, g, F, H, E, p
+
+
+def time_kernel(torch, fn, reps, stream):
+    """Average duration (s) of one launch of `fn` over `reps` launches,
+    from HIP events recorded on the launch stream."""
+    s = torch.cuda.Event(enable_timing=True)
+    t = torch.cuda.Event(enable_timing=True)
+    for _ in range(5):
+        fn()
+    s.record(stream)
+    for _ in range(reps):
+        fn()
+    t.record(stream)
+    t.synchronize()
+    return s.elapsed_time(t) / 1e3 / reps
+
+
+def cpu_baseline(F, H, E, p, iters):
+    """The FP64 oracle (as written, untuned) on this host: a bounded sample
+    of the same workload (`iters` D-Landweber iterations after one warm-up
+    iteration), in Mpixel-iters/s."""
+    import oracle as O
+    G = O.observe(F, H, E, p["nu"])
+    d = O.tikhonov(O.eigenvalues(H, *G.shape), p["alpha"])
+    X = np.zeros_like(G)
+    X, _ = O.landweber_step(X, G, H, d=d)          # warm-up
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        X, _ = O.landweber_step(X, G, H, d=d)
+    dt = time.perf_counter() - t0
+    px = G.size * iters
+    return {"value": px / dt / 1e6, "unit": "Mpixel-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} FP64 D-Landweber iterations of the 1024x1024 15x15-PSF workload "
+                      f"after 1 warm-up ({dt:.1f} s); numpy/scipy single-threaded "
+                      f"(host os.cpu_count()={os.cpu_count()})"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); "
+              "the multi-GPU sharding is a design, not part of this build", file=sys.stderr)
+        return 2
+    import torch
+    import paper_1211_0393_amd as P
+    P.load()                                            # fail loudly without the HIP library
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    plan, f, g, F, H, E, p = make_inputs(torch, P, a.dtype)
+    n = p["n"]
+    stream = torch.cuda.current_stream()
+    x = torch.zeros_like(g)
+
+    # warm-up (untimed)
+    if a.warmup > 0:
+        plan.ar_deblur_iterate(g, x, a.warmup, want_resnorm=True)
+    x.zero_()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    rc, res, _, _ = plan.ar_deblur_iterate(g, x, a.steps, want_resnorm=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    t_step = max(wall, gpu_s) / a.steps
+    value = n * n / t_step / 1e6
+
+    # quality of the timed run and of the unpreconditioned reference run
+    x.zero_()
+    rc_q, _, rre, best = plan.ar_deblur_iterate(g, x, a.steps, f_true=f, want_rre=True)
+    xr = torch.zeros_like(g)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc_p, _, rre_p, best_p = plan.ar_deblur_iterate(g, xr, a.steps, precondition=False,
+                                                    f_true=f, want_rre=True)
+    plain_s = time.perf_counter() - t1
+
+    # dominant kernel: the AR blur (two launches per step), timed alone
+    y = torch.empty_like(g)
+    t_conv = time_kernel(torch, lambda: plan.ar_blur_apply(x, y), a.kernel_reps, stream)
+    P_taps = (2 * plan.q1 + 1) * (2 * plan.q2 + 1)
+    flops = 2.0 * P_taps * n * n                        # one FMA per tap and pixel
+    achieved = flops / t_conv / 1e12
+    roof = {"bound": "alu", "kernel": "conv_kernel (A x, 15x15 taps, 1024x1024)",
+            "achieved": round(achieved, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel_us": round(t_conv * 1e6, 2),
+            "hbm_frac_of_step": round(n * n * 36 / t_step / 1e9 / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if not a.no_cpu and int(os.environ.get("RANK", "0")) == 0:
+        cpu = cpu_baseline(F, H, E, p, a.cpu_iters)
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpixel-iters/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(t_step * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 images, f64 arithmetic" if a.dtype == "f32x" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "1024x1024 phantom (40 blobs + 20 rectangles), 15x15 motion PSF "
+                               "(length 11 at 30 deg, Gaussian sigma 1), 0.5% noise, AR BCs, "
+                               "D-Landweber with Tikhonov alpha 5e-3, reblur transpose, tau 1",
+                   "n1": n, "n2": n, "psf": [15, 15], "alpha": p["alpha"],
+                   "iterations": a.steps, "parallelism": "single GPU"},
+        "status": rc,
+        "quality": {"best_it": best, "best_rre": float(np.min(rre)) if rre is not None else None,
+                    "plain_best_it": best_p,
+                    "plain_best_rre": float(np.min(rre_p)) if rre_p is not None else None,
+                    "plain_run_s": round(plain_s, 5),
+                    "final_resnorm": float(res[-1]) if res is not None else None},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

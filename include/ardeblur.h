@@ -12,8 +12,9 @@
  *    the fast, contiguous one (Sec. 1: row-wise ordering from the top-left
  *    corner).  Element (i1, i2) sits at offset i1 * n2 + i2.
  *  - Image buffers are DEVICE pointers on the plan's device, owned by the
- *    caller; the library never frees them.  Their element type is the plan
- *    dtype (AR_F32 -> float, AR_F64 -> double) unless stated otherwise.
+ *    caller; the library never frees them.  Their element type is the plan's
+ *    storage type (AR_F32 and AR_F32_ACC64 -> float, AR_F64 -> double)
+ *    unless stated otherwise.
  *  - The PSF is a HOST array of (2 q1 + 1) x (2 q2 + 1) doubles, row-major,
  *    psf[(q1 + s1) * (2 q2 + 1) + (q2 + s2)] = h_{s1,s2} (eq.
  *    (coefficienti_psf)).  It must be finite, nonnegative, sum to 1 within
@@ -39,7 +40,14 @@ extern "C" {
 
 typedef struct ar_plan_s *ar_plan_t;
 
-enum ar_dtype { AR_F32 = 0, AR_F64 = 1 };
+/* Precision of a plan.
+ *  AR_F32       : float images, float arithmetic in blur and transforms.
+ *  AR_F64       : double images and arithmetic.
+ *  AR_F32_ACC64 : float images; blur accumulation, boundary extension and
+ *                 transforms computed in double (full rate on gfx950 when
+ *                 packed FP32 is not used), intermediates stored as float.
+ * Eigenvalues, the filter division and all norms are FP64 in every mode. */
+enum ar_dtype { AR_F32 = 0, AR_F64 = 1, AR_F32_ACC64 = 2 };
 
 /* Transpose used by the iteration: the reblurring A' = A(PSF rotated by
  * 180 degrees) that the paper's experiments use (Sec. 4), or the exact
@@ -74,7 +82,7 @@ enum ar_status {
  * and the default Tikhonov filter with param = 1e-2.  Device scratch for
  * the iteration is allocated here and owned by the plan.
  *   out    : receives the plan (set to NULL on failure)
- *   dtype  : AR_F32 or AR_F64 (image buffers' element type)
+ *   dtype  : AR_F32, AR_F64 or AR_F32_ACC64 (see enum ar_dtype)
  *   device : HIP device ordinal the plan lives on
  * Errors: AR_EINVAL, AR_ESHAPE, AR_EPSF, AR_EDEVICE, AR_ENOMEM. */
 int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_host,

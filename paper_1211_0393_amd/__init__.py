@@ -8,7 +8,9 @@ library's HIP kernels.  Build the library with
 from ._lib import (  # noqa: F401
     AR_ADJOINT,
     AR_F32,
+    AR_F32_ACC64,
     AR_F64,
+    DTYPES,
     AR_FILTER_IDENTITY,
     AR_FILTER_THRESHOLD,
     AR_FILTER_TIKHONOV,

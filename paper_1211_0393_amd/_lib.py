@@ -17,7 +17,8 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libardeblur.so")
 
-AR_F32, AR_F64 = 0, 1
+AR_F32, AR_F64, AR_F32_ACC64 = 0, 1, 2
+DTYPES = {"f32": AR_F32, "f64": AR_F64, "f32x": AR_F32_ACC64}
 AR_REBLUR, AR_ADJOINT = 0, 1
 AR_FILTER_TIKHONOV, AR_FILTER_THRESHOLD, AR_FILTER_IDENTITY = 0, 1, 3
 
@@ -97,7 +98,7 @@ class Plan:
             raise ValueError("psf must be 2-D")
         self.n1, self.n2 = int(n1), int(n2)
         self.q1, self.q2 = (psf.shape[0] - 1) // 2, (psf.shape[1] - 1) // 2
-        self.dtype = {"f32": AR_F32, "f64": AR_F64}[dtype]
+        self.dtype = DTYPES[dtype]
         self.device = int(device)
         self._h = C.c_void_p()
         lib = load()

@@ -49,19 +49,21 @@ __device__ __forceinline__ Rule ar_rule(int i, int n, int q) {
   return r;
 }
 
-template <typename T>
-__device__ __forceinline__ T load_ext(const T *__restrict__ in, int n1, int n2, int q1, int q2,
+// Value of the extended image at (i, j), computed in the compute type T
+// from storage-type pixels.
+template <typename T, typename TS>
+__device__ __forceinline__ T load_ext(const TS *__restrict__ in, int n1, int n2, int q1, int q2,
                                       int i, int j, bool zero_ext) {
-  if (i >= 0 && i < n1 && j >= 0 && j < n2) return in[(size_t)i * n2 + j];
+  if (i >= 0 && i < n1 && j >= 0 && j < n2) return T(in[(size_t)i * n2 + j]);
   if (zero_ext) return T(0);
   const Rule a = ar_rule(i, n1, q1), b = ar_rule(j, n2, q2);
   if (a.w0 == 0.f || b.w0 == 0.f) return T(0);
   // tensor product of the two 1-D rules: one, two or four terms
-  T v = T(a.w0) * (T(b.w0) * in[(size_t)a.i0 * n2 + b.i0]);
-  if (b.w1 != 0.f) v += T(a.w0) * (T(b.w1) * in[(size_t)a.i0 * n2 + b.i1]);
+  T v = T(a.w0) * (T(b.w0) * T(in[(size_t)a.i0 * n2 + b.i0]));
+  if (b.w1 != 0.f) v += T(a.w0) * (T(b.w1) * T(in[(size_t)a.i0 * n2 + b.i1]));
   if (a.w1 != 0.f) {
-    v += T(a.w1) * (T(b.w0) * in[(size_t)a.i1 * n2 + b.i0]);
-    if (b.w1 != 0.f) v += T(a.w1) * (T(b.w1) * in[(size_t)a.i1 * n2 + b.i1]);
+    v += T(a.w1) * (T(b.w0) * T(in[(size_t)a.i1 * n2 + b.i0]));
+    if (b.w1 != 0.f) v += T(a.w1) * (T(b.w1) * T(in[(size_t)a.i1 * n2 + b.i1]));
   }
   return v;
 }
@@ -82,12 +84,14 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return s;
 }
 
+// TS: storage type of images; T: compute type of the halo tile, weights
+// and accumulators (double for FP64 accumulation of FP32 images).
 // Q2 >= 0: compile-time column half-width (tap loop fully unrolled).
 // Q2 <  0: generic kernel with a runtime column half-width.
-template <typename T, int Q2>
+template <typename TS, typename T, typename TO, int Q2>
 __global__ __launch_bounds__(NT) void conv_kernel(
-    const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ w, int n1, int n2,
-    int q1, int q2rt, int o1, int o2, int m1, int m2, int zero_ext, const T *__restrict__ gsub,
+    const TS *__restrict__ in, TO *__restrict__ out, const T *__restrict__ w, int n1, int n2,
+    int q1, int q2rt, int o1, int o2, int m1, int m2, int zero_ext, const TS *__restrict__ gsub,
     double *__restrict__ partial, int tiles_x) {
   constexpr bool GEN = Q2 < 0;
   const int q2 = GEN ? q2rt : Q2;
@@ -108,13 +112,13 @@ __global__ __launch_bounds__(NT) void conv_kernel(
   const int lr = tid >> 6, lc = tid & 63;
   if (inside) {
     for (int a = lr; a < LH; a += NT / 64) {
-      const T *src = in + (size_t)(ib1 + a) * n2 + ib2;
-      for (int c = lc; c < LW; c += 64) tile[a * pitch + c] = src[c];
+      const TS *src = in + (size_t)(ib1 + a) * n2 + ib2;
+      for (int c = lc; c < LW; c += 64) tile[a * pitch + c] = T(src[c]);
     }
   } else {
     for (int a = lr; a < LH; a += NT / 64)
       for (int c = lc; c < LW; c += 64)
-        tile[a * pitch + c] = load_ext(in, n1, n2, q1, q2, ib1 + a, ib2 + c, zero_ext != 0);
+        tile[a * pitch + c] = load_ext<T, TS>(in, n1, n2, q1, q2, ib1 + a, ib2 + c, zero_ext != 0);
   }
   __syncthreads();
 
@@ -186,10 +190,13 @@ __global__ __launch_bounds__(NT) void conv_kernel(
       T val = r == 0 ? acc0[c] : acc1[c];
       const size_t o = (size_t)oi * m2 + oj;
       if (gsub) {
-        val = gsub[o] - val;
-        ss += (double)val * (double)val;
+        val = T(gsub[o]) - val;
+        const TO rs = TO(val);
+        ss += (double)rs * (double)rs;
+        out[o] = rs;
+      } else {
+        out[o] = TO(val);
       }
-      out[o] = val;
     }
   }
   if (partial) {
@@ -203,8 +210,8 @@ __global__ __launch_bounds__(NT) void conv_kernel(
 // Fold of the extended-grid correlation back onto the FOV (transpose of the
 // AR extension): along each axis a ghost at 1 - t adds 2x to position 1 and
 // -1x to position 1 + t, a ghost at n + t adds 2x to n and -1x to n - t.
-template <typename T>
-__global__ __launch_bounds__(256) void fold_kernel(const T *__restrict__ ext, T *__restrict__ out,
+template <typename TS, typename T>
+__global__ __launch_bounds__(256) void fold_kernel(const T *__restrict__ ext, TS *__restrict__ out,
                                                    int n1, int n2, int q1, int q2) {
   const int j2 = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j1 = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -232,13 +239,10 @@ __global__ __launch_bounds__(256) void fold_kernel(const T *__restrict__ ext, T 
     for (int b = 0; b < c2; ++b) s += T(w2[b]) * row[e2[b]];
     acc += T(w1[a]) * s;
   }
-  out[(size_t)j1 * n2 + j2] = acc;
+  out[(size_t)j1 * n2 + j2] = TS(acc);
 }
 
-template <typename T, int Q2>
-void *conv_fn() { return reinterpret_cast<void *>(&conv_kernel<T, Q2>); }
-
-template <typename T>
+template <typename TS, typename T, typename TO>
 hipError_t launch_conv_t(const ar_plan_s *p, const void *in, void *out, const void *w, int o1,
                          int o2, int m1, int m2, bool zero_ext, const void *g, double *partial,
                          int blocks, int tiles_x, hipStream_t st) {
@@ -246,14 +250,14 @@ hipError_t launch_conv_t(const ar_plan_s *p, const void *in, void *out, const vo
   const int LW = TW + 2 * q2, pitch = (LW + 3) & ~3, LH = TH + 2 * q1;
   size_t smem = (size_t)LH * pitch * sizeof(T);
   if (smem < 64 * sizeof(double)) smem = 64 * sizeof(double);
-  const T *ti = static_cast<const T *>(in);
-  T *to = static_cast<T *>(out);
+  const TS *ti = static_cast<const TS *>(in);
+  TO *to = static_cast<TO *>(out);
   const T *tw = static_cast<const T *>(w);
-  const T *tg = static_cast<const T *>(g);
+  const TS *tg = static_cast<const TS *>(g);
   const int ze = zero_ext ? 1 : 0;
 #define AR_CONV_CASE(QQ)                                                                  \
   case QQ:                                                                                \
-    hipLaunchKernelGGL((conv_kernel<T, QQ>), dim3(blocks), dim3(NT), smem, st, ti, to, tw, \
+    hipLaunchKernelGGL((conv_kernel<TS, T, TO, QQ>), dim3(blocks), dim3(NT), smem, st, ti, to, tw, \
                        p->n1, p->n2, q1, q2, o1, o2, m1, m2, ze, tg, partial, tiles_x);   \
     break;
   switch (q2) {
@@ -262,7 +266,7 @@ hipError_t launch_conv_t(const ar_plan_s *p, const void *in, void *out, const vo
     AR_CONV_CASE(10) AR_CONV_CASE(11) AR_CONV_CASE(12) AR_CONV_CASE(13) AR_CONV_CASE(14)
     AR_CONV_CASE(15)
     default:
-      hipLaunchKernelGGL((conv_kernel<T, -1>), dim3(blocks), dim3(NT), smem, st, ti, to, tw,
+      hipLaunchKernelGGL((conv_kernel<TS, T, TO, -1>), dim3(blocks), dim3(NT), smem, st, ti, to, tw,
                          p->n1, p->n2, q1, q2, o1, o2, m1, m2, ze, tg, partial, tiles_x);
   }
 #undef AR_CONV_CASE
@@ -278,18 +282,26 @@ int conv_blocks(const ar_plan_s *p, int m1, int m2) {
 
 int conv_launch(const ar_plan_s *p, const void *in, void *out, const void *w, int o1, int o2,
                 int m1, int m2, bool zero_ext, const void *g_minus, double *partial,
-                int *nblocks_out, hipStream_t st) {
+                int *nblocks_out, hipStream_t st, bool out_compute) {
   const int tiles_x = (m2 + TW - 1) / TW;
   const int blocks = conv_blocks(p, m1, m2);
   const size_t LH = TH + 2 * (size_t)p->q1, LW = TW + 2 * (size_t)p->q2;
-  if (LH * ((LW + 3) & ~(size_t)3) * p->esize > 64 * 1024)
+  if (LH * ((LW + 3) & ~(size_t)3) * p->csize > 64 * 1024)
     return fail(AR_EUNSUPPORTED, "PSF too large for the LDS halo tile");
   if (nblocks_out) *nblocks_out = blocks;
-  hipError_t e = p->dtype == AR_F64
-                     ? launch_conv_t<double>(p, in, out, w, o1, o2, m1, m2, zero_ext, g_minus,
-                                             partial, blocks, tiles_x, st)
-                     : launch_conv_t<float>(p, in, out, w, o1, o2, m1, m2, zero_ext, g_minus,
+  hipError_t e;
+  if (p->dtype == AR_F64)
+    e = launch_conv_t<double, double, double>(p, in, out, w, o1, o2, m1, m2, zero_ext, g_minus,
+                                              partial, blocks, tiles_x, st);
+  else if (p->dtype == AR_F32_ACC64 && out_compute)
+    e = launch_conv_t<float, double, double>(p, in, out, w, o1, o2, m1, m2, zero_ext, g_minus,
+                                             partial, blocks, tiles_x, st);
+  else if (p->dtype == AR_F32_ACC64)
+    e = launch_conv_t<float, double, float>(p, in, out, w, o1, o2, m1, m2, zero_ext, g_minus,
                                             partial, blocks, tiles_x, st);
+  else
+    e = launch_conv_t<float, float, float>(p, in, out, w, o1, o2, m1, m2, zero_ext, g_minus,
+                                           partial, blocks, tiles_x, st);
   if (e != hipSuccess) return hip_fail(e, "conv_kernel launch");
   return AR_OK;
 }
@@ -298,11 +310,15 @@ int fold_launch(const ar_plan_s *p, const void *ext, void *out, hipStream_t st) 
   if (p->q1 > 36 || p->q2 > 36) return fail(AR_EUNSUPPORTED, "adjoint fold supports q <= 36");
   dim3 grid((p->n2 + 63) / 64, (p->n1 + 3) / 4);
   if (p->dtype == AR_F64)
-    hipLaunchKernelGGL(fold_kernel<double>, grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((fold_kernel<double, double>), grid, dim3(256), 0, st,
                        static_cast<const double *>(ext), static_cast<double *>(out), p->n1,
                        p->n2, p->q1, p->q2);
+  else if (p->dtype == AR_F32_ACC64)
+    hipLaunchKernelGGL((fold_kernel<float, double>), grid, dim3(256), 0, st,
+                       static_cast<const double *>(ext), static_cast<float *>(out), p->n1,
+                       p->n2, p->q1, p->q2);
   else
-    hipLaunchKernelGGL(fold_kernel<float>, grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((fold_kernel<float, float>), grid, dim3(256), 0, st,
                        static_cast<const float *>(ext), static_cast<float *>(out), p->n1, p->n2,
                        p->q1, p->q2);
   hipError_t e = hipGetLastError();
@@ -319,7 +335,7 @@ extern "C" int ar_blur_apply(ar_plan_t p, const void *x, void *y, void *stream) 
   if (x == y) return fail(AR_EALIAS, "ar_blur_apply: x and y must not alias");
   AR_HIP(hipSetDevice(p->device));
   return conv_launch(p, x, y, p->w_fwd, 0, 0, p->n1, p->n2, false, nullptr, nullptr, nullptr,
-                     static_cast<hipStream_t>(stream));
+                     static_cast<hipStream_t>(stream), false);
 }
 
 extern "C" int ar_blur_apply_T(ar_plan_t p, const void *r, void *y, int tmode, void *stream) {
@@ -329,10 +345,10 @@ extern "C" int ar_blur_apply_T(ar_plan_t p, const void *r, void *y, int tmode, v
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (tmode == AR_REBLUR)
     return conv_launch(p, r, y, p->w_rev, 0, 0, p->n1, p->n2, false, nullptr, nullptr, nullptr,
-                       st);
+                       st, false);
   if (tmode == AR_ADJOINT) {
     int rc = conv_launch(p, r, p->ext, p->w_rev, -p->q1, -p->q2, p->n1 + 2 * p->q1,
-                         p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st);
+                         p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st, true);
     if (rc != AR_OK) return rc;
     return fold_launch(p, p->ext, y, st);
   }

@@ -330,11 +330,12 @@ __device__ __forceinline__ double block_sum256(double v, double *red) {
 }
 
 // MODE: ROW_FWD, ROW_INV, ROW_INV_UPDATE (x += tau * T_{n2}-pass output).
-template <typename T, int MODE>
+// TS: storage type of the images, T: compute type (LDS, tables, arithmetic).
+template <typename TS, typename T, int MODE>
 __global__ __launch_bounds__(256) void rows_kernel(
-    const T *__restrict__ in, T *__restrict__ out, int n1, int m, FftDesc fd,
+    const TS *__restrict__ in, TS *__restrict__ out, int n1, int m, FftDesc fd,
     const V2<T> *__restrict__ tw, const V2<T> *__restrict__ gen, const V2<T> *__restrict__ post,
-    T alpha, T scale, int B, int Mp, T tau, const T *__restrict__ f_true,
+    T alpha, T scale, int B, int Mp, T tau, const TS *__restrict__ f_true,
     double *__restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V2<T> *bufA = reinterpret_cast<V2<T> *>(smem_raw);
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(256) void rows_kernel(
   for (int idx = threadIdx.x; idx < B * m; idx += blockDim.x) {
     const int s = idx / m, t = idx - s * m;
     const int r = row0 + s;
-    re[s * rs + t] = r < n1 ? in[(size_t)r * m + t] : T(0);
+    re[s * rs + t] = r < n1 ? T(in[(size_t)r * m + t]) : T(0);
   }
   __syncthreads();
   for (int s = threadIdx.x; s < B; s += blockDim.x) {
@@ -381,14 +382,14 @@ __global__ __launch_bounds__(256) void rows_kernel(
     }
     const size_t o = (size_t)r * m + t;
     if (MODE == ROW_INV_UPDATE) {
-      const T xn = out[o] + tau * val;
+      const TS xn = TS(T(out[o]) + tau * val);
       out[o] = xn;
       if (f_true) {
         const double df = (double)xn - (double)f_true[o];
         ss += df * df;
       }
     } else {
-      out[o] = val;
+      out[o] = TS(val);
     }
   }
   if (MODE == ROW_INV_UPDATE && partial) {
@@ -400,9 +401,9 @@ __global__ __launch_bounds__(256) void rows_kernel(
 
 // ---------------------------------------------------------- column pass
 
-template <typename T, int MODE>
+template <typename TS, typename T, int MODE>
 __global__ __launch_bounds__(256) void cols_kernel(
-    const T *__restrict__ in, T *__restrict__ out, int m, int n2, FftDesc fd,
+    const TS *__restrict__ in, TS *__restrict__ out, int m, int n2, FftDesc fd,
     const V2<T> *__restrict__ tw, const V2<T> *__restrict__ gen, const V2<T> *__restrict__ post,
     T alpha, T scale, int C, const T *__restrict__ dflt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(256) void cols_kernel(
   for (int idx = threadIdx.x; idx < C * m; idx += blockDim.x) {
     const int t = idx / C, s = idx - t * C;
     const int c = col0 + s;
-    re[t * C + s] = c < n2 ? in[(size_t)t * n2 + c] : T(0);
+    re[t * C + s] = c < n2 ? T(in[(size_t)t * n2 + c]) : T(0);
   }
   __syncthreads();
   for (int s = threadIdx.x; s < C; s += blockDim.x) {
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(256) void cols_kernel(
       if (t == 0) val = alpha * e0[s];
       else if (t == m - 1) val = alpha * e1[s];
       else val = dst_value<T>(U + s, C, t, M, post, scale);
-      out[(size_t)t * n2 + c] = val;
+      out[(size_t)t * n2 + c] = TS(val);
     }
     return;
   }
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(256) void cols_kernel(
     else
       val = dst_value<T>(U + s, C, t, M, post, scale) + y0 * (T(M - t) * invM) +
             y1 * (T(t) * invM);
-    out[(size_t)t * n2 + c] = val;
+    out[(size_t)t * n2 + c] = TS(val);
   }
 }
 
@@ -530,22 +531,32 @@ FftDesc make_desc(const FftPlan &fp) {
   return d;
 }
 
-// rows per workgroup / columns per workgroup
-int rows_per_block(int M, size_t esize) {
-  const size_t cplx = 2 * esize;
-  int B = 2048 / (M > 0 ? M : 1);
+// Rows (columns) per workgroup: enough sequences to give 256 threads work,
+// within 63 KiB of LDS when possible; a single long sequence may use up to
+// kMaxLds (gfx950 has 160 KiB of LDS per CU).
+constexpr size_t kLdsSoft = 63 * 1024, kMaxLds = 150 * 1024;
+int seqs_per_block(int M, size_t csize, int target) {
+  const size_t cplx = 2 * csize;
+  int B = target / (M > 0 ? M : 1);
   if (B < 1) B = 1;
   if (B > 64) B = 64;
-  while (B > 1 && 2 * (size_t)B * M * cplx > 63 * 1024) --B;
+  while (B > 1 && 2 * (size_t)B * M * cplx > kLdsSoft) --B;
   return B;
 }
-int cols_per_block(int M, size_t esize) {
-  const size_t cplx = 2 * esize;
-  int C = 4096 / (M > 0 ? M : 1);
-  if (C < 1) C = 1;
-  if (C > 64) C = 64;
-  while (C > 1 && 2 * (size_t)C * M * cplx > 63 * 1024) --C;
-  return C;
+int rows_per_block(int M, size_t csize) { return seqs_per_block(M, csize, 2048); }
+int cols_per_block(int M, size_t csize) { return seqs_per_block(M, csize, 4096); }
+
+size_t seq_lds_bytes(int B, int M, size_t csize) {
+  return 2 * (size_t)B * M * 2 * csize + 2 * (size_t)B * csize + 64;
+}
+
+// Raise the dynamic LDS limit of a kernel once when a launch needs more
+// than the default 64 KiB.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 }  // namespace
@@ -560,7 +571,8 @@ bool radix_has_codelet(int r) {
   }
 }
 
-int fft_plan_build(FftPlan &fp, int m, int dtype, hipStream_t st) {
+// `cdouble`: tables in double (compute type double) or float.
+int fft_plan_build(FftPlan &fp, int m, bool cdouble, hipStream_t st) {
   fp.m = m;
   fp.M = m - 1;
   int M = fp.M;
@@ -595,7 +607,7 @@ int fft_plan_build(FftPlan &fp, int m, int dtype, hipStream_t st) {
   }
   fp.tw_count = twc;
   fp.gen_count = genc;
-  const size_t cb = dtype == AR_F64 ? sizeof(double2) : sizeof(float2);
+  const size_t cb = cdouble ? sizeof(double2) : sizeof(float2);
   AR_HIP(hipMalloc(&fp.tw, (twc > 0 ? twc : 1) * cb));
   AR_HIP(hipMalloc(&fp.post, (size_t)(fp.M + 1) * cb));
   AR_HIP(hipMalloc(&fp.gen, (genc > 0 ? genc : 1) * cb));
@@ -612,7 +624,7 @@ int fft_plan_build(FftPlan &fp, int m, int dtype, hipStream_t st) {
   AR_HIP(hipMemcpyAsync(dints, ints.data(), ints.size() * sizeof(int), hipMemcpyHostToDevice, st));
   const int *p_ns = dints, *p_r = dints + nst, *p_b = dints + 2 * nst;
   const int *p_gr = dints + 3 * nst, *p_gb = dints + 3 * nst + ngen;
-  if (dtype == AR_F64)
+  if (cdouble)
     hipLaunchKernelGGL(tables_kernel<double>, dim3(64), dim3(256), 0, st,
                        static_cast<V2<double> *>(fp.tw), p_ns, p_r, p_b, nst,
                        static_cast<V2<double> *>(fp.post), fp.M,
@@ -636,42 +648,48 @@ void fft_plan_free(FftPlan &fp) {
 }
 
 int rows_blocks(const ar_plan_s *p) {
-  const int B = rows_per_block(p->fft_row.M, p->esize);
+  const int B = rows_per_block(p->fft_row.M, p->csize);
   return (p->n1 + B - 1) / B;
 }
 
-template <typename T>
+int max_axis_len(size_t csize) {
+  int M = (int)((kMaxLds - 64 - 2 * csize) / (4 * csize));
+  while (M > 2 && seq_lds_bytes(1, M, csize) > kMaxLds) --M;
+  return M + 1;
+}
+
+template <typename TS, typename T>
 static int rows_launch_t(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                          const void *f_true, double *partial, hipStream_t st) {
   const FftPlan &fp = p->fft_row;
   const int m = p->n2, M = fp.M;
   const int B = rows_per_block(M, sizeof(T));
   const int blocks = (p->n1 + B - 1) / B;
-  const size_t smem = 2 * (size_t)B * M * sizeof(V2<T>) + 2 * (size_t)B * sizeof(T) + 64;
+  const size_t smem = seq_lds_bytes(B, M, sizeof(T));
+  if (smem > kMaxLds) return fail(AR_EUNSUPPORTED, "row transform exceeds LDS");
   const FftDesc fd = make_desc(fp);
   const T alpha = T(std::sqrt((double)m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))));
   const T scale = T(std::sqrt(2.0 / M) / 4.0);
   auto tw = static_cast<const V2<T> *>(fp.tw);
   auto gen = static_cast<const V2<T> *>(fp.gen);
   auto post = static_cast<const V2<T> *>(fp.post);
-  auto ti = static_cast<const T *>(in);
-  auto to = static_cast<T *>(out);
-  auto tf = static_cast<const T *>(f_true);
-  switch (mode) {
-    case ROW_FWD:
-      hipLaunchKernelGGL((rows_kernel<T, ROW_FWD>), dim3(blocks), dim3(256), smem, st, ti, to,
-                         p->n1, m, fd, tw, gen, post, alpha, scale, B, M, T(tau), tf, partial);
-      break;
-    case ROW_INV:
-      hipLaunchKernelGGL((rows_kernel<T, ROW_INV>), dim3(blocks), dim3(256), smem, st, ti, to,
-                         p->n1, m, fd, tw, gen, post, alpha, scale, B, M, T(tau), tf, partial);
-      break;
-    default:
-      hipLaunchKernelGGL((rows_kernel<T, ROW_INV_UPDATE>), dim3(blocks), dim3(256), smem, st,
-                         ti, to, p->n1, m, fd, tw, gen, post, alpha, scale, B, M, T(tau), tf,
-                         partial);
+  auto ti = static_cast<const TS *>(in);
+  auto to = static_cast<TS *>(out);
+  auto tf = static_cast<const TS *>(f_true);
+  hipError_t e = hipSuccess;
+#define AR_ROWS(MODE)                                                                       \
+  e = allow_lds(rows_kernel<TS, T, MODE>, smem);                                            \
+  if (e == hipSuccess) {                                                                    \
+    hipLaunchKernelGGL((rows_kernel<TS, T, MODE>), dim3(blocks), dim3(256), smem, st, ti, to, \
+                       p->n1, m, fd, tw, gen, post, alpha, scale, B, M, T(tau), tf, partial); \
+    e = hipGetLastError();                                                                  \
   }
-  hipError_t e = hipGetLastError();
+  switch (mode) {
+    case ROW_FWD: AR_ROWS(ROW_FWD) break;
+    case ROW_INV: AR_ROWS(ROW_INV) break;
+    default: AR_ROWS(ROW_INV_UPDATE) break;
+  }
+#undef AR_ROWS
   if (e != hipSuccess) return hip_fail(e, "rows_kernel launch");
   return AR_OK;
 }
@@ -679,48 +697,53 @@ static int rows_launch_t(const ar_plan_s *p, const void *in, void *out, int mode
 int rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                 const void *f_true, double *partial, int *nblocks_out, hipStream_t st) {
   if (nblocks_out) *nblocks_out = rows_blocks(p);
-  return p->dtype == AR_F64 ? rows_launch_t<double>(p, in, out, mode, tau, f_true, partial, st)
-                            : rows_launch_t<float>(p, in, out, mode, tau, f_true, partial, st);
+  if (p->dtype == AR_F64)
+    return rows_launch_t<double, double>(p, in, out, mode, tau, f_true, partial, st);
+  if (p->dtype == AR_F32_ACC64)
+    return rows_launch_t<float, double>(p, in, out, mode, tau, f_true, partial, st);
+  return rows_launch_t<float, float>(p, in, out, mode, tau, f_true, partial, st);
 }
 
-template <typename T>
+template <typename TS, typename T>
 static int cols_launch_t(const ar_plan_s *p, const void *in, void *out, int mode,
                          hipStream_t st) {
   const FftPlan &fp = p->fft_col;
   const int m = p->n1, M = fp.M;
   const int C = cols_per_block(M, sizeof(T));
   const int blocks = (p->n2 + C - 1) / C;
-  const size_t smem = 2 * (size_t)C * M * sizeof(V2<T>) + 2 * (size_t)C * sizeof(T) + 64;
+  const size_t smem = seq_lds_bytes(C, M, sizeof(T));
+  if (smem > kMaxLds) return fail(AR_EUNSUPPORTED, "column transform exceeds LDS");
   const FftDesc fd = make_desc(fp);
   const T alpha = T(std::sqrt((double)m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))));
   const T scale = T(std::sqrt(2.0 / M) / 4.0);
   auto tw = static_cast<const V2<T> *>(fp.tw);
   auto gen = static_cast<const V2<T> *>(fp.gen);
   auto post = static_cast<const V2<T> *>(fp.post);
-  auto ti = static_cast<const T *>(in);
-  auto to = static_cast<T *>(out);
+  auto ti = static_cast<const TS *>(in);
+  auto to = static_cast<TS *>(out);
   auto td = static_cast<const T *>(p->d);
-  switch (mode) {
-    case COL_FWD:
-      hipLaunchKernelGGL((cols_kernel<T, COL_FWD>), dim3(blocks), dim3(256), smem, st, ti, to, m,
-                         p->n2, fd, tw, gen, post, alpha, scale, C, td);
-      break;
-    case COL_INV:
-      hipLaunchKernelGGL((cols_kernel<T, COL_INV>), dim3(blocks), dim3(256), smem, st, ti, to, m,
-                         p->n2, fd, tw, gen, post, alpha, scale, C, td);
-      break;
-    default:
-      hipLaunchKernelGGL((cols_kernel<T, COL_FWD_D_INV>), dim3(blocks), dim3(256), smem, st, ti,
-                         to, m, p->n2, fd, tw, gen, post, alpha, scale, C, td);
+  hipError_t e = hipSuccess;
+#define AR_COLS(MODE)                                                                        \
+  e = allow_lds(cols_kernel<TS, T, MODE>, smem);                                             \
+  if (e == hipSuccess) {                                                                     \
+    hipLaunchKernelGGL((cols_kernel<TS, T, MODE>), dim3(blocks), dim3(256), smem, st, ti, to, \
+                       m, p->n2, fd, tw, gen, post, alpha, scale, C, td);                    \
+    e = hipGetLastError();                                                                   \
   }
-  hipError_t e = hipGetLastError();
+  switch (mode) {
+    case COL_FWD: AR_COLS(COL_FWD) break;
+    case COL_INV: AR_COLS(COL_INV) break;
+    default: AR_COLS(COL_FWD_D_INV) break;
+  }
+#undef AR_COLS
   if (e != hipSuccess) return hip_fail(e, "cols_kernel launch");
   return AR_OK;
 }
 
 int cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
-  return p->dtype == AR_F64 ? cols_launch_t<double>(p, in, out, mode, st)
-                            : cols_launch_t<float>(p, in, out, mode, st);
+  if (p->dtype == AR_F64) return cols_launch_t<double, double>(p, in, out, mode, st);
+  if (p->dtype == AR_F32_ACC64) return cols_launch_t<float, double>(p, in, out, mode, st);
+  return cols_launch_t<float, float>(p, in, out, mode, st);
 }
 
 }  // namespace ar

@@ -80,20 +80,21 @@ bool radix_has_codelet(int r);
 
 struct ar_plan_s {
   int n1 = 0, n2 = 0, q1 = 0, q2 = 0, dtype = AR_F32, device = 0;
-  size_t esize = 4;          // bytes per image element
+  size_t esize = 4;          // bytes per image element (storage type)
+  size_t csize = 4;          // bytes per element of the compute type
   // device PSF data
   double *H64 = nullptr;     // (2q1+1)(2q2+1) FP64 PSF as given
   double *S64 = nullptr;     // symmetrized PSF, FP64
-  void *w_fwd = nullptr;     // correlation weights of A: rot180(H), dtype
-  void *w_rev = nullptr;     // correlation weights of A' and of A^T's correlation: H, dtype
+  void *w_fwd = nullptr;     // correlation weights of A: rot180(H), compute type
+  void *w_rev = nullptr;     // weights of A' and of A^T's correlation: H, compute type
   double *lambda = nullptr;  // n1*n2 FP64 eigenvalues
   double *d64 = nullptr;     // n1*n2 FP64 filter
-  void *d = nullptr;         // n1*n2 filter in dtype
+  void *d = nullptr;         // n1*n2 filter in the compute type
   ar::FftPlan fft_row;       // axis i2, length n2
   ar::FftPlan fft_col;       // axis i1, length n1
   // scratch owned by the plan
   void *r = nullptr, *y = nullptr, *c = nullptr;  // n1*n2 dtype each
-  void *ext = nullptr;       // (n1+2q1)(n2+2q2) dtype, adjoint correlation
+  void *ext = nullptr;       // (n1+2q1)(n2+2q2) compute type, adjoint correlation
   double *partials = nullptr;  // per-iteration partial sums
   size_t partials_cap = 0;     // doubles
   double *scalars = nullptr;   // reduced per-iteration scalars
@@ -107,16 +108,20 @@ namespace ar {
 // ---------------------------------------------------------------- launchers
 
 // blur kernels (ar_blur.hip)
+// out_compute: write the output in the compute type (extended-grid
+// intermediate of A^T) instead of the storage type.
 int conv_launch(const ar_plan_s *p, const void *in, void *out, const void *w, int o1, int o2,
                 int m1, int m2, bool zero_ext, const void *g_minus, double *partial,
-                int *nblocks_out, hipStream_t st);
+                int *nblocks_out, hipStream_t st, bool out_compute = false);
 int conv_blocks(const ar_plan_s *p, int m1, int m2);
 int fold_launch(const ar_plan_s *p, const void *ext, void *out, hipStream_t st);
 
 // transform kernels (ar_fft.hip)
 enum RowMode { ROW_FWD = 0, ROW_INV = 1, ROW_INV_UPDATE = 2 };
 enum ColMode { COL_FWD = 0, COL_INV = 1, COL_FWD_D_INV = 2 };
-int fft_plan_build(ar::FftPlan &fp, int m, int dtype, hipStream_t st);
+int fft_plan_build(ar::FftPlan &fp, int m, bool cdouble, hipStream_t st);
+// longest axis the LDS-resident transform supports for a compute type size
+int max_axis_len(size_t csize);
 void fft_plan_free(ar::FftPlan &fp);
 int rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                 const void *f_true, double *partial, int *nblocks_out, hipStream_t st);

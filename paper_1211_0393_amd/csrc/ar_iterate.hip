@@ -78,7 +78,7 @@ extern "C" int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters,
                        nullptr, st);
     } else {
       rc = conv_launch(p, p->r, p->ext, p->w_rev, -p->q1, -p->q2, p->n1 + 2 * p->q1,
-                       p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st);
+                       p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st, true);
       if (rc == AR_OK) rc = fold_launch(p, p->ext, p->y, st);
     }
     if (rc != AR_OK) return rc;

@@ -173,7 +173,7 @@ int elem_blocks(size_t total) {
 }  // namespace
 
 int spectrum_launch(ar_plan_s *p, hipStream_t st) {
-  if (p->dtype == AR_F64)
+  if (p->csize == 8)
     hipLaunchKernelGGL(psf_prep_kernel<double>, dim3(4), dim3(256), 0, st, p->H64, p->S64,
                        static_cast<double *>(p->w_fwd), static_cast<double *>(p->w_rev), p->q1,
                        p->q2);
@@ -197,7 +197,7 @@ int spectrum_launch(ar_plan_s *p, hipStream_t st) {
 
 int filter_launch(ar_plan_s *p, int filter, double param, hipStream_t st) {
   const size_t total = (size_t)p->n1 * p->n2;
-  if (p->dtype == AR_F64)
+  if (p->csize == 8)
     hipLaunchKernelGGL(filter_kernel<double>, dim3(elem_blocks(total)), dim3(256), 0, st,
                        p->lambda, p->d64, static_cast<double *>(p->d), total, filter, param);
   else
@@ -254,9 +254,6 @@ int reduce_rows_launch(const double *partials, int rows, int cols, double *out, 
 
 using namespace ar;
 
-// Largest axis length the LDS-resident transform supports: two complex
-// buffers of n - 1 points per workgroup within 63 KiB of LDS.
-static int max_axis(int dtype) { return dtype == AR_F64 ? 2017 : 4033; }
 
 static void plan_free(ar_plan_s *p) {
   if (!p) return;
@@ -276,12 +273,15 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
   if (!out) return fail(AR_EINVAL, "ar_plan_create: out is NULL");
   *out = nullptr;
   if (!psf_host) return fail(AR_EINVAL, "ar_plan_create: psf is NULL");
-  if (dtype != AR_F32 && dtype != AR_F64) return fail(AR_EINVAL, "ar_plan_create: bad dtype");
+  if (dtype != AR_F32 && dtype != AR_F64 && dtype != AR_F32_ACC64)
+    return fail(AR_EINVAL, "ar_plan_create: bad dtype");
+  const size_t esize = dtype == AR_F64 ? 8 : 4;
+  const size_t csize = dtype == AR_F32 ? 4 : 8;
   if (q1 < 0 || q2 < 0) return fail(AR_ESHAPE, "ar_plan_create: negative PSF half-width");
   if (n1 < 3 || n2 < 3) return fail(AR_ESHAPE, "ar_plan_create: need n1, n2 >= 3");
   if (q1 > n1 - 3 || q2 > n2 - 3)
     return fail(AR_ESHAPE, "ar_plan_create: AR algebra needs q_j <= n_j - 3");
-  if (n1 > max_axis(dtype) || n2 > max_axis(dtype))
+  if (n1 > max_axis_len(csize) || n2 > max_axis_len(csize))
     return fail(AR_ESHAPE, "ar_plan_create: axis longer than the LDS-resident transform supports");
   const int K1 = 2 * q1 + 1, K2 = 2 * q2 + 1, P = K1 * K2;
   double sum = 0.0;
@@ -304,7 +304,8 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
   p->q2 = q2;
   p->dtype = dtype;
   p->device = device;
-  p->esize = dtype == AR_F64 ? 8 : 4;
+  p->esize = esize;
+  p->csize = csize;
   const size_t npx = (size_t)n1 * n2;
   const size_t next = (size_t)(n1 + 2 * q1) * (n2 + 2 * q2);
   int rc = AR_OK;
@@ -317,11 +318,11 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
     return true;
   };
   bool ok = alloc((void **)&p->H64, P * sizeof(double)) && alloc((void **)&p->S64, P * sizeof(double)) &&
-            alloc(&p->w_fwd, P * p->esize) && alloc(&p->w_rev, P * p->esize) &&
+            alloc(&p->w_fwd, P * p->csize) && alloc(&p->w_rev, P * p->csize) &&
             alloc((void **)&p->lambda, npx * sizeof(double)) &&
-            alloc((void **)&p->d64, npx * sizeof(double)) && alloc(&p->d, npx * p->esize) &&
+            alloc((void **)&p->d64, npx * sizeof(double)) && alloc(&p->d, npx * p->csize) &&
             alloc(&p->r, npx * p->esize) && alloc(&p->y, npx * p->esize) &&
-            alloc(&p->c, npx * p->esize) && alloc(&p->ext, next * p->esize);
+            alloc(&p->c, npx * p->esize) && alloc(&p->ext, next * p->csize);
   if (!ok) {
     plan_free(p);
     return rc;
@@ -334,8 +335,8 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
     return rc;
   }
   if ((rc = spectrum_launch(p, st)) != AR_OK || (rc = filter_launch(p, AR_FILTER_TIKHONOV, 1e-2, st)) != AR_OK ||
-      (rc = fft_plan_build(p->fft_row, n2, dtype, st)) != AR_OK ||
-      (rc = fft_plan_build(p->fft_col, n1, dtype, st)) != AR_OK) {
+      (rc = fft_plan_build(p->fft_row, n2, csize == 8, st)) != AR_OK ||
+      (rc = fft_plan_build(p->fft_col, n1, csize == 8, st)) != AR_OK) {
     plan_free(p);
     return rc;
   }

@@ -56,8 +56,9 @@ def test_shape_errors(n1, n2, q):
 
 def test_axis_too_long_for_lds_transform():
     psf = np.ones((1, 1))
-    assert _create(4034, 16, psf)[0] == -2
-    assert _create(16, 2018, psf, dtype=1)[0] == -2
+    assert _create(9597, 16, psf)[0] == -2
+    assert _create(16, 4799, psf, dtype=1)[0] == -2
+    assert _create(4799, 16, psf, dtype=2)[0] == -2
 
 
 @pytest.mark.parametrize("bad", ["neg", "nan", "inf", "sum"])

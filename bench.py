@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-tune", action="store_true", help="skip the plan autotuner")
     return ap.parse_args()
 
 
@@ -114,6 +115,10 @@ def main():
     plan, f, g, F, H, E, p = make_inputs(torch, P, a.dtype)
     n = p["n"]
     stream = torch.cuda.current_stream()
+    tuned_us = plan.ar_plan_autotune() if not a.no_tune else None
+    tuning = {k: plan.ar_plan_get_tune(v) for k, v in
+              [("row_waves", P.AR_TUNE_ROW_WAVES), ("col_waves", P.AR_TUNE_COL_WAVES),
+               ("row_excl", P.AR_TUNE_ROW_EXCL), ("col_excl", P.AR_TUNE_COL_EXCL)]}
     x = torch.zeros_like(g)
 
     # warm-up (untimed)
@@ -177,6 +182,7 @@ def main():
                     "plain_best_rre": float(np.min(rre_p)) if rre_p is not None else None,
                     "plain_run_s": round(plain_s, 5),
                     "final_resnorm": float(res[-1]) if res is not None else None},
+        "tuning": dict(tuning, precond_us=tuned_us),
         "roofline": roof,
         "cpu_baseline": cpu,
     }

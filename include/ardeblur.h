@@ -156,6 +156,28 @@ int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters, double tau
                       double *resnorm_host, double *rre_host, int *best_it_host,
                       void *stream);
 
+/* Launch tunables of a plan (they change speed, never results).
+ *  AR_TUNE_ROW_WAVES / AR_TUNE_COL_WAVES : rows (columns) transformed per
+ *      workgroup by the wave-per-sequence transform, 1, 2 or 4 (0 = auto)
+ *  AR_TUNE_ROW_EXCL / AR_TUNE_COL_EXCL   : 1 = reserve a whole CU per
+ *      workgroup of that pass (spreads few workgroups over all CUs)     */
+enum ar_tune_key { AR_TUNE_ROW_WAVES = 0, AR_TUNE_COL_WAVES = 1, AR_TUNE_ROW_EXCL = 2,
+                   AR_TUNE_COL_EXCL = 3 };
+
+/* Set one tunable (value 0 restores the automatic choice).  Errors:
+ * AR_EINVAL for an unknown key or value. */
+int ar_plan_tune(ar_plan_t p, int key, int value);
+
+/* Read a tunable's current value into *value. */
+int ar_plan_get_tune(ar_plan_t p, int key, int *value);
+
+/* Autotuner: times every candidate setting of the tunables on this plan's
+ * own scratch buffers with HIP events on `stream` (the kernels of one
+ * preconditioner application), keeps the fastest, and returns the best
+ * measured time of that application in *best_us (may be NULL).  Uses and
+ * overwrites the plan's scratch; synchronizes `stream`. */
+int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream);
+
 /* Thread-local message describing the last failure ("" if none). */
 const char *ar_last_error(void);
 

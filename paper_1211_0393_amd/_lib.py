@@ -21,6 +21,7 @@ AR_F32, AR_F64, AR_F32_ACC64 = 0, 1, 2
 DTYPES = {"f32": AR_F32, "f64": AR_F64, "f32x": AR_F32_ACC64}
 AR_REBLUR, AR_ADJOINT = 0, 1
 AR_FILTER_TIKHONOV, AR_FILTER_THRESHOLD, AR_FILTER_IDENTITY = 0, 1, 3
+AR_TUNE_ROW_WAVES, AR_TUNE_COL_WAVES, AR_TUNE_ROW_EXCL, AR_TUNE_COL_EXCL = 0, 1, 2, 3
 
 STATUS = {
     0: "AR_OK", -1: "AR_EINVAL", -2: "AR_ESHAPE", -3: "AR_EPSF", -4: "AR_EALIAS",
@@ -42,6 +43,9 @@ SIGNATURES = [
     ("ar_precond_solve", _I, [_VP, _VP, _VP, _VP]),
     ("ar_deblur_iterate", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _VP,
                                C.POINTER(_D), C.POINTER(_D), C.POINTER(_I), _VP]),
+    ("ar_plan_tune", _I, [_VP, _I, _I]),
+    ("ar_plan_get_tune", _I, [_VP, _I, C.POINTER(_I)]),
+    ("ar_plan_autotune", _I, [_VP, C.POINTER(_D), _VP]),
     ("ar_last_error", C.c_char_p, []),
     ("ar_version", C.c_char_p, []),
 ]
@@ -128,6 +132,20 @@ class Plan:
         self.close()
 
     # --- entry points -------------------------------------------------
+    def ar_plan_tune(self, key, value):
+        _check(load().ar_plan_tune(self._h, int(key), int(value)))
+
+    def ar_plan_get_tune(self, key):
+        v = C.c_int(0)
+        _check(load().ar_plan_get_tune(self._h, int(key), C.byref(v)))
+        return v.value
+
+    def ar_plan_autotune(self, stream=None):
+        """Pick the fastest launch tunables; returns the best time in us."""
+        us = C.c_double(0.0)
+        _check(load().ar_plan_autotune(self._h, C.byref(us), _stream(stream)))
+        return us.value
+
     def ar_blur_apply(self, x, y, stream=None):
         _check(load().ar_blur_apply(self._h, _ptr(x), _ptr(y), _stream(stream)))
         return y

@@ -35,37 +35,44 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
   return start + i;
 }
 
-// AR extension rule along one axis: position i of an axis of length n maps
-// to w0 * f[i0] + w1 * f[i1] (w1 == 0 for an interior position).  Positions
-// beyond one halo width are never consumed by a stored output; they read 0.
-struct Rule { int i0, i1; float w0, w1; };
+// AR extension rule along one axis, branch-free: position i of an axis of
+// length n maps to w0 * f[i0] + w1 * f[i1]: interior (i, 1) + (i, 0);
+// before the start (0, 2) + (-i, -1) (f_{1-t} = 2 f_1 - f_{1+t}); past the
+// end (n-1, 2) + (2n-2-i, -1) (f_{n+t} = 2 f_n - f_{n-t}).  `dead` marks
+// positions that no stored output consumes (more than q outside) or, with
+// zero extension, any position outside the image; they read exactly 0.
+struct Rule { int i0, i1; float w0, w1; bool dead; };
 
-__device__ __forceinline__ Rule ar_rule(int i, int n, int q) {
+__device__ __forceinline__ Rule ar_rule(int i, int n, int q, bool zero_ext) {
   Rule r;
-  if (i >= 0 && i < n) { r.i0 = i; r.i1 = i; r.w0 = 1.f; r.w1 = 0.f; }
-  else if (i < 0 && i >= -q) { r.i0 = 0; r.i1 = -i; r.w0 = 2.f; r.w1 = -1.f; }        // f_{1-t} = 2 f_1 - f_{1+t}
-  else if (i >= n && i <= n - 1 + q) { r.i0 = n - 1; r.i1 = 2 * n - 2 - i; r.w0 = 2.f; r.w1 = -1.f; }  // f_{n+t} = 2 f_n - f_{n-t}
-  else { r.i0 = 0; r.i1 = 0; r.w0 = 0.f; r.w1 = 0.f; }
+  const bool lo = i < 0, hi = i > n - 1;
+  r.dead = (i < -q) | (i > n - 1 + q) | (zero_ext & (lo | hi));
+  r.i0 = lo ? 0 : (hi ? n - 1 : i);
+  r.i1 = lo ? -i : (hi ? 2 * n - 2 - i : i);
+  r.w0 = (lo | hi) ? 2.f : 1.f;
+  r.w1 = (lo | hi) ? -1.f : 0.f;
+  // keep every address inside the image (the value is discarded when dead)
+  r.i0 = r.i0 < 0 ? 0 : (r.i0 > n - 1 ? n - 1 : r.i0);
+  r.i1 = r.i1 < 0 ? 0 : (r.i1 > n - 1 ? n - 1 : r.i1);
   return r;
 }
 
-// Value of the extended image at (i, j), computed in the compute type T
-// from storage-type pixels.
+// Value of the extended image at (i, j) in the compute type T from
+// storage-type pixels: the tensor product of the two 1-D rules (one, two or
+// four distinct terms; corners give the double anti-reflection 4, -2, -2, 1).
+// All four loads are unconditional so a caller can batch them.
 template <typename T, typename TS>
 __device__ __forceinline__ T load_ext(const TS *__restrict__ in, int n1, int n2, int q1, int q2,
                                       int i, int j, bool zero_ext) {
-  if (i >= 0 && i < n1 && j >= 0 && j < n2) return T(in[(size_t)i * n2 + j]);
-  if (zero_ext) return T(0);
-  const Rule a = ar_rule(i, n1, q1), b = ar_rule(j, n2, q2);
-  if (a.w0 == 0.f || b.w0 == 0.f) return T(0);
-  // tensor product of the two 1-D rules: one, two or four terms
-  T v = T(a.w0) * (T(b.w0) * T(in[(size_t)a.i0 * n2 + b.i0]));
-  if (b.w1 != 0.f) v += T(a.w0) * (T(b.w1) * T(in[(size_t)a.i0 * n2 + b.i1]));
-  if (a.w1 != 0.f) {
-    v += T(a.w1) * (T(b.w0) * T(in[(size_t)a.i1 * n2 + b.i0]));
-    if (b.w1 != 0.f) v += T(a.w1) * (T(b.w1) * T(in[(size_t)a.i1 * n2 + b.i1]));
-  }
-  return v;
+  const Rule a = ar_rule(i, n1, q1, zero_ext), b = ar_rule(j, n2, q2, zero_ext);
+  const T x00 = T(in[(size_t)a.i0 * n2 + b.i0]);
+  const T x01 = T(in[(size_t)a.i0 * n2 + b.i1]);
+  const T x10 = T(in[(size_t)a.i1 * n2 + b.i0]);
+  const T x11 = T(in[(size_t)a.i1 * n2 + b.i1]);
+  // a term with a zero weight repeats the pixel of a weighted term (i1 == i0
+  // there), so evaluating it unconditionally adds an exact zero
+  const T v = T(a.w0) * (T(b.w0) * x00 + T(b.w1) * x01) + T(a.w1) * (T(b.w0) * x10 + T(b.w1) * x11);
+  return (a.dead | b.dead) ? T(0) : v;
 }
 
 template <typename T>
@@ -108,17 +115,47 @@ __global__ __launch_bounds__(NT) void conv_kernel(
   const int ib1 = o1 + r0 - q1, ib2 = o2 + c0 - q2;
   const int tid = threadIdx.x;
   const bool inside = ib1 >= 0 && ib2 >= 0 && ib1 + LH <= n1 && ib2 + LW <= n2;
-  // stage the halo tile: 4 rows x 64 columns of threads per sweep
+  // stage the halo tile: 4 rows x 64 columns of threads per sweep; each
+  // thread first loads a chunk of its elements into registers (clamped,
+  // unconditional addresses) and then stores them, so a chunk costs one
+  // memory latency instead of one per element
   const int lr = tid >> 6, lc = tid & 63;
-  if (inside) {
-    for (int a = lr; a < LH; a += NT / 64) {
-      const TS *src = in + (size_t)(ib1 + a) * n2 + ib2;
-      for (int c = lc; c < LW; c += 64) tile[a * pitch + c] = T(src[c]);
+  constexpr int CR = 8, CC = 2;  // rows x column-sweeps per chunk
+  for (int a0 = lr; a0 < LH; a0 += 4 * CR) {
+    for (int c0 = lc; c0 < LW; c0 += 64 * CC) {
+      T vals[CR][CC];
+      if (inside) {
+#pragma unroll
+        for (int i = 0; i < CR; ++i) {
+          const int a = a0 + 4 * i < LH ? a0 + 4 * i : a0;
+          const TS *src = in + (size_t)(ib1 + a) * n2 + ib2;
+#pragma unroll
+          for (int j = 0; j < CC; ++j) {
+            const int c = c0 + 64 * j < LW ? c0 + 64 * j : c0;
+            vals[i][j] = T(src[c]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < CR; ++i)
+#pragma unroll
+          for (int j = 0; j < CC; ++j)
+            vals[i][j] = load_ext<T, TS>(in, n1, n2, q1, q2, ib1 + a0 + 4 * i, ib2 + c0 + 64 * j,
+                                         zero_ext != 0);
+      }
+#pragma unroll
+      for (int i = 0; i < CR; ++i)
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+          const int a = a0 + 4 * i, c = c0 + 64 * j;
+          if (a < LH && c < LW) tile[a * pitch + c] = vals[i][j];
+        }
     }
-  } else {
-    for (int a = lr; a < LH; a += NT / 64)
-      for (int c = lc; c < LW; c += 64)
-        tile[a * pitch + c] = load_ext<T, TS>(in, n1, n2, q1, q2, ib1 + a, ib2 + c, zero_ext != 0);
+  }
+  if constexpr (!GEN) {
+    T *swr = tile + (size_t)LH * pitch;
+    const int P = (2 * q1 + 1) * KW;
+    for (int e = tid; e < P; e += NT) swr[e] = w[e];
   }
   __syncthreads();
 
@@ -130,31 +167,53 @@ __global__ __launch_bounds__(NT) void conv_kernel(
 
   const int krows = 2 * q1 + 2;
   if constexpr (!GEN) {
+    // Software-pipelined sliding window: input row k feeds output row 0
+    // with PSF row k and output row 1 with PSF row k - 1.  The next input
+    // row and PSF row (broadcast reads of the LDS weight copy) are issued
+    // before the current row's FMAs; indices are clamped, not branched.
     constexpr int KWc = 2 * Q2 + 1;
     constexpr int NV = RX + 2 * Q2;
+    const T *sw = tile + (size_t)LH * pitch;
+    const int klast = 2 * q1;
+    T vcur[NV], wcur[KWc], wprev[KWc];
+    {
+      const T *rowp = tile + ly * pitch + lx;
+#pragma unroll
+      for (int t = 0; t < NV; ++t) vcur[t] = rowp[t];
+#pragma unroll
+      for (int b = 0; b < KWc; ++b) {
+        wcur[b] = sw[b];
+        wprev[b] = T(0);
+      }
+    }
     for (int k = 0; k < krows; ++k) {
-      const T *rowp = tile + (ly + k) * pitch + lx;
-      T v[NV];
+      const int kn = k + 1 < krows ? k + 1 : k;
+      const int wn = k + 1 <= klast ? k + 1 : klast;
+      T vnext[NV], wnext[KWc];
+      const T *rowp = tile + (ly + kn) * pitch + lx;
 #pragma unroll
-      for (int t = 0; t < NV; ++t) v[t] = rowp[t];
-      if (k <= 2 * q1) {
-        const T *wr = w + k * KWc;
+      for (int t = 0; t < NV; ++t) vnext[t] = rowp[t];
 #pragma unroll
-        for (int b = 0; b < KWc; ++b) {
-          const T wb = wr[b];
+      for (int b = 0; b < KWc; ++b) wnext[b] = sw[wn * KWc + b];
+      if (k <= klast) {
 #pragma unroll
-          for (int c = 0; c < RX; ++c) acc0[c] = fma(wb, v[c + b], acc0[c]);
-        }
+        for (int b = 0; b < KWc; ++b)
+#pragma unroll
+          for (int c = 0; c < RX; ++c) acc0[c] = fma(wcur[b], vcur[c + b], acc0[c]);
       }
       if (k >= 1) {
-        const T *wr = w + (k - 1) * KWc;
 #pragma unroll
-        for (int b = 0; b < KWc; ++b) {
-          const T wb = wr[b];
+        for (int b = 0; b < KWc; ++b)
 #pragma unroll
-          for (int c = 0; c < RX; ++c) acc1[c] = fma(wb, v[c + b], acc1[c]);
-        }
+          for (int c = 0; c < RX; ++c) acc1[c] = fma(wprev[b], vcur[c + b], acc1[c]);
       }
+#pragma unroll
+      for (int b = 0; b < KWc; ++b) {
+        wprev[b] = wcur[b];
+        wcur[b] = wnext[b];
+      }
+#pragma unroll
+      for (int t = 0; t < NV; ++t) vcur[t] = vnext[t];
     }
   } else {
     for (int k = 0; k < krows; ++k) {
@@ -248,17 +307,17 @@ hipError_t launch_conv_t(const ar_plan_s *p, const void *in, void *out, const vo
                          int blocks, int tiles_x, hipStream_t st) {
   const int q1 = p->q1, q2 = p->q2;
   const int LW = TW + 2 * q2, pitch = (LW + 3) & ~3, LH = TH + 2 * q1;
-  size_t smem = (size_t)LH * pitch * sizeof(T);
+  size_t smem = ((size_t)LH * pitch + (size_t)(2 * q1 + 1) * (2 * q2 + 1)) * sizeof(T);
   if (smem < 64 * sizeof(double)) smem = 64 * sizeof(double);
   const TS *ti = static_cast<const TS *>(in);
   TO *to = static_cast<TO *>(out);
   const T *tw = static_cast<const T *>(w);
   const TS *tg = static_cast<const TS *>(g);
   const int ze = zero_ext ? 1 : 0;
-#define AR_CONV_CASE(QQ)                                                                  \
-  case QQ:                                                                                \
-    hipLaunchKernelGGL((conv_kernel<TS, T, TO, QQ>), dim3(blocks), dim3(NT), smem, st, ti, to, tw, \
-                       p->n1, p->n2, q1, q2, o1, o2, m1, m2, ze, tg, partial, tiles_x);   \
+#define AR_CONV_CASE(QQ)                                                                      \
+  case QQ:                                                                                    \
+    hipLaunchKernelGGL((conv_kernel<TS, T, TO, QQ>), dim3(blocks), dim3(NT), smem, st, ti, to, \
+                       tw, p->n1, p->n2, q1, q2, o1, o2, m1, m2, ze, tg, partial, tiles_x);   \
     break;
   switch (q2) {
     AR_CONV_CASE(0) AR_CONV_CASE(1) AR_CONV_CASE(2) AR_CONV_CASE(3) AR_CONV_CASE(4)
@@ -286,7 +345,8 @@ int conv_launch(const ar_plan_s *p, const void *in, void *out, const void *w, in
   const int tiles_x = (m2 + TW - 1) / TW;
   const int blocks = conv_blocks(p, m1, m2);
   const size_t LH = TH + 2 * (size_t)p->q1, LW = TW + 2 * (size_t)p->q2;
-  if (LH * ((LW + 3) & ~(size_t)3) * p->csize > 64 * 1024)
+  if ((LH * ((LW + 3) & ~(size_t)3) + (2 * (size_t)p->q1 + 1) * (2 * p->q2 + 1)) * p->csize >
+      64 * 1024)
     return fail(AR_EUNSUPPORTED, "PSF too large for the LDS halo tile");
   if (nblocks_out) *nblocks_out = blocks;
   hipError_t e;

@@ -20,119 +20,13 @@
 #include <cmath>
 #include <vector>
 
+#include "ar_codelets.h"
 #include "ar_internal.h"
 
 namespace ar {
 namespace {
 
-// ----------------------------------------------- compile-time roots of unity
-
-constexpr double kPi = 3.141592653589793238462643383279502884;
-
-constexpr double sin_taylor(double x) {
-  double x2 = x * x, term = x, s = x;
-  for (int k = 1; k < 14; ++k) {
-    term *= -x2 / double((2 * k) * (2 * k + 1));
-    s += term;
-  }
-  return s;
-}
-constexpr double cos_taylor(double x) {
-  double x2 = x * x, term = 1.0, s = 1.0;
-  for (int k = 1; k < 14; ++k) {
-    term *= -x2 / double((2 * k - 1) * (2 * k));
-    s += term;
-  }
-  return s;
-}
-// cos(2 pi num / den) with exact reduction to the first octant.
-constexpr double cos2pi(long num, long den) {
-  num %= den;
-  if (num < 0) num += den;
-  const long q = (4 * num) / den, rem = 4 * num - q * den;
-  double c = 0, s = 0;
-  if (2 * rem <= den) {
-    const double th = (kPi / 2) * double(rem) / double(den);
-    c = cos_taylor(th);
-    s = sin_taylor(th);
-  } else {
-    const double th = (kPi / 2) * double(den - rem) / double(den);
-    c = sin_taylor(th);
-    s = cos_taylor(th);
-  }
-  return q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
-}
-constexpr double sin2pi(long num, long den) { return cos2pi(4 * num - den, 4 * den); }
-
-template <typename F, int... I>
-__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-// ----------------------------------------------------------- DFT codelets
-
-// In-place forward DFT of odd length R: pairs v_j and v_{R-j} so that each
-// output pair (k, R-k) needs (R-1)/2 real-by-complex products for the
-// cosine part and as many for the sine part.
-template <int R, typename T>
-__device__ __forceinline__ void dft_odd(V2<T> (&v)[R]) {
-  constexpr int H = (R - 1) / 2;
-  V2<T> a[H], b[H];
-  static_for<H>([&](auto J) {
-    constexpr int j = J + 1;
-    a[J] = cadd(v[j], v[R - j]);
-    b[J] = csub(v[j], v[R - j]);
-  });
-  const V2<T> v0 = v[0];
-  V2<T> s0 = v0;
-  static_for<H>([&](auto J) { s0 = cadd(s0, a[J]); });
-  v[0] = s0;
-  static_for<H>([&](auto K) {
-    constexpr int k = K + 1;
-    V2<T> C = v0, S{T(0), T(0)};
-    static_for<H>([&](auto J) {
-      constexpr int j = J + 1;
-      constexpr int idx = (j * k) % R;
-      constexpr T cv = T(cos2pi(idx, R));
-      constexpr T sv = T(sin2pi(idx, R));
-      C.x = fma(a[J].x, cv, C.x);
-      C.y = fma(a[J].y, cv, C.y);
-      if constexpr (J == 0) {
-        S.x = b[J].x * sv;
-        S.y = b[J].y * sv;
-      } else {
-        S.x = fma(b[J].x, sv, S.x);
-        S.y = fma(b[J].y, sv, S.y);
-      }
-    });
-    // out_k = C - i S, out_{R-k} = C + i S
-    v[k] = {C.x + S.y, C.y - S.x};
-    v[R - k] = {C.x - S.y, C.y + S.x};
-  });
-}
-
-template <int R, typename T>
-__device__ __forceinline__ void dft(V2<T> (&v)[R]) {
-  if constexpr (R == 2) {
-    const V2<T> t = v[0];
-    v[0] = cadd(t, v[1]);
-    v[1] = csub(t, v[1]);
-  } else if constexpr (R == 4) {
-    const V2<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    const V2<T> t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
-    v[0] = cadd(t0, t2);
-    v[2] = csub(t0, t2);
-    v[1] = {t1.x + t3.y, t1.y - t3.x};  // t1 - i t3
-    v[3] = {t1.x - t3.y, t1.y + t3.x};  // t1 + i t3
-  } else {
-    static_assert(R % 2 == 1, "odd radix expected");
-    dft_odd<R, T>(v);
-  }
-}
+using namespace cl;
 
 // ------------------------------------------------------------ FFT stages
 
@@ -308,11 +202,6 @@ __device__ __forceinline__ T dst_value(const V2<T> *__restrict__ U, int es, int 
   return scale * ((C.y - A.y) + cs.x * (A.x - C.x) + cs.y * (A.y + C.y));
 }
 
-__device__ __forceinline__ int xcd_remap(int b, int G) {
-  const int x = b & 7, i = b >> 3;
-  const int g8 = G >> 3, rem = G & 7;
-  return x * g8 + (x < rem ? x : rem) + i;
-}
 
 // ------------------------------------------------------------- row pass
 
@@ -637,10 +526,11 @@ int fft_plan_build(FftPlan &fp, int m, bool cdouble, hipStream_t st) {
   AR_HIP(hipGetLastError());
   AR_HIP(hipStreamSynchronize(st));
   AR_HIP(hipFree(dints));
-  return AR_OK;
+  return wave_plan_build(fp.w, fp.M, cdouble, st);
 }
 
 void fft_plan_free(FftPlan &fp) {
+  wave_plan_free(fp.w);
   if (fp.tw) (void)hipFree(fp.tw);
   if (fp.post) (void)hipFree(fp.post);
   if (fp.gen) (void)hipFree(fp.gen);
@@ -648,6 +538,7 @@ void fft_plan_free(FftPlan &fp) {
 }
 
 int rows_blocks(const ar_plan_s *p) {
+  if (wave_rows_ok(p)) return wave_rows_blocks(p);
   const int B = rows_per_block(p->fft_row.M, p->csize);
   return (p->n1 + B - 1) / B;
 }
@@ -697,6 +588,7 @@ static int rows_launch_t(const ar_plan_s *p, const void *in, void *out, int mode
 int rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                 const void *f_true, double *partial, int *nblocks_out, hipStream_t st) {
   if (nblocks_out) *nblocks_out = rows_blocks(p);
+  if (wave_rows_ok(p)) return wave_rows_launch(p, in, out, mode, tau, f_true, partial, st);
   if (p->dtype == AR_F64)
     return rows_launch_t<double, double>(p, in, out, mode, tau, f_true, partial, st);
   if (p->dtype == AR_F32_ACC64)
@@ -741,6 +633,7 @@ static int cols_launch_t(const ar_plan_s *p, const void *in, void *out, int mode
 }
 
 int cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
+  if (wave_cols_ok(p)) return wave_cols_launch(p, in, out, mode, st);
   if (p->dtype == AR_F64) return cols_launch_t<double, double>(p, in, out, mode, st);
   if (p->dtype == AR_F32_ACC64) return cols_launch_t<float, double>(p, in, out, mode, st);
   return cols_launch_t<float, float>(p, in, out, mode, st);

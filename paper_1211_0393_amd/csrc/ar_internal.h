@@ -45,6 +45,27 @@ __device__ __forceinline__ V2<T> csub(V2<T> a, V2<T> b) { return {a.x - b.x, a.y
 
 constexpr int kMaxStages = 24;
 
+// In-place decimation-in-time plan of the wave-per-sequence engine: stage t
+// combines sub-transforms of length L[t] with radix R[t] (largest radix
+// first); input goes to digit-reversed positions drev[n]; stage twiddles
+// e^{-2 pi i k r / (L R)} sit at tw + tw_off[t] + (r - 1) * L[t] + k.
+struct WavePlan {
+  bool ok = false;
+  int M = 0, nst = 0, twn = 0;
+  int R[kMaxStages] = {};
+  int L[kMaxStages] = {};
+  int tw_off[kMaxStages] = {};
+  void *tw = nullptr;   // V2<T>[]
+  int *drev = nullptr;  // int[M]
+};
+
+struct WDesc {
+  int M, nst, twn;  // twn: total number of twiddles over all stages
+  int R[kMaxStages];
+  int L[kMaxStages];
+  int tw_off[kMaxStages];
+};
+
 // Complex FFT of length M = m - 1 used for the DST-I of length m - 2 along
 // one image axis of length m.  Stage s has radix radix[s]; ns[s] is the
 // product of the radices before it (Stockham stride).  Twiddles are stored
@@ -61,6 +82,7 @@ struct FftPlan {
   void *gen = nullptr;   // V2<T>[]
   void *post = nullptr;  // V2<T>[M+1]: (cos, sin)(pi k / M)
   size_t tw_count = 0, gen_count = 0;
+  WavePlan w;            // wave-per-sequence engine (when every radix has a codelet)
 };
 
 // Device-side view passed to kernels by value.
@@ -101,6 +123,8 @@ struct ar_plan_s {
   size_t scalars_cap = 0;
   int filter = AR_FILTER_TIKHONOV;
   double filter_param = 1e-2;
+  // launch tunables (0 = automatic), set by ar_plan_tune / ar_plan_autotune
+  int tune[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace ar {
@@ -127,6 +151,16 @@ int rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double 
                 const void *f_true, double *partial, int *nblocks_out, hipStream_t st);
 int rows_blocks(const ar_plan_s *p);
 int cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st);
+
+// wave-per-sequence transform engine (ar_xform.hip)
+int wave_plan_build(WavePlan &w, int M, bool cdouble, hipStream_t st);
+void wave_plan_free(WavePlan &w);
+bool wave_rows_ok(const ar_plan_s *p);
+bool wave_cols_ok(const ar_plan_s *p);
+int wave_rows_blocks(const ar_plan_s *p);
+int wave_rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
+                     const void *f_true, double *partial, hipStream_t st);
+int wave_cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st);
 
 // plan-time and helper kernels (ar_plan.hip)
 int spectrum_launch(ar_plan_s *p, hipStream_t st);

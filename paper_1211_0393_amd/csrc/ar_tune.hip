@@ -1,0 +1,110 @@
+// Launch tunables and the autotuner of a plan (gfx950).
+//
+// The autotuner times each candidate setting of the transform launch
+// tunables (waves per workgroup, CU-exclusive workgroups) on the plan's
+// own scratch with HIP events, and keeps the fastest.  Settings change the
+// launch geometry only; every setting computes the same result.
+#include <cfloat>
+#include <vector>
+
+#include "ar_internal.h"
+
+using namespace ar;
+
+static bool tune_valid(int key, int value) {
+  switch (key) {
+    case AR_TUNE_ROW_WAVES:
+    case AR_TUNE_COL_WAVES:
+      return value == 0 || value == 1 || value == 2 || value == 4;
+    case AR_TUNE_ROW_EXCL:
+    case AR_TUNE_COL_EXCL:
+      return value == 0 || value == 1;
+    default:
+      return false;
+  }
+}
+
+extern "C" int ar_plan_tune(ar_plan_t p, int key, int value) {
+  if (!p) return fail(AR_EINVAL, "ar_plan_tune: null plan");
+  if (!tune_valid(key, value)) return fail(AR_EINVAL, "ar_plan_tune: bad key or value");
+  p->tune[key] = value;
+  return AR_OK;
+}
+
+extern "C" int ar_plan_get_tune(ar_plan_t p, int key, int *value) {
+  if (!p || !value) return fail(AR_EINVAL, "ar_plan_get_tune: null argument");
+  if (key < 0 || key > AR_TUNE_COL_EXCL) return fail(AR_EINVAL, "ar_plan_get_tune: bad key");
+  *value = p->tune[key];
+  return AR_OK;
+}
+
+namespace {
+
+// Average time (us) of `reps` runs of fn after two warm-up runs.
+template <typename F>
+int time_us(F &&fn, hipStream_t st, int reps, double *us) {
+  hipEvent_t a, b;
+  AR_HIP(hipEventCreate(&a));
+  AR_HIP(hipEventCreate(&b));
+  int rc = AR_OK;
+  for (int i = 0; i < 2 && rc == AR_OK; ++i) rc = fn();
+  if (rc == AR_OK) {
+    (void)hipEventRecord(a, st);
+    for (int i = 0; i < reps && rc == AR_OK; ++i) rc = fn();
+    (void)hipEventRecord(b, st);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    *us = 1e3 * ms / reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
+  if (!p) return fail(AR_EINVAL, "ar_plan_autotune: null plan");
+  AR_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t bytes = (size_t)p->n1 * p->n2 * p->esize;
+  AR_HIP(hipMemsetAsync(p->y, 0, bytes, st));
+  const int reps = 5;
+  const int waves[3] = {1, 2, 4};
+  // rows: forward and inverse pass
+  double best_r = DBL_MAX;
+  int br_w = 0, br_x = 0;
+  for (int w : waves)
+    for (int x = 0; x < 2; ++x) {
+      p->tune[AR_TUNE_ROW_WAVES] = w;
+      p->tune[AR_TUNE_ROW_EXCL] = x;
+      double us = 0;
+      int rc = time_us(
+          [&]() {
+            int r = rows_launch(p, p->y, p->c, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
+            return r != AR_OK ? r : rows_launch(p, p->c, p->r, ROW_INV, 0.0, nullptr, nullptr, nullptr, st);
+          },
+          st, reps, &us);
+      if (rc != AR_OK) return rc;
+      if (us < best_r) { best_r = us; br_w = w; br_x = x; }
+    }
+  p->tune[AR_TUNE_ROW_WAVES] = br_w;
+  p->tune[AR_TUNE_ROW_EXCL] = br_x;
+  // columns: the fused forward / filter / inverse pass
+  double best_c = DBL_MAX;
+  int bc_w = 0, bc_x = 0;
+  for (int w : waves)
+    for (int x = 0; x < 2; ++x) {
+      p->tune[AR_TUNE_COL_WAVES] = w;
+      p->tune[AR_TUNE_COL_EXCL] = x;
+      double us = 0;
+      int rc = time_us([&]() { return cols_launch(p, p->c, p->c, COL_FWD_D_INV, st); }, st, reps, &us);
+      if (rc != AR_OK) return rc;
+      if (us < best_c) { best_c = us; bc_w = w; bc_x = x; }
+    }
+  p->tune[AR_TUNE_COL_WAVES] = bc_w;
+  p->tune[AR_TUNE_COL_EXCL] = bc_x;
+  if (best_us) *best_us = best_r + best_c;
+  return AR_OK;
+}

@@ -101,6 +101,9 @@ def test_bad_dtype_and_null_arguments():
     assert lib.ar_eigenvalues(None, None, None) == -1
     assert lib.ar_filter_values(None, None, None) == -1
     assert lib.ar_deblur_iterate(None, None, None, 1, 1.0, 0, 1, None, None, None, None, None) == -1
+    assert lib.ar_plan_tune(None, 0, 1) == -1
+    assert lib.ar_plan_get_tune(None, 0, None) == -1
+    assert lib.ar_plan_autotune(None, None, None) == -1
     assert lib.ar_plan_destroy(None) == 0
     assert "null" in lib.ar_last_error().decode().lower()
 

@@ -354,3 +354,33 @@ def test_batch_sizes_transform_and_blur():
             plan.ar_precond_solve(x, y)
             d = O.tikhonov(O.eigenvalues(H, n, n), prm["alpha"])
             assert rel(host(y), O.precond_apply(X, d)) <= 2e-5
+
+
+@pytest.mark.parametrize("dt", ["f32", "f32x"])
+def test_tunables_do_not_change_results(dt):
+    """Every launch setting of the transform engine gives bitwise the same
+    preconditioner output; the autotuner picks one of them."""
+    n1, n2 = 300, 256          # n2 - 1 = 255 = 3 * 5 * 17: wave engine on rows
+    H = synth.psf_random(3, 4, seed=2)
+    Y = np.random.default_rng(1).standard_normal((n1, n2))
+    with P.Plan(n1, n2, H, dtype=dt) as plan:
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, 1e-2)
+        y = dev(Y, TDT[dt])
+        z = torch.empty_like(y)
+        plan.ar_precond_solve(y, z)
+        ref = host(z)
+        for w in (1, 2, 4):
+            for x in (0, 1):
+                for key_w, key_x in ((P.AR_TUNE_ROW_WAVES, P.AR_TUNE_ROW_EXCL),
+                                     (P.AR_TUNE_COL_WAVES, P.AR_TUNE_COL_EXCL)):
+                    plan.ar_plan_tune(key_w, w)
+                    plan.ar_plan_tune(key_x, x)
+                    plan.ar_precond_solve(y, z)
+                    assert np.array_equal(host(z), ref)
+        us = plan.ar_plan_autotune()
+        assert us > 0
+        assert plan.ar_plan_get_tune(P.AR_TUNE_ROW_WAVES) in (1, 2, 4)
+        plan.ar_precond_solve(y, z)
+        assert np.array_equal(host(z), ref)
+        with pytest.raises(P.ArError):
+            plan.ar_plan_tune(P.AR_TUNE_ROW_WAVES, 3)

@@ -65,19 +65,12 @@ def make_inputs(torch, P, dt):
     return plan, f, g, F, H, E, p
 
 
-def time_kernel(torch, fn, reps, stream):
-    """Average duration (s) of one launch of `fn` over `reps` launches,
-    from HIP events recorded on the launch stream."""
-    s = torch.cuda.Event(enable_timing=True)
-    t = torch.cuda.Event(enable_timing=True)
-    for _ in range(5):
-        fn()
-    s.record(stream)
-    for _ in range(reps):
-        fn()
-    t.record(stream)
-    t.synchronize()
-    return s.elapsed_time(t) / 1e3 / reps
+def finite_min(v):
+    if v is None:
+        return None
+    v = np.asarray(v)
+    v = v[np.isfinite(v)]
+    return float(v.min()) if v.size else None
 
 
 def cpu_baseline(F, H, E, p, iters):
@@ -148,17 +141,34 @@ def main():
                                                     f_true=f, want_rre=True)
     plain_s = time.perf_counter() - t1
 
-    # dominant kernel: the AR blur (two launches per step), timed alone
-    y = torch.empty_like(g)
-    t_conv = time_kernel(torch, lambda: plan.ar_blur_apply(x, y), a.kernel_reps, stream)
+    # per-kernel durations of one step (HIP events on this stream), and the
+    # roofline of the dominant kernel with its algorithmic work per launch
+    phase_us = plan.ar_iterate_profile(g, x, reps=a.kernel_reps)
     P_taps = (2 * plan.q1 + 1) * (2 * plan.q2 + 1)
-    flops = 2.0 * P_taps * n * n                        # one FMA per tap and pixel
-    achieved = flops / t_conv / 1e12
-    roof = {"bound": "alu", "kernel": "conv_kernel (A x, 15x15 taps, 1024x1024)",
-            "achieved": round(achieved, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
-            "kernel_us": round(t_conv * 1e6, 2),
-            "hbm_frac_of_step": round(n * n * 36 / t_step / 1e9 / HBM_PEAK_GBS, 4)}
+    npx = n * n
+    es = 4                                           # FP32 images
+    ds = 8 if a.dtype == "f32x" else 4               # filter in the compute type
+    phases = [
+        ("residual blur r = g - A x", "alu", 2.0 * P_taps * npx, 3 * es * npx),
+        ("reblur y = A' r", "alu", 2.0 * P_taps * npx, 2 * es * npx),
+        ("row pass of T~", "hbm", None, 2 * es * npx),
+        ("column pass T~, d, T", "hbm", None, (2 * es + ds) * npx),
+        ("row pass of T + update", "hbm", None, 3 * es * npx),
+    ]
+    rooflines = []
+    for (name, bound, flops, nbytes), us in zip(phases, phase_us):
+        t = us * 1e-6
+        if bound == "alu":
+            ach, peak, unit = flops / t / 1e12, VALU_PEAK_TFLOPS, "TFLOP/s"
+        else:
+            ach, peak, unit = nbytes / t / 1e9, HBM_PEAK_GBS, "GB/s"
+        rooflines.append({"kernel": name, "bound": bound, "achieved": round(ach, 2), "peak": peak,
+                          "unit": unit, "frac": round(ach / peak, 4), "traffic": None,
+                          "kernel_us": round(us, 2),
+                          "algorithmic": {"flops": flops, "bytes": nbytes}})
+    dom = int(np.argmax(phase_us))
+    roof = dict(rooflines[dom])
+    roof["hbm_frac_of_step"] = round(npx * 36 / t_step / 1e9 / HBM_PEAK_GBS, 4)
 
     cpu = None
     if not a.no_cpu and int(os.environ.get("RANK", "0")) == 0:
@@ -177,16 +187,16 @@ def main():
                    "n1": n, "n2": n, "psf": [15, 15], "alpha": p["alpha"],
                    "iterations": a.steps, "parallelism": "single GPU"},
         "status": rc,
-        "quality": {"best_it": best, "best_rre": float(np.min(rre)) if rre is not None else None,
-                    "plain_best_it": best_p,
-                    "plain_best_rre": float(np.min(rre_p)) if rre_p is not None else None,
+        "quality": {"best_it": best, "best_rre": finite_min(rre),
+                    "plain_best_it": best_p, "plain_best_rre": finite_min(rre_p),
                     "plain_run_s": round(plain_s, 5),
-                    "final_resnorm": float(res[-1]) if res is not None else None},
+                    "diverged": bool(res is not None and not np.all(np.isfinite(res)))},
         "tuning": dict(tuning, precond_us=tuned_us),
         "roofline": roof,
+        "kernels": rooflines,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, allow_nan=False), flush=True)
     plan.close()
     return 0
 

@@ -178,6 +178,20 @@ int ar_plan_get_tune(ar_plan_t p, int key, int *value);
  * overwrites the plan's scratch; synchronizes `stream`. */
 int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream);
 
+/* Phase profiler of one (D-)Landweber iteration: runs `reps` iterations on
+ * copies of the plan's scratch (x and g are read, x is left unchanged) and
+ * records HIP events on `stream` around each kernel, returning the average
+ * duration in microseconds of each phase in phase_us[0..4]:
+ *   0: r = g - A x (residual blur with FP64 norm partials)
+ *   1: y = A' r or A^T r (transpose blur; correlation + fold for A^T)
+ *   2: row pass of T~ (0 when precondition == 0)
+ *   3: column pass T~ / d / T (0 when precondition == 0)
+ *   4: row pass of T fused with x += tau w (the plain update when
+ *      precondition == 0)
+ * x, g: device, plan dtype; reps >= 1. */
+int ar_iterate_profile(ar_plan_t p, const void *g, const void *x, int tmode, int precondition,
+                       int reps, double *phase_us, void *stream);
+
 /* Thread-local message describing the last failure ("" if none). */
 const char *ar_last_error(void);
 

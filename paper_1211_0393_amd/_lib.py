@@ -46,6 +46,7 @@ SIGNATURES = [
     ("ar_plan_tune", _I, [_VP, _I, _I]),
     ("ar_plan_get_tune", _I, [_VP, _I, C.POINTER(_I)]),
     ("ar_plan_autotune", _I, [_VP, C.POINTER(_D), _VP]),
+    ("ar_iterate_profile", _I, [_VP, _VP, _VP, _I, _I, _I, C.POINTER(_D), _VP]),
     ("ar_last_error", C.c_char_p, []),
     ("ar_version", C.c_char_p, []),
 ]
@@ -145,6 +146,14 @@ class Plan:
         us = C.c_double(0.0)
         _check(load().ar_plan_autotune(self._h, C.byref(us), _stream(stream)))
         return us.value
+
+    def ar_iterate_profile(self, g, x, tmode=AR_REBLUR, precondition=True, reps=20, stream=None):
+        """Average microseconds of the five kernels of one iteration."""
+        us = (C.c_double * 5)()
+        _check(load().ar_iterate_profile(self._h, _ptr(g), _ptr(x), int(tmode),
+                                         int(bool(precondition)), int(reps),
+                                         C.cast(us, C.POINTER(C.c_double)), _stream(stream)))
+        return list(us)
 
     def ar_blur_apply(self, x, y, stream=None):
         _check(load().ar_blur_apply(self._h, _ptr(x), _ptr(y), _stream(stream)))

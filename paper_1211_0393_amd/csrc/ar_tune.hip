@@ -108,3 +108,59 @@ extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
   if (best_us) *best_us = best_r + best_c;
   return AR_OK;
 }
+
+extern "C" int ar_iterate_profile(ar_plan_t p, const void *g, const void *x, int tmode,
+                                  int precondition, int reps, double *phase_us, void *stream) {
+  if (!p || !g || !x || !phase_us) return fail(AR_EINVAL, "ar_iterate_profile: null argument");
+  if (reps < 1) return fail(AR_EINVAL, "ar_iterate_profile: reps < 1");
+  if (tmode != AR_REBLUR && tmode != AR_ADJOINT)
+    return fail(AR_EINVAL, "ar_iterate_profile: unknown tmode");
+  AR_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t bytes = (size_t)p->n1 * p->n2 * p->esize;
+  // work on a private copy of x so the caller's iterate is untouched
+  void *xw = nullptr;
+  AR_HIP(hipMalloc(&xw, bytes));
+  AR_HIP(hipMemcpyAsync(xw, x, bytes, hipMemcpyDeviceToDevice, st));
+  hipEvent_t ev[6];
+  for (auto &e : ev) AR_HIP(hipEventCreate(&e));
+  double acc[5] = {0, 0, 0, 0, 0};
+  int rc = AR_OK;
+  for (int it = -1; it < reps && rc == AR_OK; ++it) {  // it = -1: warm-up
+    (void)hipEventRecord(ev[0], st);
+    rc = conv_launch(p, xw, p->r, p->w_fwd, 0, 0, p->n1, p->n2, false, g, nullptr, nullptr, st);
+    (void)hipEventRecord(ev[1], st);
+    if (rc == AR_OK) {
+      if (tmode == AR_REBLUR) {
+        rc = conv_launch(p, p->r, p->y, p->w_rev, 0, 0, p->n1, p->n2, false, nullptr, nullptr,
+                         nullptr, st);
+      } else {
+        rc = conv_launch(p, p->r, p->ext, p->w_rev, -p->q1, -p->q2, p->n1 + 2 * p->q1,
+                         p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st, true);
+        if (rc == AR_OK) rc = fold_launch(p, p->ext, p->y, st);
+      }
+    }
+    (void)hipEventRecord(ev[2], st);
+    if (rc == AR_OK && precondition)
+      rc = rows_launch(p, p->y, p->c, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
+    (void)hipEventRecord(ev[3], st);
+    if (rc == AR_OK && precondition) rc = cols_launch(p, p->c, p->c, COL_FWD_D_INV, st);
+    (void)hipEventRecord(ev[4], st);
+    if (rc == AR_OK)
+      rc = precondition ? rows_launch(p, p->c, xw, ROW_INV_UPDATE, 1.0, nullptr, nullptr, nullptr, st)
+                        : axpy_launch(p, xw, p->y, 1.0, nullptr, nullptr, nullptr, st);
+    (void)hipEventRecord(ev[5], st);
+    (void)hipEventSynchronize(ev[5]);
+    if (it >= 0)
+      for (int k = 0; k < 5; ++k) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+        acc[k] += 1e3 * ms;
+      }
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  (void)hipFree(xw);
+  if (rc != AR_OK) return rc;
+  for (int k = 0; k < 5; ++k) phase_us[k] = acc[k] / reps;
+  return AR_OK;
+}

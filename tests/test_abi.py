@@ -104,6 +104,7 @@ def test_bad_dtype_and_null_arguments():
     assert lib.ar_plan_tune(None, 0, 1) == -1
     assert lib.ar_plan_get_tune(None, 0, None) == -1
     assert lib.ar_plan_autotune(None, None, None) == -1
+    assert lib.ar_iterate_profile(None, None, None, 0, 1, 1, None, None) == -1
     assert lib.ar_plan_destroy(None) == 0
     assert "null" in lib.ar_last_error().decode().lower()
 

@@ -111,7 +111,8 @@ def main():
     tuned_us = plan.ar_plan_autotune() if not a.no_tune else None
     tuning = {k: plan.ar_plan_get_tune(v) for k, v in
               [("row_waves", P.AR_TUNE_ROW_WAVES), ("col_waves", P.AR_TUNE_COL_WAVES),
-               ("row_excl", P.AR_TUNE_ROW_EXCL), ("col_excl", P.AR_TUNE_COL_EXCL)]}
+               ("row_excl", P.AR_TUNE_ROW_EXCL), ("col_excl", P.AR_TUNE_COL_EXCL),
+               ("row_fft", P.AR_TUNE_ROW_ALGO), ("col_fft", P.AR_TUNE_COL_ALGO)]}
     x = torch.zeros_like(g)
 
     # warm-up (untimed)

@@ -160,9 +160,12 @@ int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters, double tau
  *  AR_TUNE_ROW_WAVES / AR_TUNE_COL_WAVES : rows (columns) transformed per
  *      workgroup by the wave-per-sequence transform, 1, 2 or 4 (0 = auto)
  *  AR_TUNE_ROW_EXCL / AR_TUNE_COL_EXCL   : 1 = reserve a whole CU per
- *      workgroup of that pass (spreads few workgroups over all CUs)     */
+ *      workgroup of that pass (spreads few workgroups over all CUs)
+ *  AR_TUNE_ROW_ALGO / AR_TUNE_COL_ALGO   : FFT of the DST-I, 1 = mixed
+ *      radix (only when every prime factor of n - 1 is <= 31), 2 = Bluestein
+ *      chirp-z with a power-of-two FFT (any length); 0 = auto            */
 enum ar_tune_key { AR_TUNE_ROW_WAVES = 0, AR_TUNE_COL_WAVES = 1, AR_TUNE_ROW_EXCL = 2,
-                   AR_TUNE_COL_EXCL = 3 };
+                   AR_TUNE_COL_EXCL = 3, AR_TUNE_ROW_ALGO = 4, AR_TUNE_COL_ALGO = 5 };
 
 /* Set one tunable (value 0 restores the automatic choice).  Errors:
  * AR_EINVAL for an unknown key or value. */

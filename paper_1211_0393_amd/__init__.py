@@ -15,8 +15,10 @@ from ._lib import (  # noqa: F401
     AR_FILTER_THRESHOLD,
     AR_FILTER_TIKHONOV,
     AR_REBLUR,
+    AR_TUNE_COL_ALGO,
     AR_TUNE_COL_EXCL,
     AR_TUNE_COL_WAVES,
+    AR_TUNE_ROW_ALGO,
     AR_TUNE_ROW_EXCL,
     AR_TUNE_ROW_WAVES,
     ArError,

@@ -22,6 +22,7 @@ DTYPES = {"f32": AR_F32, "f64": AR_F64, "f32x": AR_F32_ACC64}
 AR_REBLUR, AR_ADJOINT = 0, 1
 AR_FILTER_TIKHONOV, AR_FILTER_THRESHOLD, AR_FILTER_IDENTITY = 0, 1, 3
 AR_TUNE_ROW_WAVES, AR_TUNE_COL_WAVES, AR_TUNE_ROW_EXCL, AR_TUNE_COL_EXCL = 0, 1, 2, 3
+AR_TUNE_ROW_ALGO, AR_TUNE_COL_ALGO = 4, 5
 
 STATUS = {
     0: "AR_OK", -1: "AR_EINVAL", -2: "AR_ESHAPE", -3: "AR_EPSF", -4: "AR_EALIAS",

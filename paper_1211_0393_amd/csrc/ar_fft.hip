@@ -526,11 +526,14 @@ int fft_plan_build(FftPlan &fp, int m, bool cdouble, hipStream_t st) {
   AR_HIP(hipGetLastError());
   AR_HIP(hipStreamSynchronize(st));
   AR_HIP(hipFree(dints));
-  return wave_plan_build(fp.w, fp.M, cdouble, st);
+  int rc = wave_plan_build(fp.w, fp.M, cdouble, false, st);
+  if (rc != AR_OK) return rc;
+  return wave_plan_build(fp.wb, fp.M, cdouble, true, st);
 }
 
 void fft_plan_free(FftPlan &fp) {
   wave_plan_free(fp.w);
+  wave_plan_free(fp.wb);
   if (fp.tw) (void)hipFree(fp.tw);
   if (fp.post) (void)hipFree(fp.post);
   if (fp.gen) (void)hipFree(fp.gen);

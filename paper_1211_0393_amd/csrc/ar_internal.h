@@ -49,18 +49,25 @@ constexpr int kMaxStages = 24;
 // combines sub-transforms of length L[t] with radix R[t] (largest radix
 // first); input goes to digit-reversed positions drev[n]; stage twiddles
 // e^{-2 pi i k r / (L R)} sit at tw + tw_off[t] + (r - 1) * L[t] + k.
+// Either the FFT of length N = M itself (mixed radix, every radix with a
+// codelet) or Bluestein's chirp-z form: the length-M DFT as a cyclic
+// convolution of power-of-two length N >= 2M - 1 (forward DIT FFT, product
+// with the precomputed spectrum bhat of the chirp, inverse via a DIF FFT of
+// the conjugate), chirp[j] = e^{-i pi j^2 / M}.
 struct WavePlan {
-  bool ok = false;
-  int M = 0, nst = 0, twn = 0;
+  bool ok = false, bs = false;
+  int M = 0, N = 0, nst = 0, twn = 0;
   int R[kMaxStages] = {};
   int L[kMaxStages] = {};
   int tw_off[kMaxStages] = {};
-  void *tw = nullptr;   // V2<T>[]
-  int *drev = nullptr;  // int[M]
+  void *tw = nullptr;     // V2<T>[twn]
+  int *drev = nullptr;    // int[N]
+  void *chirp = nullptr;  // V2<T>[M]   (Bluestein)
+  void *bhat = nullptr;   // V2<T>[N]   (Bluestein; includes 1/N)
 };
 
 struct WDesc {
-  int M, nst, twn;  // twn: total number of twiddles over all stages
+  int M, N, bs, nst, twn;  // twn: total number of twiddles over all stages
   int R[kMaxStages];
   int L[kMaxStages];
   int tw_off[kMaxStages];
@@ -82,7 +89,8 @@ struct FftPlan {
   void *gen = nullptr;   // V2<T>[]
   void *post = nullptr;  // V2<T>[M+1]: (cos, sin)(pi k / M)
   size_t tw_count = 0, gen_count = 0;
-  WavePlan w;            // wave-per-sequence engine (when every radix has a codelet)
+  WavePlan w;            // wave-per-sequence engine, mixed radix (every radix has a codelet)
+  WavePlan wb;           // wave-per-sequence engine, Bluestein (any length)
 };
 
 // Device-side view passed to kernels by value.
@@ -153,11 +161,15 @@ int rows_blocks(const ar_plan_s *p);
 int cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st);
 
 // wave-per-sequence transform engine (ar_xform.hip)
-int wave_plan_build(WavePlan &w, int M, bool cdouble, hipStream_t st);
+int wave_plan_build(WavePlan &w, int M, bool cdouble, bool bluestein, hipStream_t st);
 void wave_plan_free(WavePlan &w);
 bool wave_rows_ok(const ar_plan_s *p);
 bool wave_cols_ok(const ar_plan_s *p);
 int wave_rows_blocks(const ar_plan_s *p);
+// FFT form the wave engine uses for that axis: 1 mixed radix, 2 Bluestein,
+// 0 none (the block-wide engine runs instead)
+int wave_rows_algo(const ar_plan_s *p);
+int wave_cols_algo(const ar_plan_s *p);
 int wave_rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                      const void *f_true, double *partial, hipStream_t st);
 int wave_cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st);

@@ -1,9 +1,10 @@
 // Launch tunables and the autotuner of a plan (gfx950).
 //
-// The autotuner times each candidate setting of the transform launch
-// tunables (waves per workgroup, CU-exclusive workgroups) on the plan's
+// The autotuner times each candidate setting of the transform tunables
+// (FFT form, waves per workgroup, CU-exclusive workgroups) on the plan's
 // own scratch with HIP events, and keeps the fastest.  Settings change the
-// launch geometry only; every setting computes the same result.
+// launch geometry or the FFT factorisation only; every setting computes the
+// same transform (up to rounding).
 #include <cfloat>
 #include <vector>
 
@@ -19,6 +20,9 @@ static bool tune_valid(int key, int value) {
     case AR_TUNE_ROW_EXCL:
     case AR_TUNE_COL_EXCL:
       return value == 0 || value == 1;
+    case AR_TUNE_ROW_ALGO:
+    case AR_TUNE_COL_ALGO:
+      return value == 0 || value == 1 || value == 2;
     default:
       return false;
   }
@@ -33,7 +37,7 @@ extern "C" int ar_plan_tune(ar_plan_t p, int key, int value) {
 
 extern "C" int ar_plan_get_tune(ar_plan_t p, int key, int *value) {
   if (!p || !value) return fail(AR_EINVAL, "ar_plan_get_tune: null argument");
-  if (key < 0 || key > AR_TUNE_COL_EXCL) return fail(AR_EINVAL, "ar_plan_get_tune: bad key");
+  if (key < 0 || key > AR_TUNE_COL_ALGO) return fail(AR_EINVAL, "ar_plan_get_tune: bad key");
   *value = p->tune[key];
   return AR_OK;
 }
@@ -74,37 +78,52 @@ extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
   const int waves[3] = {1, 2, 4};
   // rows: forward and inverse pass
   double best_r = DBL_MAX;
-  int br_w = 0, br_x = 0;
-  for (int w : waves)
-    for (int x = 0; x < 2; ++x) {
-      p->tune[AR_TUNE_ROW_WAVES] = w;
-      p->tune[AR_TUNE_ROW_EXCL] = x;
-      double us = 0;
-      int rc = time_us(
-          [&]() {
-            int r = rows_launch(p, p->y, p->c, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
-            return r != AR_OK ? r : rows_launch(p, p->c, p->r, ROW_INV, 0.0, nullptr, nullptr, nullptr, st);
-          },
-          st, reps, &us);
-      if (rc != AR_OK) return rc;
-      if (us < best_r) { best_r = us; br_w = w; br_x = x; }
-    }
+  int br_a = 0, br_w = 0, br_x = 0;
+  for (int a = 1; a <= 2; ++a) {
+    p->tune[AR_TUNE_ROW_ALGO] = a;
+    if (wave_rows_algo(p) != a) continue;  // that FFT form is not available here
+    for (int w : waves)
+      for (int x = 0; x < 2; ++x) {
+        p->tune[AR_TUNE_ROW_WAVES] = w;
+        p->tune[AR_TUNE_ROW_EXCL] = x;
+        double us = 0;
+        int rc = time_us(
+            [&]() {
+              int r = rows_launch(p, p->y, p->c, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
+              return r != AR_OK ? r
+                                : rows_launch(p, p->c, p->r, ROW_INV, 0.0, nullptr, nullptr,
+                                              nullptr, st);
+            },
+            st, reps, &us);
+        if (rc != AR_OK) return rc;
+        if (us < best_r) { best_r = us; br_a = a; br_w = w; br_x = x; }
+      }
+  }
+  p->tune[AR_TUNE_ROW_ALGO] = br_a;
   p->tune[AR_TUNE_ROW_WAVES] = br_w;
   p->tune[AR_TUNE_ROW_EXCL] = br_x;
+  if (best_r == DBL_MAX) best_r = 0;  // block-wide engine only
   // columns: the fused forward / filter / inverse pass
   double best_c = DBL_MAX;
-  int bc_w = 0, bc_x = 0;
-  for (int w : waves)
-    for (int x = 0; x < 2; ++x) {
-      p->tune[AR_TUNE_COL_WAVES] = w;
-      p->tune[AR_TUNE_COL_EXCL] = x;
-      double us = 0;
-      int rc = time_us([&]() { return cols_launch(p, p->c, p->c, COL_FWD_D_INV, st); }, st, reps, &us);
-      if (rc != AR_OK) return rc;
-      if (us < best_c) { best_c = us; bc_w = w; bc_x = x; }
-    }
+  int bc_a = 0, bc_w = 0, bc_x = 0;
+  for (int a = 1; a <= 2; ++a) {
+    p->tune[AR_TUNE_COL_ALGO] = a;
+    if (wave_cols_algo(p) != a) continue;
+    for (int w : waves)
+      for (int x = 0; x < 2; ++x) {
+        p->tune[AR_TUNE_COL_WAVES] = w;
+        p->tune[AR_TUNE_COL_EXCL] = x;
+        double us = 0;
+        int rc = time_us([&]() { return cols_launch(p, p->c, p->c, COL_FWD_D_INV, st); }, st,
+                         reps, &us);
+        if (rc != AR_OK) return rc;
+        if (us < best_c) { best_c = us; bc_a = a; bc_w = w; bc_x = x; }
+      }
+  }
+  p->tune[AR_TUNE_COL_ALGO] = bc_a;
   p->tune[AR_TUNE_COL_WAVES] = bc_w;
   p->tune[AR_TUNE_COL_EXCL] = bc_x;
+  if (best_c == DBL_MAX) best_c = 0;
   if (best_us) *best_us = best_r + best_c;
   return AR_OK;
 }

@@ -2,22 +2,30 @@
 //
 // Same mathematics as the block-wide engine (Theorem 1: endpoint scaling,
 // ramp removal / restoration, DST-I of length m - 2 through one complex FFT
-// of length M = m - 1 on the packed odd extension), organised so that every
-// wavefront owns one row (or one column) from global load to global store:
-//   * the packed sequence u_t = z_{2t} + i z_{2t+1} is written straight from
-//     global memory into the wave's LDS buffer at digit-reversed positions;
-//   * the FFT is an in-place mixed-radix decimation-in-time transform, one
-//     butterfly per lane per step, largest radix first (its stage needs no
-//     twiddles); twiddles of stage t are stored as [r - 1][k] so that lanes
-//     with consecutive k read consecutive addresses;
-//   * the DST values are formed from U_k and U_{M-k} and stored directly.
-// A workgroup holds W waves (W sequences) and synchronises them between FFT
-// stages.  The column pass of the preconditioner keeps the filtered
-// coefficients in a per-wave LDS staging row and runs the inverse FFT in the
-// same workgroup.  Every radix of M must have a codelet; other lengths use
-// the block-wide engine.
+// of length M = m - 1 on the packed odd extension u_t = z_{2t} + i z_{2t+1}),
+// organised so that every wavefront owns one row (or one column) from global
+// load to global store:
+//   * the packed sequence is written from registers into the wave's LDS
+//     buffer at digit-reversed positions;
+//   * the FFT is an in-place decimation-in-time (DIT) transform, one
+//     butterfly per lane per step; twiddles of stage t are stored [r - 1][k]
+//     so that lanes with consecutive k read consecutive words;
+//   * the FFT is either the mixed-radix FFT of length M (every prime factor
+//     has a codelet, largest radix first) or Bluestein's chirp-z form:
+//     a_j = u_j w_j with w_j = e^{-i pi j^2 / M}, a DIT FFT of power-of-two
+//     length N >= 2M - 1, the product with the chirp spectrum, and the
+//     inverse FFT as a decimation-in-frequency (DIF) FFT of the conjugate,
+//     which leaves its result at digit-reversed positions, so that
+//     U_k = w_k conj(D[drev(k)]) needs no extra permutation pass;
+//   * the DST values come from U_k and U_{M-k} and are stored directly.
+// Twiddle, post-processing and digit-reversal tables are staged in LDS once
+// per workgroup; the global loads of a kernel are issued before its first
+// barrier.  The column pass of the preconditioner keeps the filtered
+// coefficients in a per-wave LDS row and runs the inverse transform in the
+// same workgroup.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <vector>
 
 #include "ar_codelets.h"
@@ -28,22 +36,24 @@ namespace {
 
 using namespace cl;
 
-// ------------------------------------------------------------ DIT stages
+// ------------------------------------------------------------ FFT stages
 
 // Butterflies are processed NB at a time per lane: indices are clamped so
-// that every load of a chunk is unconditional and issued together (one
-// memory latency per chunk instead of one per butterfly); only the stores
-// are guarded.  In-place is safe: butterflies of one stage touch disjoint
+// that every load of a chunk is issued together; only the stores are
+// guarded.  In place is safe: butterflies of one stage touch disjoint
 // positions.
 template <int R> struct Chunk { static constexpr int value = R <= 4 ? 4 : (R <= 11 ? 2 : 1); };
 
-template <typename T, int R>
-__device__ __forceinline__ void dit_bfly(V2<T> *U, int M, int L, const V2<T> *__restrict__ tw,
-                                         int lane) {
+// One stage.  DIT: twiddle the inputs, then the DFT.  DIF (the transpose
+// of the DIT stage): the DFT, then twiddle the outputs.
+template <typename T, int R, bool DIF>
+__device__ __forceinline__ void bfly(V2<T> *U, int N, int L, const V2<T> *__restrict__ tw,
+                                     int lane) {
   constexpr int NB = Chunk<R>::value;
-  const int nb = M / R;
+  const int nb = N / R;
   for (int j0 = lane; j0 < nb; j0 += 64 * NB) {
     V2<T> v[NB][R];
+    V2<T> t[NB][R - 1];
     int base[NB];
     bool ok[NB];
 #pragma unroll
@@ -54,49 +64,120 @@ __device__ __forceinline__ void dit_bfly(V2<T> *U, int M, int L, const V2<T> *__
       const int g = j / L, k = j - g * L;
       base[c] = g * L * R + k;
       static_for<R>([&](auto r) { v[c][r] = U[base[c] + r * L]; });
-      if (L > 1)
-        static_for<R - 1>([&](auto r) { v[c][r + 1] = cmul(v[c][r + 1], tw[r * L + k]); });
+      if (L > 1) {
+        static_for<R - 1>([&](auto r) { t[c][r] = tw[r * L + k]; });
+        if constexpr (!DIF)
+          static_for<R - 1>([&](auto r) { v[c][r + 1] = cmul(v[c][r + 1], t[c][r]); });
+      }
     }
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-      if (ok[c])
+      if (!ok[c]) continue;
+      if constexpr (!DIF) {
         dft_emit<R, T>(v[c], [&](auto K, V2<T> x) { U[base[c] + decltype(K)::value * L] = x; });
+      } else {
+        dft_emit<R, T>(v[c], [&](auto K, V2<T> x) {
+          constexpr int r = decltype(K)::value;
+          if constexpr (r > 0)
+            if (L > 1) x = cmul(x, t[c][r - 1]);
+          U[base[c] + r * L] = x;
+        });
+      }
     }
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void dit_run(V2<T> *U, const WDesc &wd, const V2<T> *__restrict__ tw,
-                                     int lane) {
-  const int M = wd.M;
-  for (int t = 0; t < wd.nst; ++t) {
-    const V2<T> *tt = tw + wd.tw_off[t];
-    const int L = wd.L[t];
-    switch (wd.R[t]) {
-      case 2: dit_bfly<T, 2>(U, M, L, tt, lane); break;
-      case 3: dit_bfly<T, 3>(U, M, L, tt, lane); break;
-      case 4: dit_bfly<T, 4>(U, M, L, tt, lane); break;
-      case 5: dit_bfly<T, 5>(U, M, L, tt, lane); break;
-      case 7: dit_bfly<T, 7>(U, M, L, tt, lane); break;
-      case 11: dit_bfly<T, 11>(U, M, L, tt, lane); break;
-      case 13: dit_bfly<T, 13>(U, M, L, tt, lane); break;
-      case 17: dit_bfly<T, 17>(U, M, L, tt, lane); break;
-      case 19: dit_bfly<T, 19>(U, M, L, tt, lane); break;
-      case 23: dit_bfly<T, 23>(U, M, L, tt, lane); break;
-      case 29: dit_bfly<T, 29>(U, M, L, tt, lane); break;
-      default: dit_bfly<T, 31>(U, M, L, tt, lane); break;
+// DIT runs stages 0..nst-1 (digit-reversed in, natural out); DIF runs them
+// backwards (natural in, digit-reversed out).  Bluestein plans use radices
+// 4 and 2 only.
+template <typename T, bool DIF, bool BS>
+__device__ __forceinline__ void fft_run(V2<T> *U, const WDesc &wd, const V2<T> *__restrict__ tw,
+                                        int lane) {
+  const int N = wd.N;
+  for (int s = 0; s < wd.nst; ++s) {
+    const int st = DIF ? wd.nst - 1 - s : s;
+    const V2<T> *tt = tw + wd.tw_off[st];
+    const int L = wd.L[st];
+    if constexpr (BS) {
+      if (wd.R[st] == 4)
+        bfly<T, 4, DIF>(U, N, L, tt, lane);
+      else
+        bfly<T, 2, DIF>(U, N, L, tt, lane);
+    } else {
+      switch (wd.R[st]) {
+        case 2: bfly<T, 2, DIF>(U, N, L, tt, lane); break;
+        case 3: bfly<T, 3, DIF>(U, N, L, tt, lane); break;
+        case 4: bfly<T, 4, DIF>(U, N, L, tt, lane); break;
+        case 5: bfly<T, 5, DIF>(U, N, L, tt, lane); break;
+        case 7: bfly<T, 7, DIF>(U, N, L, tt, lane); break;
+        case 11: bfly<T, 11, DIF>(U, N, L, tt, lane); break;
+        case 13: bfly<T, 13, DIF>(U, N, L, tt, lane); break;
+        case 17: bfly<T, 17, DIF>(U, N, L, tt, lane); break;
+        case 19: bfly<T, 19, DIF>(U, N, L, tt, lane); break;
+        case 23: bfly<T, 23, DIF>(U, N, L, tt, lane); break;
+        case 29: bfly<T, 29, DIF>(U, N, L, tt, lane); break;
+        default: bfly<T, 31, DIF>(U, N, L, tt, lane); break;
+      }
     }
     __syncthreads();
   }
 }
 
+constexpr int kRowChunk = 16;  // elements per lane per batch (covers 1024 per wave)
+
+// Bluestein middle step, natural order, in place: U_k <- conj(U_k bhat_k)
+template <typename T>
+__device__ __forceinline__ void bs_mid(V2<T> *U, int N, const V2<T> *__restrict__ bhat, int lane) {
+  for (int k0 = lane; k0 < N; k0 += 64 * kRowChunk) {
+    V2<T> b[kRowChunk];
+#pragma unroll
+    for (int c = 0; c < kRowChunk; ++c) {
+      const int k = k0 + 64 * c;
+      b[c] = bhat[k < N ? k : k0];
+    }
+#pragma unroll
+    for (int c = 0; c < kRowChunk; ++c) {
+      const int k = k0 + 64 * c;
+      if (k < N) {
+        const V2<T> z = cmul(U[k], b[c]);
+        U[k] = {z.x, -z.y};
+      }
+    }
+  }
+}
+
+// The DFT of the packed sequence held in U.
+template <typename T, bool BS>
+__device__ __forceinline__ void fft_full(V2<T> *U, const WDesc &wd, const V2<T> *tw,
+                                         const V2<T> *__restrict__ bhat, int lane) {
+  fft_run<T, false, BS>(U, wd, tw, lane);
+  if constexpr (BS) {
+    bs_mid<T>(U, wd.N, bhat, lane);
+    __syncthreads();
+    fft_run<T, true, BS>(U, wd, tw, lane);
+  }
+}
+
 // ------------------------------------------------- packing and DST values
 
+// U_k of the length-M DFT (1 <= k <= M - 1) from the buffer
+template <typename T, bool BS>
+__device__ __forceinline__ V2<T> getU(const V2<T> *U, const int *s_drev,
+                                      const V2<T> *__restrict__ chirp, int k) {
+  if constexpr (!BS) {
+    return U[k];
+  } else {
+    const V2<T> d = U[s_drev[k]];
+    return cmul(chirp[k], V2<T>{d.x, -d.y});
+  }
+}
+
 // sum_j x_j sin(pi j k / M) * scale from U_k and U_{M-k}, 1 <= k <= M-1
-template <typename T>
-__device__ __forceinline__ T wdst(const V2<T> *U, int k, int M, const V2<T> *__restrict__ post,
-                                  T scale) {
-  const V2<T> A = U[k], C = U[M - k];
+template <typename T, bool BS>
+__device__ __forceinline__ T wdst(const V2<T> *U, const int *s_drev, const V2<T> *chirp, int k,
+                                  int M, const V2<T> *__restrict__ post, T scale) {
+  const V2<T> A = getU<T, BS>(U, s_drev, chirp, k);
+  const V2<T> C = getU<T, BS>(U, s_drev, chirp, M - k);
   const V2<T> cs = post[k];
   return scale * ((C.y - A.y) + cs.x * (A.x - C.x) + cs.y * (A.y + C.y));
 }
@@ -104,11 +185,12 @@ __device__ __forceinline__ T wdst(const V2<T> *U, int k, int M, const V2<T> *__r
 // Output k of a forward (INV = false) or inverse (INV = true) AR pass of
 // length m = M + 1: endpoints from e0/e1, interior from the DST (plus the
 // ramp for the inverse).  Loads use a clamped index (branch-free).
-template <typename T, bool INV>
-__device__ __forceinline__ T wcoef(const V2<T> *U, int k, int M, const V2<T> *__restrict__ post,
-                                   T scale, T alpha, T e0, T e1, T invM) {
+template <typename T, bool INV, bool BS>
+__device__ __forceinline__ T wcoef(const V2<T> *U, const int *s_drev, const V2<T> *chirp, int k,
+                                   int M, const V2<T> *__restrict__ post, T scale, T alpha, T e0,
+                                   T e1, T invM) {
   const int kc = k < 1 ? 1 : (k > M - 1 ? M - 1 : k);
-  const T d = wdst<T>(U, kc, M, post, scale);
+  const T d = wdst<T, BS>(U, s_drev, chirp, kc, M, post, scale);
   if (!INV) return k == 0 ? alpha * e0 : (k == M ? alpha * e1 : d);
   const T y0 = e0 / alpha, y1 = e1 / alpha;
   const T in = d + y0 * (T(M - k) * invM) + y1 * (T(k) * invM);
@@ -131,41 +213,42 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
 
 // ------------------------------------------------------- LDS layout
 
-// Workgroup LDS: [twiddles: twn][post: M+1][drev: M ints][U: W x M][aux: W x aux]
+// Workgroup LDS: [twiddles: twn][post: M+1][drev: N ints][U: W x N][aux: W x aux]
 template <typename T>
 struct WLayout {
   V2<T> *tw, *post, *U;
   int *drev;
   unsigned char *aux;
-  __device__ WLayout(unsigned char *raw, int twn, int M, int W, int wave, size_t aux_bytes) {
+  __device__ WLayout(unsigned char *raw, int twn, int M, int N, int W, int wave,
+                     size_t aux_bytes) {
     tw = reinterpret_cast<V2<T> *>(raw);
     post = tw + twn;
     drev = reinterpret_cast<int *>(post + M + 1);
-    size_t off = (size_t)(twn + M + 1) * sizeof(V2<T>) + (size_t)M * sizeof(int);
+    size_t off = (size_t)(twn + M + 1) * sizeof(V2<T>) + (size_t)N * sizeof(int);
     off = (off + 15) & ~(size_t)15;
-    U = reinterpret_cast<V2<T> *>(raw + off) + (size_t)wave * M;
-    off += (size_t)W * M * sizeof(V2<T>);
+    U = reinterpret_cast<V2<T> *>(raw + off) + (size_t)wave * N;
+    off += (size_t)W * N * sizeof(V2<T>);
     aux = raw + off + (size_t)wave * aux_bytes;
   }
 };
 
-size_t wlds_bytes(int twn, int M, int W, size_t csize, size_t aux_bytes) {
-  size_t off = (size_t)(twn + M + 1) * 2 * csize + (size_t)M * sizeof(int);
+size_t wlds_bytes(int twn, int M, int N, int W, size_t csize, size_t aux_bytes) {
+  size_t off = (size_t)(twn + M + 1) * 2 * csize + (size_t)N * sizeof(int);
   off = (off + 15) & ~(size_t)15;
-  return off + (size_t)W * M * 2 * csize + (size_t)W * aux_bytes;
+  return off + (size_t)W * N * 2 * csize + (size_t)W * aux_bytes;
 }
 
-constexpr int kTabChunk = 4;   // table elements per thread per batch
-constexpr int kRowChunk = 16;  // row elements per lane per batch (covers m <= 1024 at once)
+constexpr int kTabChunk = 4;  // table elements per thread per batch
 
 // Twiddle, post and digit-reversal tables into LDS; indices are clamped so
 // that all loads of a batch are issued before any store.
 template <typename T>
 __device__ __forceinline__ void load_tables(const WLayout<T> &Ly, const V2<T> *__restrict__ tw,
                                             int twn, const V2<T> *__restrict__ post, int M,
-                                            const int *__restrict__ drev) {
+                                            const int *__restrict__ drev, int N) {
   const int nth = blockDim.x, tid = threadIdx.x;
-  const int tot = (twn > M + 1 ? twn : M + 1);
+  int tot = twn > M + 1 ? twn : M + 1;
+  tot = tot > N ? tot : N;
   const int twmax = twn > 0 ? twn - 1 : 0;
   for (int e0 = tid; e0 < tot; e0 += nth * kTabChunk) {
     V2<T> a[kTabChunk], p[kTabChunk];
@@ -175,35 +258,41 @@ __device__ __forceinline__ void load_tables(const WLayout<T> &Ly, const V2<T> *_
       const int e = e0 + nth * c;
       a[c] = tw[e < twn ? e : twmax];
       p[c] = post[e <= M ? e : M];
-      d[c] = drev[e < M ? e : M - 1];
+      d[c] = drev[e < N ? e : N - 1];
     }
 #pragma unroll
     for (int c = 0; c < kTabChunk; ++c) {
       const int e = e0 + nth * c;
       if (e < twn) Ly.tw[e] = a[c];
       if (e <= M) Ly.post[e] = p[c];
-      if (e < M) Ly.drev[e] = d[c];
+      if (e < N) Ly.drev[e] = d[c];
     }
   }
 }
 
-// Raw interior values x_j, j = 2t and 2t+1 (mirrored for t beyond M/2),
-// of one chunk of the packed sequence, read with clamped indices.
-template <typename TSRC, typename T>
-__device__ __forceinline__ void pack_load(T (&xr)[kRowChunk], T (&xi)[kRowChunk],
-                                          const TSRC *src, long stride, int t0, int M) {
+// One chunk of the packed sequence: raw interior values x_j for j = 2t and
+// 2t + 1 (mirrored past M) and, for Bluestein, the chirp w_t; clamped
+// indices so that every load is unconditional.
+template <typename TSRC, typename T, bool BS>
+struct PackChunk {
+  T xr[kRowChunk], xi[kRowChunk];
+  V2<T> w[BS ? kRowChunk : 1];
+  __device__ __forceinline__ void load(const TSRC *src, long stride, int t0, int M,
+                                       const V2<T> *__restrict__ chirp) {
 #pragma unroll
-  for (int c = 0; c < kRowChunk; ++c) {
-    const int t = t0 + 64 * c;
-    int j0 = 2 * t, j1 = 2 * t + 1;
-    j0 = j0 < M ? j0 : 2 * M - j0;
-    j1 = j1 < M ? j1 : 2 * M - j1;
-    j0 = (j0 < 1 || j0 > M - 1) ? 1 : j0;  // tau = 0, M (value unused) or t past the end
-    j1 = (j1 < 1 || j1 > M - 1) ? 1 : j1;
-    xr[c] = T(src[(long)j0 * stride]);
-    xi[c] = T(src[(long)j1 * stride]);
+    for (int c = 0; c < kRowChunk; ++c) {
+      const int t = t0 + 64 * c;
+      int j0 = 2 * t, j1 = 2 * t + 1;
+      j0 = j0 < M ? j0 : 2 * M - j0;
+      j1 = j1 < M ? j1 : 2 * M - j1;
+      j0 = (j0 < 1 || j0 > M - 1) ? 1 : j0;  // tau = 0, M (value unused) or past the end
+      j1 = (j1 < 1 || j1 > M - 1) ? 1 : j1;
+      xr[c] = T(src[(long)j0 * stride]);
+      xi[c] = T(src[(long)j1 * stride]);
+      if constexpr (BS) w[c] = chirp[t < M ? t : 0];
+    }
   }
-}
+};
 
 // z_tau of the odd extension from a loaded raw value (ramp removed if asked)
 template <typename T>
@@ -215,59 +304,62 @@ __device__ __forceinline__ T zfrom(T x, int tau, int M, bool ramp, T e0, T e1, T
   return zero ? T(0) : x;
 }
 
-template <typename T>
-__device__ __forceinline__ void pack_store(V2<T> *U, const int *s_drev, const T (&xr)[kRowChunk],
-                                           const T (&xi)[kRowChunk], int t0, int M, bool active,
-                                           bool ramp, T e0, T e1) {
+// Store one chunk at digit-reversed positions; Bluestein zero-pads t >= M.
+template <typename TSRC, typename T, bool BS>
+__device__ __forceinline__ void pack_store(V2<T> *U, const int *s_drev,
+                                           const PackChunk<TSRC, T, BS> &pc, int t0, int M, int N,
+                                           bool active, bool ramp, T e0, T e1) {
   const T invM = T(1) / T(M);
 #pragma unroll
   for (int c = 0; c < kRowChunk; ++c) {
     const int t = t0 + 64 * c;
-    if (t >= M) continue;
+    if (t >= N) continue;
     V2<T> u{T(0), T(0)};
-    if (active) {
-      u.x = zfrom<T>(xr[c], 2 * t, M, ramp, e0, e1, invM);
-      u.y = zfrom<T>(xi[c], 2 * t + 1, M, ramp, e0, e1, invM);
+    if (active && t < M) {
+      u.x = zfrom<T>(pc.xr[c], 2 * t, M, ramp, e0, e1, invM);
+      u.y = zfrom<T>(pc.xi[c], 2 * t + 1, M, ramp, e0, e1, invM);
+      if constexpr (BS) u = cmul(u, pc.w[c]);
     }
     U[s_drev[t]] = u;
   }
 }
 
-// Pack the whole sequence (chunk 0 already loaded into xr/xi).
-template <typename TSRC, typename T>
-__device__ __forceinline__ void pack_rest(V2<T> *U, const int *s_drev, T (&xr)[kRowChunk],
-                                          T (&xi)[kRowChunk], const TSRC *src, long stride,
-                                          int lane, int M, bool active, bool ramp, T e0, T e1) {
-  pack_store<T>(U, s_drev, xr, xi, lane, M, active, ramp, e0, e1);
-  for (int t0 = lane + 64 * kRowChunk; t0 < M; t0 += 64 * kRowChunk) {
-    pack_load<TSRC, T>(xr, xi, src, stride, t0, M);
-    pack_store<T>(U, s_drev, xr, xi, t0, M, active, ramp, e0, e1);
+// Pack the whole sequence (chunk 0 already loaded into pc).
+template <typename TSRC, typename T, bool BS>
+__device__ __forceinline__ void pack_all(V2<T> *U, const int *s_drev, PackChunk<TSRC, T, BS> &pc,
+                                         const TSRC *src, long stride, int lane, int M, int N,
+                                         const V2<T> *chirp, bool active, bool ramp, T e0, T e1) {
+  pack_store<TSRC, T, BS>(U, s_drev, pc, lane, M, N, active, ramp, e0, e1);
+  for (int t0 = lane + 64 * kRowChunk; t0 < N; t0 += 64 * kRowChunk) {
+    pc.load(src, stride, t0, M, chirp);
+    pack_store<TSRC, T, BS>(U, s_drev, pc, t0, M, N, active, ramp, e0, e1);
   }
 }
 
 // ---------------------------------------------------------------- rows
 
-template <typename TS, typename T, int MODE>
+template <typename TS, typename T, int MODE, bool BS>
 __global__ __launch_bounds__(256) void rows_w_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int n1, int m, WDesc wd,
     const V2<T> *__restrict__ tw, const int *__restrict__ drev, const V2<T> *__restrict__ post,
-    T alpha, T scale, T tau, const TS *__restrict__ f_true, double *__restrict__ partial) {
+    const V2<T> *__restrict__ chirp, const V2<T> *__restrict__ bhat, T alpha, T scale, T tau,
+    const TS *__restrict__ f_true, double *__restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int M = wd.M;
+  const int M = wd.M, N = wd.N;
   const int W = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = xcd_remap(blockIdx.x, gridDim.x) * W + wave;
   const bool active = row < n1;
   const size_t auxb = MODE == ROW_INV_UPDATE ? 2 * (size_t)m * sizeof(TS) : 0;
-  const WLayout<T> Ly(smem_raw, wd.twn, M, W, wave, auxb);
+  const WLayout<T> Ly(smem_raw, wd.twn, M, N, W, wave, auxb);
   const TS *src = in + (size_t)(active ? row : 0) * m;
   TS *dst = out + (size_t)(active ? row : 0) * m;
   const TS *fr = f_true ? f_true + (size_t)(active ? row : 0) * m : nullptr;
   TS *sx = reinterpret_cast<TS *>(Ly.aux);
   TS *sf = sx + m;
   // one batch of global loads: this wave's row, x and f (update), tables
-  T xr[kRowChunk], xi[kRowChunk];
-  pack_load<TS, T>(xr, xi, src, 1, lane, M);
+  PackChunk<TS, T, BS> pc;
+  pc.load(src, 1, lane, M, chirp);
   const T e0 = T(src[0]), e1 = T(src[m - 1]);
   if (MODE == ROW_INV_UPDATE) {
     for (int k0 = lane; k0 < m; k0 += 64 * kRowChunk) {
@@ -289,11 +381,12 @@ __global__ __launch_bounds__(256) void rows_w_kernel(
       }
     }
   }
-  load_tables<T>(Ly, tw, wd.twn, post, M, drev);
+  load_tables<T>(Ly, tw, wd.twn, post, M, drev, N);
   __syncthreads();
-  pack_rest<TS, T>(Ly.U, Ly.drev, xr, xi, src, 1, lane, M, active, MODE == ROW_FWD, e0, e1);
+  pack_all<TS, T, BS>(Ly.U, Ly.drev, pc, src, 1, lane, M, N, chirp, active, MODE == ROW_FWD, e0,
+                      e1);
   __syncthreads();
-  dit_run<T>(Ly.U, wd, Ly.tw, lane);
+  fft_full<T, BS>(Ly.U, wd, Ly.tw, bhat, lane);
   double ss = 0.0;
   if (active) {
     const T invM = T(1) / T(M);
@@ -303,7 +396,8 @@ __global__ __launch_bounds__(256) void rows_w_kernel(
       for (int c = 0; c < kPostChunk; ++c) {
         const int kr = k0 + 64 * c;
         const int k = kr < m ? kr : k0;
-        val[c] = wcoef<T, MODE != ROW_FWD>(Ly.U, k, M, Ly.post, scale, alpha, e0, e1, invM);
+        val[c] = wcoef<T, MODE != ROW_FWD, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha,
+                                               e0, e1, invM);
       }
 #pragma unroll
       for (int c = 0; c < kPostChunk; ++c) {
@@ -332,24 +426,25 @@ __global__ __launch_bounds__(256) void rows_w_kernel(
 
 // ------------------------------------------------------------- columns
 
-template <typename TS, typename T, int MODE>
+template <typename TS, typename T, int MODE, bool BS>
 __global__ __launch_bounds__(256) void cols_w_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int m, int n2, WDesc wd,
     const V2<T> *__restrict__ tw, const int *__restrict__ drev, const V2<T> *__restrict__ post,
-    T alpha, T scale, const T *__restrict__ dflt) {
+    const V2<T> *__restrict__ chirp, const V2<T> *__restrict__ bhat, T alpha, T scale,
+    const T *__restrict__ dflt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int M = wd.M;
+  const int M = wd.M, N = wd.N;
   const int W = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = xcd_remap(blockIdx.x, gridDim.x) * W + wave;
   const bool active = col < n2;
   const size_t auxb = MODE == COL_FWD_D_INV ? (size_t)m * sizeof(T) : 0;
-  const WLayout<T> Ly(smem_raw, wd.twn, M, W, wave, auxb);
+  const WLayout<T> Ly(smem_raw, wd.twn, M, N, W, wave, auxb);
   T *S = reinterpret_cast<T *>(Ly.aux);
   const long ld = n2;
   const TS *src = in + (active ? col : 0);
-  T xr[kRowChunk], xi[kRowChunk];
-  pack_load<TS, T>(xr, xi, src, ld, lane, M);
+  PackChunk<TS, T, BS> pc;
+  pc.load(src, ld, lane, M, chirp);
   T e0 = T(src[0]);
   T e1 = T(src[(long)(m - 1) * ld]);
   if (MODE == COL_FWD_D_INV) {
@@ -369,21 +464,23 @@ __global__ __launch_bounds__(256) void cols_w_kernel(
       }
     }
   }
-  load_tables<T>(Ly, tw, wd.twn, post, M, drev);
+  load_tables<T>(Ly, tw, wd.twn, post, M, drev, N);
   __syncthreads();
-  pack_rest<TS, T>(Ly.U, Ly.drev, xr, xi, src, ld, lane, M, active, MODE != COL_INV, e0, e1);
+  pack_all<TS, T, BS>(Ly.U, Ly.drev, pc, src, ld, lane, M, N, chirp, active, MODE != COL_INV, e0,
+                      e1);
   __syncthreads();
-  dit_run<T>(Ly.U, wd, Ly.tw, lane);
+  fft_full<T, BS>(Ly.U, wd, Ly.tw, bhat, lane);
   const T invM = T(1) / T(M);
   if (MODE == COL_FWD_D_INV) {
-    // S[k] <- d_k * (T~ y)_k (same lane reads and writes S[k])
+    // S[k] <- d_k * (T~ y)_k (each lane reads and writes only its own S[k])
     for (int k0 = lane; k0 < m; k0 += 64 * kPostChunk) {
       T val[kPostChunk];
 #pragma unroll
       for (int c = 0; c < kPostChunk; ++c) {
         const int kr = k0 + 64 * c;
         const int k = kr < m ? kr : k0;
-        val[c] = wcoef<T, false>(Ly.U, k, M, Ly.post, scale, alpha, e0, e1, invM);
+        val[c] = wcoef<T, false, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha, e0, e1,
+                                     invM);
       }
 #pragma unroll
       for (int c = 0; c < kPostChunk; ++c) {
@@ -394,12 +491,13 @@ __global__ __launch_bounds__(256) void cols_w_kernel(
     __syncthreads();
     e0 = S[0];
     e1 = S[m - 1];
-    for (int t0 = lane; t0 < M; t0 += 64 * kRowChunk) {
-      pack_load<T, T>(xr, xi, S, 1, t0, M);
-      pack_store<T>(Ly.U, Ly.drev, xr, xi, t0, M, active, false, e0, e1);
+    PackChunk<T, T, BS> ps;
+    for (int t0 = lane; t0 < N; t0 += 64 * kRowChunk) {
+      ps.load(S, 1, t0, M, chirp);
+      pack_store<T, T, BS>(Ly.U, Ly.drev, ps, t0, M, N, active, false, e0, e1);
     }
     __syncthreads();
-    dit_run<T>(Ly.U, wd, Ly.tw, lane);
+    fft_full<T, BS>(Ly.U, wd, Ly.tw, bhat, lane);
   }
   if (active) {
     for (int k0 = lane; k0 < m; k0 += 64 * kPostChunk) {
@@ -408,7 +506,8 @@ __global__ __launch_bounds__(256) void cols_w_kernel(
       for (int c = 0; c < kPostChunk; ++c) {
         const int kr = k0 + 64 * c;
         const int k = kr < m ? kr : k0;
-        val[c] = wcoef<T, MODE != COL_FWD>(Ly.U, k, M, Ly.post, scale, alpha, e0, e1, invM);
+        val[c] = wcoef<T, MODE != COL_FWD, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha,
+                                               e0, e1, invM);
       }
 #pragma unroll
       for (int c = 0; c < kPostChunk; ++c) {
@@ -438,27 +537,25 @@ __global__ void wtables_kernel(V2<T> *tw, const int *R, const int *L, const int 
   }
 }
 
+constexpr size_t kMaxLdsW = 150 * 1024;
+
 // Waves (sequences) per workgroup: `forced` if it fits, else the largest
 // power of two <= 4 whose LDS fits.
 int wave_count(size_t fixed, size_t per_wave, int nseq, int forced) {
   if (forced == 1 || forced == 2 || forced == 4) {
     int W = forced;
-    while (W > 1 && fixed + (size_t)W * per_wave > 150 * 1024) W >>= 1;
+    while (W > 1 && fixed + (size_t)W * per_wave > kMaxLdsW) W >>= 1;
     return W;
   }
   int W = 4;
-  while (W > 1 && fixed + (size_t)W * per_wave > 150 * 1024) W >>= 1;
+  while (W > 1 && fixed + (size_t)W * per_wave > kMaxLdsW) W >>= 1;
   while (W > 1 && W / 2 >= nseq) W >>= 1;
   return W;
 }
 
 // With the exclusive flag the dynamic LDS is padded so that one workgroup
 // occupies a CU (the dispatcher then spreads workgroups over all CUs).
-size_t excl_pad(size_t smem, int excl) {
-  return excl && smem < 81 * 1024 ? 81 * 1024 : smem;
-}
-
-constexpr size_t kMaxLdsW = 150 * 1024;
+size_t excl_pad(size_t smem, int excl) { return excl && smem < 81 * 1024 ? 81 * 1024 : smem; }
 
 template <typename K>
 hipError_t allow_lds_w(K kernel, size_t bytes) {
@@ -470,6 +567,8 @@ hipError_t allow_lds_w(K kernel, size_t bytes) {
 WDesc make_wdesc(const WavePlan &w) {
   WDesc d{};
   d.M = w.M;
+  d.N = w.N;
+  d.bs = w.bs ? 1 : 0;
   d.nst = w.nst;
   d.twn = w.twn;
   for (int s = 0; s < kMaxStages; ++s) {
@@ -480,21 +579,70 @@ WDesc make_wdesc(const WavePlan &w) {
   return d;
 }
 
+// In-place iterative radix-2 FFT (host, FP64) of a power-of-two length;
+// run once per plan for the chirp spectrum.
+void host_fft(std::vector<std::complex<double>> &a) {
+  const size_t n = a.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    for (size_t k = 0; k < len / 2; ++k) {
+      const double ang = -2.0 * M_PI * (double)k / (double)len;
+      const std::complex<double> w(std::cos(ang), std::sin(ang));
+      for (size_t i = 0; i < n; i += len) {
+        const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+    }
+  }
+}
+
+template <typename T>
+int upload_complex(void **dst, const std::vector<std::complex<double>> &v) {
+  std::vector<V2<T>> h(v.size());
+  for (size_t i = 0; i < v.size(); ++i) h[i] = {T(v[i].real()), T(v[i].imag())};
+  AR_HIP(hipMalloc(dst, (h.empty() ? 1 : h.size()) * sizeof(V2<T>)));
+  AR_HIP(hipMemcpy(*dst, h.data(), h.size() * sizeof(V2<T>), hipMemcpyHostToDevice));
+  return AR_OK;
+}
+
 }  // namespace
 
-// Factor M into codelet radices (4s first, then odd primes), largest radix
-// first; build the digit-reversal table and the twiddle tables.
-int wave_plan_build(WavePlan &w, int M, bool cdouble, hipStream_t st) {
+// Mixed radix: factor M into codelet radices (4s first, then odd primes),
+// largest radix first; not applicable when a prime factor exceeds 31.
+// Bluestein: N = smallest power of two >= 2M - 1 in radices 4 (and one 2),
+// chirp w_j = e^{-i pi j^2 / M} (j^2 reduced mod 2M exactly), and
+// bhat = FFT_N(b) / N with b_j = conj(w_j) and b_{N-j} = b_j.
+// Both build their digit-reversal and twiddle tables.
+int wave_plan_build(WavePlan &w, int M, bool cdouble, bool bluestein, hipStream_t st) {
   w = WavePlan{};
   w.M = M;
+  if (M < 2) return AR_OK;
   std::vector<int> rad;
-  int r = M;
-  while (r % 4 == 0) { rad.push_back(4); r /= 4; }
-  while (r % 2 == 0) { rad.push_back(2); r /= 2; }
-  for (int p = 3; p <= 31 && r > 1; p += 2)
-    while (r % p == 0 && cl::has_codelet(p)) { rad.push_back(p); r /= p; }
-  if (r != 1 || rad.empty() || (int)rad.size() > kMaxStages) return AR_OK;  // not applicable
-  std::sort(rad.begin(), rad.end(), [](int a, int b) { return a > b; });
+  int N = M;
+  if (bluestein) {
+    N = 1;
+    while (N < 2 * M - 1) N <<= 1;
+    int r = N;
+    while (r % 4 == 0) { rad.push_back(4); r /= 4; }
+    while (r % 2 == 0) { rad.push_back(2); r /= 2; }
+  } else {
+    int r = M;
+    while (r % 4 == 0) { rad.push_back(4); r /= 4; }
+    while (r % 2 == 0) { rad.push_back(2); r /= 2; }
+    for (int p = 3; p <= 31 && r > 1; p += 2)
+      while (r % p == 0 && cl::has_codelet(p)) { rad.push_back(p); r /= p; }
+    if (r != 1 || rad.empty()) return AR_OK;  // not applicable
+    std::sort(rad.begin(), rad.end(), [](int a, int b) { return a > b; });
+  }
+  if (rad.empty() || (int)rad.size() > kMaxStages) return AR_OK;
+  w.N = N;
+  w.bs = bluestein;
   w.nst = (int)rad.size();
   int L = 1;
   size_t off = 0;
@@ -509,11 +657,12 @@ int wave_plan_build(WavePlan &w, int M, bool cdouble, hipStream_t st) {
     off += (size_t)(rad[s] - 1) * L;
     L *= rad[s];
   }
+  w.twn = (int)off;
   // digit reversal: natural index n has digits (most significant first)
   // p_0..p_{s-1} in radices R_0..R_{s-1}; its position is sum_t p_t prod_{u<t} R_u
-  std::vector<int> drev(M);
-  for (int n = 0; n < M; ++n) {
-    int rem = n, pos = 0, wpos = 1, wnat = M;
+  std::vector<int> drev(N);
+  for (int n = 0; n < N; ++n) {
+    int rem = n, pos = 0, wpos = 1, wnat = N;
     for (int t = 0; t < w.nst; ++t) {
       wnat /= w.R[t];
       const int d = rem / wnat;
@@ -523,11 +672,10 @@ int wave_plan_build(WavePlan &w, int M, bool cdouble, hipStream_t st) {
     }
     drev[n] = pos;
   }
-  w.twn = (int)off;
   const size_t cb = cdouble ? sizeof(double2) : sizeof(float2);
   AR_HIP(hipMalloc(&w.tw, (off > 0 ? off : 1) * cb));
-  AR_HIP(hipMalloc((void **)&w.drev, (size_t)M * sizeof(int)));
-  AR_HIP(hipMemcpy(w.drev, drev.data(), (size_t)M * sizeof(int), hipMemcpyHostToDevice));
+  AR_HIP(hipMalloc((void **)&w.drev, (size_t)N * sizeof(int)));
+  AR_HIP(hipMemcpy(w.drev, drev.data(), (size_t)N * sizeof(int), hipMemcpyHostToDevice));
   std::vector<int> ints;
   ints.insert(ints.end(), hR.begin(), hR.end());
   ints.insert(ints.end(), hL.begin(), hL.end());
@@ -545,6 +693,23 @@ int wave_plan_build(WavePlan &w, int M, bool cdouble, hipStream_t st) {
   AR_HIP(hipGetLastError());
   AR_HIP(hipStreamSynchronize(st));
   AR_HIP(hipFree(dints));
+  if (bluestein) {
+    std::vector<std::complex<double>> chirp(M), b(N, 0.0);
+    for (int j = 0; j < M; ++j) {
+      const long jj = ((long)j * j) % (2L * M);
+      const double ang = -M_PI * (double)jj / (double)M;
+      chirp[j] = std::complex<double>(std::cos(ang), std::sin(ang));
+    }
+    for (int j = 0; j < M; ++j) b[j] = std::conj(chirp[j]);
+    for (int j = 1; j < M; ++j) b[N - j] = std::conj(chirp[j]);
+    host_fft(b);
+    for (auto &v : b) v /= (double)N;
+    int rc = cdouble ? upload_complex<double>(&w.chirp, chirp)
+                     : upload_complex<float>(&w.chirp, chirp);
+    if (rc != AR_OK) return rc;
+    rc = cdouble ? upload_complex<double>(&w.bhat, b) : upload_complex<float>(&w.bhat, b);
+    if (rc != AR_OK) return rc;
+  }
   w.ok = true;
   return AR_OK;
 }
@@ -552,7 +717,9 @@ int wave_plan_build(WavePlan &w, int M, bool cdouble, hipStream_t st) {
 void wave_plan_free(WavePlan &w) {
   if (w.tw) (void)hipFree(w.tw);
   if (w.drev) (void)hipFree(w.drev);
-  w.tw = nullptr;
+  if (w.chirp) (void)hipFree(w.chirp);
+  if (w.bhat) (void)hipFree(w.bhat);
+  w.tw = w.chirp = w.bhat = nullptr;
   w.drev = nullptr;
   w.ok = false;
 }
@@ -560,54 +727,80 @@ void wave_plan_free(WavePlan &w) {
 static size_t rows_aux(const ar_plan_s *p) { return 2 * (size_t)p->n2 * p->esize; }
 static size_t cols_aux(const ar_plan_s *p) { return (size_t)p->n1 * p->csize; }
 
-static int rows_waves(const ar_plan_s *p) {
-  const int M = p->fft_row.M;
-  const size_t fixed = wlds_bytes(p->fft_row.w.twn, M, 0, p->csize, 0);
-  return wave_count(fixed, (size_t)M * 2 * p->csize + rows_aux(p), p->n1, p->tune[AR_TUNE_ROW_WAVES]);
-}
-static int cols_waves(const ar_plan_s *p) {
-  const int M = p->fft_col.M;
-  const size_t fixed = wlds_bytes(p->fft_col.w.twn, M, 0, p->csize, 0);
-  return wave_count(fixed, (size_t)M * 2 * p->csize + cols_aux(p), p->n2, p->tune[AR_TUNE_COL_WAVES]);
+static bool fits(const WavePlan &w, const ar_plan_s *p, size_t aux) {
+  return w.ok && wlds_bytes(w.twn, w.M, w.N, 1, p->csize, aux) <= kMaxLdsW;
 }
 
-bool wave_rows_ok(const ar_plan_s *p) {
-  return p->fft_row.w.ok &&
-         wlds_bytes(p->fft_row.w.twn, p->fft_row.M, 1, p->csize, rows_aux(p)) <= kMaxLdsW;
+// FFT form per axis: the tunable (1 mixed radix, 2 Bluestein) when that
+// plan exists and fits in LDS, else mixed radix when it does, else Bluestein.
+static const WavePlan *pick(const FftPlan &fp, int algo, const ar_plan_s *p, size_t aux) {
+  if (algo == 1 && fits(fp.w, p, aux)) return &fp.w;
+  if (algo == 2 && fits(fp.wb, p, aux)) return &fp.wb;
+  if (fits(fp.w, p, aux)) return &fp.w;
+  if (fits(fp.wb, p, aux)) return &fp.wb;
+  return nullptr;
 }
-bool wave_cols_ok(const ar_plan_s *p) {
-  return p->fft_col.w.ok &&
-         wlds_bytes(p->fft_col.w.twn, p->fft_col.M, 1, p->csize, cols_aux(p)) <= kMaxLdsW;
+static const WavePlan *row_plan(const ar_plan_s *p) {
+  return pick(p->fft_row, p->tune[AR_TUNE_ROW_ALGO], p, rows_aux(p));
 }
+static const WavePlan *col_plan(const ar_plan_s *p) {
+  return pick(p->fft_col, p->tune[AR_TUNE_COL_ALGO], p, cols_aux(p));
+}
+
+static int rows_waves(const ar_plan_s *p, const WavePlan &w) {
+  const size_t fixed = wlds_bytes(w.twn, w.M, w.N, 0, p->csize, 0);
+  return wave_count(fixed, (size_t)w.N * 2 * p->csize + rows_aux(p), p->n1,
+                    p->tune[AR_TUNE_ROW_WAVES]);
+}
+static int cols_waves(const ar_plan_s *p, const WavePlan &w) {
+  const size_t fixed = wlds_bytes(w.twn, w.M, w.N, 0, p->csize, 0);
+  return wave_count(fixed, (size_t)w.N * 2 * p->csize + cols_aux(p), p->n2,
+                    p->tune[AR_TUNE_COL_WAVES]);
+}
+
+bool wave_rows_ok(const ar_plan_s *p) { return row_plan(p) != nullptr; }
+bool wave_cols_ok(const ar_plan_s *p) { return col_plan(p) != nullptr; }
 
 int wave_rows_blocks(const ar_plan_s *p) {
-  const int W = rows_waves(p);
+  const int W = rows_waves(p, *row_plan(p));
   return (p->n1 + W - 1) / W;
 }
 
-template <typename TS, typename T>
-static int wave_rows_t(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
-                       const void *f_true, double *partial, hipStream_t st) {
-  const FftPlan &fp = p->fft_row;
-  const int m = p->n2, M = fp.M;
-  const int W = rows_waves(p);
+// 1 = mixed radix, 2 = Bluestein, 0 = neither (block-wide engine)
+int wave_rows_algo(const ar_plan_s *p) {
+  const WavePlan *w = row_plan(p);
+  return w ? (w->bs ? 2 : 1) : 0;
+}
+int wave_cols_algo(const ar_plan_s *p) {
+  const WavePlan *w = col_plan(p);
+  return w ? (w->bs ? 2 : 1) : 0;
+}
+
+template <typename TS, typename T, bool BS>
+static int wave_rows_t(const ar_plan_s *p, const WavePlan &w, const void *in, void *out, int mode,
+                       double tau, const void *f_true, double *partial, hipStream_t st) {
+  const int m = p->n2, M = w.M;
+  const int W = rows_waves(p, w);
   const int blocks = (p->n1 + W - 1) / W;
-  const size_t smem = excl_pad(wlds_bytes(fp.w.twn, M, W, sizeof(T), rows_aux(p)),
-                               p->tune[AR_TUNE_ROW_EXCL]);
-  const WDesc wd = make_wdesc(fp.w);
+  const size_t smem =
+      excl_pad(wlds_bytes(w.twn, M, w.N, W, sizeof(T), rows_aux(p)), p->tune[AR_TUNE_ROW_EXCL]);
+  const WDesc wd = make_wdesc(w);
   const T alpha = T(std::sqrt((double)m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))));
   const T scale = T(std::sqrt(2.0 / M) / 4.0);
-  auto tw = static_cast<const V2<T> *>(fp.w.tw);
-  auto post = static_cast<const V2<T> *>(fp.post);
+  auto tw = static_cast<const V2<T> *>(w.tw);
+  auto post = static_cast<const V2<T> *>(p->fft_row.post);
+  auto chirp = static_cast<const V2<T> *>(w.chirp);
+  auto bhat = static_cast<const V2<T> *>(w.bhat);
   auto ti = static_cast<const TS *>(in);
   auto to = static_cast<TS *>(out);
   auto tf = static_cast<const TS *>(f_true);
   hipError_t e = hipSuccess;
 #define AR_WROWS(MODE)                                                                          \
-  e = allow_lds_w(rows_w_kernel<TS, T, MODE>, smem);                                            \
+  e = allow_lds_w(rows_w_kernel<TS, T, MODE, BS>, smem);                                        \
   if (e == hipSuccess) {                                                                        \
-    hipLaunchKernelGGL((rows_w_kernel<TS, T, MODE>), dim3(blocks), dim3(64 * W), smem, st, ti,  \
-                       to, p->n1, m, wd, tw, fp.w.drev, post, alpha, scale, T(tau), tf, partial); \
+    hipLaunchKernelGGL((rows_w_kernel<TS, T, MODE, BS>), dim3(blocks), dim3(64 * W), smem, st,  \
+                       ti, to, p->n1, m, wd, tw, w.drev, post, chirp, bhat, alpha, scale,        \
+                       T(tau), tf, partial);                                                    \
     e = hipGetLastError();                                                                      \
   }
   switch (mode) {
@@ -620,37 +813,47 @@ static int wave_rows_t(const ar_plan_s *p, const void *in, void *out, int mode, 
   return AR_OK;
 }
 
+template <typename TS, typename T>
+static int wave_rows_d(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
+                       const void *f_true, double *partial, hipStream_t st) {
+  const WavePlan &w = *row_plan(p);
+  if (w.bs) return wave_rows_t<TS, T, true>(p, w, in, out, mode, tau, f_true, partial, st);
+  return wave_rows_t<TS, T, false>(p, w, in, out, mode, tau, f_true, partial, st);
+}
+
 int wave_rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                      const void *f_true, double *partial, hipStream_t st) {
   if (p->dtype == AR_F64)
-    return wave_rows_t<double, double>(p, in, out, mode, tau, f_true, partial, st);
+    return wave_rows_d<double, double>(p, in, out, mode, tau, f_true, partial, st);
   if (p->dtype == AR_F32_ACC64)
-    return wave_rows_t<float, double>(p, in, out, mode, tau, f_true, partial, st);
-  return wave_rows_t<float, float>(p, in, out, mode, tau, f_true, partial, st);
+    return wave_rows_d<float, double>(p, in, out, mode, tau, f_true, partial, st);
+  return wave_rows_d<float, float>(p, in, out, mode, tau, f_true, partial, st);
 }
 
-template <typename TS, typename T>
-static int wave_cols_t(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
-  const FftPlan &fp = p->fft_col;
-  const int m = p->n1, M = fp.M;
-  const int W = cols_waves(p);
+template <typename TS, typename T, bool BS>
+static int wave_cols_t(const ar_plan_s *p, const WavePlan &w, const void *in, void *out, int mode,
+                       hipStream_t st) {
+  const int m = p->n1, M = w.M;
+  const int W = cols_waves(p, w);
   const int blocks = (p->n2 + W - 1) / W;
-  const size_t smem = excl_pad(wlds_bytes(fp.w.twn, M, W, sizeof(T), cols_aux(p)),
-                               p->tune[AR_TUNE_COL_EXCL]);
-  const WDesc wd = make_wdesc(fp.w);
+  const size_t smem =
+      excl_pad(wlds_bytes(w.twn, M, w.N, W, sizeof(T), cols_aux(p)), p->tune[AR_TUNE_COL_EXCL]);
+  const WDesc wd = make_wdesc(w);
   const T alpha = T(std::sqrt((double)m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))));
   const T scale = T(std::sqrt(2.0 / M) / 4.0);
-  auto tw = static_cast<const V2<T> *>(fp.w.tw);
-  auto post = static_cast<const V2<T> *>(fp.post);
+  auto tw = static_cast<const V2<T> *>(w.tw);
+  auto post = static_cast<const V2<T> *>(p->fft_col.post);
+  auto chirp = static_cast<const V2<T> *>(w.chirp);
+  auto bhat = static_cast<const V2<T> *>(w.bhat);
   auto ti = static_cast<const TS *>(in);
   auto to = static_cast<TS *>(out);
   auto td = static_cast<const T *>(p->d);
   hipError_t e = hipSuccess;
 #define AR_WCOLS(MODE)                                                                          \
-  e = allow_lds_w(cols_w_kernel<TS, T, MODE>, smem);                                            \
+  e = allow_lds_w(cols_w_kernel<TS, T, MODE, BS>, smem);                                        \
   if (e == hipSuccess) {                                                                        \
-    hipLaunchKernelGGL((cols_w_kernel<TS, T, MODE>), dim3(blocks), dim3(64 * W), smem, st, ti,  \
-                       to, m, p->n2, wd, tw, fp.w.drev, post, alpha, scale, td);                \
+    hipLaunchKernelGGL((cols_w_kernel<TS, T, MODE, BS>), dim3(blocks), dim3(64 * W), smem, st,  \
+                       ti, to, m, p->n2, wd, tw, w.drev, post, chirp, bhat, alpha, scale, td);  \
     e = hipGetLastError();                                                                      \
   }
   switch (mode) {
@@ -663,10 +866,17 @@ static int wave_cols_t(const ar_plan_s *p, const void *in, void *out, int mode, 
   return AR_OK;
 }
 
+template <typename TS, typename T>
+static int wave_cols_d(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
+  const WavePlan &w = *col_plan(p);
+  if (w.bs) return wave_cols_t<TS, T, true>(p, w, in, out, mode, st);
+  return wave_cols_t<TS, T, false>(p, w, in, out, mode, st);
+}
+
 int wave_cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
-  if (p->dtype == AR_F64) return wave_cols_t<double, double>(p, in, out, mode, st);
-  if (p->dtype == AR_F32_ACC64) return wave_cols_t<float, double>(p, in, out, mode, st);
-  return wave_cols_t<float, float>(p, in, out, mode, st);
+  if (p->dtype == AR_F64) return wave_cols_d<double, double>(p, in, out, mode, st);
+  if (p->dtype == AR_F32_ACC64) return wave_cols_d<float, double>(p, in, out, mode, st);
+  return wave_cols_d<float, float>(p, in, out, mode, st);
 }
 
 }  // namespace ar

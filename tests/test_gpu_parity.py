@@ -356,31 +356,83 @@ def test_batch_sizes_transform_and_blur():
             assert rel(host(y), O.precond_apply(X, d)) <= 2e-5
 
 
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("algo", [1, 2])
+@pytest.mark.parametrize("n1,n2", [(128, 96), (256, 300), (193, 385), (1024, 1024), (512, 129)])
+def test_transform_fft_forms(n1, n2, algo, dt):
+    """Both FFT forms of the DST-I (mixed radix where n - 1 factors over
+    codelet radices, Bluestein chirp-z for any length) against the oracle,
+    forward, inverse and the fused preconditioner column pass."""
+    say(f"fft form {algo} n=({n1},{n2}) {dt}")
+    H = synth.psf_random(2, 3, seed=5)
+    rng = np.random.default_rng(n1 + 3 * n2 + algo)
+    X = rng.standard_normal((n1, n2)).astype(NDT[dt]).astype(np.float64)
+    with P.Plan(n1, n2, H, dtype=dt) as plan:
+        plan.ar_plan_tune(P.AR_TUNE_ROW_ALGO, algo)
+        plan.ar_plan_tune(P.AR_TUNE_COL_ALGO, algo)
+        x = dev(X, TDT[dt])
+        c = torch.empty_like(x)
+        plan.ar_transform(x, c)
+        Cg = host(c)
+        e = rel(Cg, O.ar_fwd(X))
+        say(f"  fwd rel err {e:.2e}")
+        assert e <= TOL_T[dt], e
+        Cq = Cg.astype(NDT[dt]).astype(np.float64)
+        xr = torch.empty_like(x)
+        plan.ar_transform_inv(dev(Cq, TDT[dt]), xr)
+        e = rel(host(xr), O.ar_inv(Cq))
+        say(f"  inv rel err {e:.2e}")
+        assert e <= TOL_T[dt], e
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, 1e-2)
+        plan.ar_precond_solve(x, xr)
+        d = O.tikhonov(O.eigenvalues(H, n1, n2), 1e-2)
+        e = rel(host(xr), O.precond_apply(X, d))
+        say(f"  solve rel err {e:.2e}")
+        assert e <= TOL_D[dt], e
+
+
 @pytest.mark.parametrize("dt", ["f32", "f32x"])
 def test_tunables_do_not_change_results(dt):
-    """Every launch setting of the transform engine gives bitwise the same
-    preconditioner output; the autotuner picks one of them."""
-    n1, n2 = 300, 256          # n2 - 1 = 255 = 3 * 5 * 17: wave engine on rows
+    """For a fixed FFT form every launch setting of the transform engine
+    gives bitwise the same preconditioner output; the autotuner picks one
+    of the settings (and either FFT form)."""
+    n1, n2 = 300, 256          # n - 1 = 299 = 13 * 23 and 255 = 3 * 5 * 17
     H = synth.psf_random(3, 4, seed=2)
     Y = np.random.default_rng(1).standard_normal((n1, n2))
     with P.Plan(n1, n2, H, dtype=dt) as plan:
         plan.ar_precond_set(P.AR_FILTER_TIKHONOV, 1e-2)
         y = dev(Y, TDT[dt])
         z = torch.empty_like(y)
-        plan.ar_precond_solve(y, z)
-        ref = host(z)
-        for w in (1, 2, 4):
-            for x in (0, 1):
-                for key_w, key_x in ((P.AR_TUNE_ROW_WAVES, P.AR_TUNE_ROW_EXCL),
-                                     (P.AR_TUNE_COL_WAVES, P.AR_TUNE_COL_EXCL)):
-                    plan.ar_plan_tune(key_w, w)
-                    plan.ar_plan_tune(key_x, x)
-                    plan.ar_precond_solve(y, z)
-                    assert np.array_equal(host(z), ref)
+        refs = {}
+        for algo in (1, 2):
+            plan.ar_plan_tune(P.AR_TUNE_ROW_ALGO, algo)
+            plan.ar_plan_tune(P.AR_TUNE_COL_ALGO, algo)
+            for key in (P.AR_TUNE_ROW_WAVES, P.AR_TUNE_ROW_EXCL, P.AR_TUNE_COL_WAVES,
+                        P.AR_TUNE_COL_EXCL):
+                plan.ar_plan_tune(key, 0)
+            plan.ar_precond_solve(y, z)
+            ref = refs[algo] = host(z)
+            for w in (1, 2, 4):
+                for x in (0, 1):
+                    for key_w, key_x in ((P.AR_TUNE_ROW_WAVES, P.AR_TUNE_ROW_EXCL),
+                                         (P.AR_TUNE_COL_WAVES, P.AR_TUNE_COL_EXCL)):
+                        plan.ar_plan_tune(key_w, w)
+                        plan.ar_plan_tune(key_x, x)
+                        plan.ar_precond_solve(y, z)
+                        assert np.array_equal(host(z), ref)
+        assert rel(refs[1], refs[2]) <= TOL_D[dt]
         us = plan.ar_plan_autotune()
         assert us > 0
         assert plan.ar_plan_get_tune(P.AR_TUNE_ROW_WAVES) in (1, 2, 4)
+        ra = plan.ar_plan_get_tune(P.AR_TUNE_ROW_ALGO)
+        ca = plan.ar_plan_get_tune(P.AR_TUNE_COL_ALGO)
+        assert ra in (1, 2) and ca in (1, 2)
         plan.ar_precond_solve(y, z)
-        assert np.array_equal(host(z), ref)
+        if ra == ca:
+            assert np.array_equal(host(z), refs[ra])
+        else:
+            assert rel(host(z), refs[1]) <= TOL_D[dt]
         with pytest.raises(P.ArError):
             plan.ar_plan_tune(P.AR_TUNE_ROW_WAVES, 3)
+        with pytest.raises(P.ArError):
+            plan.ar_plan_tune(P.AR_TUNE_COL_ALGO, 3)

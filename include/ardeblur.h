@@ -195,6 +195,59 @@ int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream);
 int ar_iterate_profile(ar_plan_t p, const void *g, const void *x, int tmode, int precondition,
                        int reps, double *phase_us, void *stream);
 
+/* ------------------------------------------------------------------
+ * Batched executor: many independent deblurring problems of uneven sizes,
+ * each with its own plan (PSF, eigenvalues, filter), iterated together.
+ * Problems are grouped by PSF column half-width (one blur launch per group)
+ * and by image shape (one transform launch per group, sharing the FFT
+ * tables); every launch covers all problems of its group, and the whole
+ * run of `iters` iterations is captured once into a HIP graph that
+ * ar_batch_iterate replays with a single graph launch.
+ * ------------------------------------------------------------------ */
+typedef struct ar_batch_s *ar_batch_t;
+
+/* Create a batch over `count` plans (host array).  The plans must be
+ * distinct, share one dtype and device, and outlive the batch; the batch
+ * runs on their scratch buffers, so a plan must not be used on its own
+ * while a batch call that includes it is in flight.  Every image shape of
+ * the batch must fit the wave-per-sequence transform (n <= 2048 for
+ * AR_F32, n <= 1024 for the double-arithmetic dtypes).  `stream` is used
+ * for set-up copies and synchronized.
+ * Errors: AR_EINVAL (null, count < 1, repeated plan, mixed dtype/device),
+ * AR_EUNSUPPORTED, AR_EDEVICE, AR_ENOMEM. */
+int ar_batch_create(ar_batch_t *out, int count, const ar_plan_t *plans, void *stream);
+
+/* Autotuner of a batch: for every shape group, times each candidate
+ * transform setting (FFT form, waves per workgroup, CU-exclusive
+ * workgroups) on the batched launches themselves and stores the fastest
+ * in every plan of the group (batched launches use the settings of the
+ * group's first plan).
+ * *best_us (may be NULL) receives the tuned time of one batched
+ * preconditioner application.  Uses the plans' scratch; synchronizes. */
+int ar_batch_autotune(ar_batch_t b, double *best_us, void *stream);
+
+/* Run `iters` (D-)Landweber steps on every problem of the batch, exactly
+ * the recurrence of ar_deblur_iterate applied to each problem with its
+ * plan's filter.
+ *   g, x      : host arrays of `count` device pointers (problem i has its
+ *               plan's shape and dtype); x is in/out
+ *   f_true    : NULL or a host array of `count` device pointers
+ *   resnorm_host : NULL or count*iters doubles, [i * iters + k] = ||r_k|| of problem i
+ *   rre_host     : NULL or count*iters doubles (needs f_true)
+ *   best_it_host : NULL or count ints (needs f_true)
+ * The first call for a given (iters, tau, tmode, precondition, outputs,
+ * launch settings) captures the graph; later calls only update the
+ * device-side job tables and replay it.  Calls on one batch must be
+ * ordered (same stream, or synchronized between).
+ * Errors as ar_deblur_iterate; AR_ENONFINITE if any requested residual
+ * norm is not finite. */
+int ar_batch_iterate(ar_batch_t b, const void *const *g, void *const *x, int iters, double tau,
+                     int tmode, int precondition, const void *const *f_true,
+                     double *resnorm_host, double *rre_host, int *best_it_host, void *stream);
+
+/* Release a batch (not its plans).  NULL is a no-op returning AR_OK. */
+int ar_batch_destroy(ar_batch_t b);
+
 /* Thread-local message describing the last failure ("" if none). */
 const char *ar_last_error(void);
 

@@ -22,6 +22,7 @@ from ._lib import (  # noqa: F401
     AR_TUNE_ROW_EXCL,
     AR_TUNE_ROW_WAVES,
     ArError,
+    Batch,
     LIB_PATH,
     Plan,
     SIGNATURES,

@@ -48,6 +48,11 @@ SIGNATURES = [
     ("ar_plan_get_tune", _I, [_VP, _I, C.POINTER(_I)]),
     ("ar_plan_autotune", _I, [_VP, C.POINTER(_D), _VP]),
     ("ar_iterate_profile", _I, [_VP, _VP, _VP, _I, _I, _I, C.POINTER(_D), _VP]),
+    ("ar_batch_create", _I, [C.POINTER(_VP), _I, C.POINTER(_VP), _VP]),
+    ("ar_batch_autotune", _I, [_VP, C.POINTER(_D), _VP]),
+    ("ar_batch_iterate", _I, [_VP, C.POINTER(_VP), C.POINTER(_VP), _I, _D, _I, _I,
+                              C.POINTER(_VP), C.POINTER(_D), C.POINTER(_D), C.POINTER(_I), _VP]),
+    ("ar_batch_destroy", _I, [_VP]),
     ("ar_last_error", C.c_char_p, []),
     ("ar_version", C.c_char_p, []),
 ]
@@ -206,6 +211,71 @@ class Plan:
                 np.array(res[:]) if res is not None else None,
                 np.array(rre[:]) if rre is not None else None,
                 best.value if best is not None else None)
+
+
+def _ptr_array(ts):
+    arr = (C.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+class Batch:
+    """Owns an ``ar_batch_t`` over a list of :class:`Plan` (kept alive here)."""
+
+    def __init__(self, plans, stream=None):
+        self.plans = list(plans)
+        self.count = len(self.plans)
+        handles = (C.c_void_p * self.count)(*[p.handle.value for p in self.plans])
+        self._h = C.c_void_p()
+        _check(load().ar_batch_create(C.byref(self._h), self.count, handles, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            load().ar_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def ar_batch_autotune(self, stream=None):
+        us = C.c_double(0.0)
+        _check(load().ar_batch_autotune(self._h, C.byref(us), _stream(stream)))
+        return us.value
+
+    def ar_batch_iterate(self, g, x, iters, tau=1.0, tmode=AR_REBLUR, precondition=True,
+                         f_true=None, want_resnorm=False, want_rre=False, stream=None):
+        """g, x, f_true: lists of tensors.  Returns (status, resnorm[count, iters] or None,
+        rre[count, iters] or None, best_it[count] or None)."""
+        n = self.count
+        if len(g) != n or len(x) != n or (f_true is not None and len(f_true) != n):
+            raise ValueError("one tensor per problem expected")
+        gp, xp = _ptr_array(g), _ptr_array(x)
+        fp = _ptr_array(f_true) if f_true is not None else None
+        res = (C.c_double * (n * iters))() if want_resnorm and iters > 0 else None
+        rre = (C.c_double * (n * iters))() if want_rre and iters > 0 else None
+        best = (C.c_int * n)() if want_rre else None
+        rc = load().ar_batch_iterate(
+            self._h, gp, xp, int(iters), float(tau), int(tmode), int(bool(precondition)), fp,
+            C.cast(res, C.POINTER(C.c_double)) if res is not None else None,
+            C.cast(rre, C.POINTER(C.c_double)) if rre is not None else None,
+            C.cast(best, C.POINTER(C.c_int)) if best is not None else None,
+            _stream(stream))
+        if rc not in (0, -7):
+            _check(rc)
+        return (rc,
+                np.array(res[:]).reshape(n, iters) if res is not None else None,
+                np.array(rre[:]).reshape(n, iters) if rre is not None else None,
+                np.array(best[:]) if best is not None else None)
 
 
 def version():

@@ -96,20 +96,20 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // Q2 >= 0: compile-time column half-width (tap loop fully unrolled).
 // Q2 <  0: generic kernel with a runtime column half-width.
 template <typename TS, typename T, typename TO, int Q2>
-__global__ __launch_bounds__(NT) void conv_kernel(
-    const TS *__restrict__ in, TO *__restrict__ out, const T *__restrict__ w, int n1, int n2,
-    int q1, int q2rt, int o1, int o2, int m1, int m2, int zero_ext, const TS *__restrict__ gsub,
-    double *__restrict__ partial, int tiles_x) {
+__device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__restrict__ in,
+                                          TO *__restrict__ out, const T *__restrict__ w, int n1,
+                                          int n2, int q1, int q2rt, int o1, int o2, int m1, int m2,
+                                          int zero_ext, const TS *__restrict__ gsub,
+                                          double *__restrict__ partial_slot, int logical,
+                                          int tiles_x) {
   constexpr bool GEN = Q2 < 0;
   const int q2 = GEN ? q2rt : Q2;
   const int KW = 2 * q2 + 1;
   const int LW = TW + 2 * q2;
   const int pitch = (LW + 3) & ~3;
   const int LH = TH + 2 * q1;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   T *tile = reinterpret_cast<T *>(smem_raw);
 
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int ty_tile = logical / tiles_x, tx_tile = logical - ty_tile * tiles_x;
   const int r0 = ty_tile * TH, c0 = tx_tile * TW;
   const int ib1 = o1 + r0 - q1, ib2 = o2 + c0 - q2;
@@ -258,20 +258,51 @@ __global__ __launch_bounds__(NT) void conv_kernel(
       }
     }
   }
-  if (partial) {
+  if (partial_slot) {
     // the tile is no longer read: reuse LDS for the reduction
     double *red = reinterpret_cast<double *>(smem_raw);
     const double s = block_sum<T>(ss, red);
-    if (tid == 0) partial[blockIdx.x] = s;
+    if (tid == 0) *partial_slot = s;
   }
 }
+
+template <typename TS, typename T, typename TO, int Q2>
+__global__ __launch_bounds__(NT) void conv_kernel(
+    const TS *__restrict__ in, TO *__restrict__ out, const T *__restrict__ w, int n1, int n2,
+    int q1, int q2rt, int o1, int o2, int m1, int m2, int zero_ext, const TS *__restrict__ gsub,
+    double *__restrict__ partial, int tiles_x) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  conv_tile<TS, T, TO, Q2>(smem_raw, in, out, w, n1, n2, q1, q2rt, o1, o2, m1, m2, zero_ext, gsub,
+                           partial ? partial + blockIdx.x : nullptr,
+                           xcd_remap(blockIdx.x, gridDim.x), tiles_x);
+}
+
+// Batched form: workgroup b computes tile tiles[b].y of job tiles[b].x.
+// ext_mode: correlation onto the zero-extended grid (the first half of A^T).
+template <typename TS, typename T, typename TO, int Q2>
+__global__ __launch_bounds__(NT) void conv_batch_kernel(const ConvJob *__restrict__ jobs,
+                                                        const int2 *__restrict__ tiles, int k,
+                                                        int ext_mode) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int2 jt = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  const ConvJob J = jobs[jt.x];
+  const int q2 = Q2 < 0 ? J.q2 : Q2;
+  const int o1 = ext_mode ? -J.q1 : 0, o2 = ext_mode ? -q2 : 0;
+  const int m1 = J.n1 - 2 * o1, m2 = J.n2 - 2 * o2;
+  conv_tile<TS, T, TO, Q2>(smem_raw, static_cast<const TS *>(J.in), static_cast<TO *>(J.out),
+                           static_cast<const T *>(J.w), J.n1, J.n2, J.q1, q2, o1, o2, m1, m2,
+                           ext_mode, static_cast<const TS *>(J.gsub),
+                           J.part ? J.part + (size_t)k * J.nblk + jt.y : nullptr, jt.y,
+                           J.tiles_x);
+}
+
 
 // Fold of the extended-grid correlation back onto the FOV (transpose of the
 // AR extension): along each axis a ghost at 1 - t adds 2x to position 1 and
 // -1x to position 1 + t, a ghost at n + t adds 2x to n and -1x to n - t.
 template <typename TS, typename T>
-__global__ __launch_bounds__(256) void fold_kernel(const T *__restrict__ ext, TS *__restrict__ out,
-                                                   int n1, int n2, int q1, int q2) {
+__device__ __forceinline__ void fold_at(const T *__restrict__ ext, TS *__restrict__ out, int n1,
+                                        int n2, int q1, int q2) {
   const int j2 = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j1 = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (j1 >= n1 || j2 >= n2) return;
@@ -299,6 +330,19 @@ __global__ __launch_bounds__(256) void fold_kernel(const T *__restrict__ ext, TS
     acc += T(w1[a]) * s;
   }
   out[(size_t)j1 * n2 + j2] = TS(acc);
+}
+
+template <typename TS, typename T>
+__global__ __launch_bounds__(256) void fold_kernel(const T *__restrict__ ext, TS *__restrict__ out,
+                                                   int n1, int n2, int q1, int q2) {
+  fold_at<TS, T>(ext, out, n1, n2, q1, q2);
+}
+
+// Batched fold: blockIdx.z selects the job (in = extended grid, out = y).
+template <typename TS, typename T>
+__global__ __launch_bounds__(256) void fold_batch_kernel(const ConvJob *__restrict__ jobs) {
+  const ConvJob J = jobs[blockIdx.z];
+  fold_at<TS, T>(static_cast<const T *>(J.in), static_cast<TS *>(J.out), J.n1, J.n2, J.q1, J.q2);
 }
 
 template <typename TS, typename T, typename TO>
@@ -332,7 +376,75 @@ hipError_t launch_conv_t(const ar_plan_s *p, const void *in, void *out, const vo
   return hipGetLastError();
 }
 
+template <typename TS, typename T, typename TO>
+hipError_t launch_conv_batch_t(int q2, const ConvJob *jobs, const int2 *tiles, int ntiles, int k,
+                               int ext_mode, size_t smem, hipStream_t st) {
+  if (smem < 64 * sizeof(double)) smem = 64 * sizeof(double);
+#define AR_CONVB_CASE(QQ)                                                                        \
+  case QQ:                                                                                       \
+    hipLaunchKernelGGL((conv_batch_kernel<TS, T, TO, QQ>), dim3(ntiles), dim3(NT), smem, st,     \
+                       jobs, tiles, k, ext_mode);                                               \
+    break;
+  switch (q2) {
+    AR_CONVB_CASE(0) AR_CONVB_CASE(1) AR_CONVB_CASE(2) AR_CONVB_CASE(3) AR_CONVB_CASE(4)
+    AR_CONVB_CASE(5) AR_CONVB_CASE(6) AR_CONVB_CASE(7) AR_CONVB_CASE(8) AR_CONVB_CASE(9)
+    AR_CONVB_CASE(10) AR_CONVB_CASE(11) AR_CONVB_CASE(12) AR_CONVB_CASE(13) AR_CONVB_CASE(14)
+    AR_CONVB_CASE(15)
+    default:
+      hipLaunchKernelGGL((conv_batch_kernel<TS, T, TO, -1>), dim3(ntiles), dim3(NT), smem, st,
+                         jobs, tiles, k, ext_mode);
+  }
+#undef AR_CONVB_CASE
+  return hipGetLastError();
+}
+
 }  // namespace
+
+int conv_tiles(int m1, int m2, int *tiles_x) {
+  const int tx = (m2 + TW - 1) / TW;
+  if (tiles_x) *tiles_x = tx;
+  return ((m1 + TH - 1) / TH) * tx;
+}
+
+size_t conv_batch_smem(int dtype, int q1max, int q2) {
+  const size_t cs = dtype == AR_F32 ? sizeof(float) : sizeof(double);
+  const size_t LH = TH + 2 * (size_t)q1max, LW = TW + 2 * (size_t)q2;
+  return (LH * ((LW + 3) & ~(size_t)3) + (2 * (size_t)q1max + 1) * (2 * q2 + 1)) * cs;
+}
+
+int conv_batch_launch(int dtype, int q2, const ConvJob *jobs, const int2 *tiles, int ntiles, int k,
+                      bool ext_mode, size_t smem, hipStream_t st) {
+  if (smem > 64 * 1024) return fail(AR_EUNSUPPORTED, "PSF too large for the LDS halo tile");
+  if (ntiles == 0) return AR_OK;
+  const int em = ext_mode ? 1 : 0;
+  hipError_t e;
+  if (dtype == AR_F64)
+    e = launch_conv_batch_t<double, double, double>(q2, jobs, tiles, ntiles, k, em, smem, st);
+  else if (dtype == AR_F32_ACC64 && ext_mode)
+    e = launch_conv_batch_t<float, double, double>(q2, jobs, tiles, ntiles, k, em, smem, st);
+  else if (dtype == AR_F32_ACC64)
+    e = launch_conv_batch_t<float, double, float>(q2, jobs, tiles, ntiles, k, em, smem, st);
+  else
+    e = launch_conv_batch_t<float, float, float>(q2, jobs, tiles, ntiles, k, em, smem, st);
+  if (e != hipSuccess) return hip_fail(e, "conv_batch_kernel launch");
+  return AR_OK;
+}
+
+int fold_batch_launch(int dtype, const ConvJob *jobs, int count, int n1max, int n2max, int qmax,
+                      hipStream_t st) {
+  if (qmax > 36) return fail(AR_EUNSUPPORTED, "adjoint fold supports q <= 36");
+  if (count == 0) return AR_OK;
+  dim3 grid((n2max + 63) / 64, (n1max + 3) / 4, count);
+  if (dtype == AR_F64)
+    hipLaunchKernelGGL((fold_batch_kernel<double, double>), grid, dim3(256), 0, st, jobs);
+  else if (dtype == AR_F32_ACC64)
+    hipLaunchKernelGGL((fold_batch_kernel<float, double>), grid, dim3(256), 0, st, jobs);
+  else
+    hipLaunchKernelGGL((fold_batch_kernel<float, float>), grid, dim3(256), 0, st, jobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "fold_batch_kernel launch");
+  return AR_OK;
+}
 
 int conv_blocks(const ar_plan_s *p, int m1, int m2) {
   (void)p;

@@ -137,6 +137,41 @@ struct ar_plan_s {
 
 namespace ar {
 
+// ---------------------------------------------------------------- batches
+
+// One problem of a batched convolution launch (device array).  The blur
+// reads `in` (n1 x n2), writes `out` (n1 x n2, or the (n1+2q1) x (n2+2q2)
+// extended grid in the compute type for the adjoint's correlation), with
+// correlation weights `w` ((2q1+1) x (2q2+1), compute type); `gsub` makes
+// it write gsub - A in and FP64 partial norms to part[k * nblk + tile].
+struct ConvJob {
+  const void *in;
+  void *out;
+  const void *gsub;
+  const void *w;
+  double *part;
+  int n1, n2, q1, q2;
+  int tiles_x, nblk;
+};
+
+// One problem of a batched transform / update launch (device array),
+// indexed by blockIdx.y: `aux` is d (column pass), f_true (row update) or
+// nothing; partial sums go to part[k * nblk + blockIdx.x].
+struct XJob {
+  const void *in;
+  void *out;
+  const void *aux;
+  double *part;
+  int n1, n2, nblk, pad;
+};
+
+// Fixed-order sums of rows of per-problem partials: out[r] = sum_c part[r * nblk + c]
+struct RedJob {
+  const double *part;
+  double *out;
+  int nblk, pad;
+};
+
 // ---------------------------------------------------------------- launchers
 
 // blur kernels (ar_blur.hip)
@@ -147,6 +182,16 @@ int conv_launch(const ar_plan_s *p, const void *in, void *out, const void *w, in
                 int *nblocks_out, hipStream_t st, bool out_compute = false);
 int conv_blocks(const ar_plan_s *p, int m1, int m2);
 int fold_launch(const ar_plan_s *p, const void *ext, void *out, hipStream_t st);
+// batched blur: every job shares dtype and q2 (the compile-time tap width);
+// tiles[b] = (job, tile of that job) for workgroup b; k selects the partials
+// of iteration k; ext_mode: correlation onto the zero-extended grid (A^T).
+size_t conv_batch_smem(int dtype, int q1max, int q2);
+int conv_batch_launch(int dtype, int q2, const ConvJob *jobs, const int2 *tiles, int ntiles, int k,
+                      bool ext_mode, size_t smem, hipStream_t st);
+int conv_tiles(int m1, int m2, int *tiles_x);
+// batched fold of the extended-grid correlation (in = ext, out = y)
+int fold_batch_launch(int dtype, const ConvJob *jobs, int count, int n1max, int n2max,
+                      int qmax, hipStream_t st);
 
 // transform kernels (ar_fft.hip)
 enum RowMode { ROW_FWD = 0, ROW_INV = 1, ROW_INV_UPDATE = 2 };
@@ -173,6 +218,12 @@ int wave_cols_algo(const ar_plan_s *p);
 int wave_rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                      const void *f_true, double *partial, hipStream_t st);
 int wave_cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st);
+// batched forms: `count` problems of the leader's shape and dtype, one per
+// blockIdx.y, with the leader's tables and launch settings
+int wave_rows_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, int mode,
+                           double tau, int k, hipStream_t st);
+int wave_cols_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, int mode,
+                           hipStream_t st);
 
 // plan-time and helper kernels (ar_plan.hip)
 int spectrum_launch(ar_plan_s *p, hipStream_t st);
@@ -183,5 +234,12 @@ int axpy_blocks(const ar_plan_s *p);
 int reduce_rows_launch(const double *partials, int rows, int cols, double *out, hipStream_t st);
 int sumsq_launch(const ar_plan_s *p, const void *x, double *partial, int *nblocks_out,
                  hipStream_t st);
+// batched elementwise kernels: grid (nblk, count); x = job.out, y = job.in,
+// f = job.aux
+int axpy_batch_launch(int dtype, const XJob *jobs, int count, int nblk, double tau, int k,
+                      hipStream_t st);
+int sumsq_batch_launch(int dtype, const XJob *jobs, int count, int nblk, hipStream_t st);
+int reduce_batch_launch(const RedJob *jobs, int count, int rows, hipStream_t st);
+int elem_blocks_n(size_t total);
 
 }  // namespace ar

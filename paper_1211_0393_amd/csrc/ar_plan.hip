@@ -163,6 +163,58 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const double *__restri
   if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
+// Batched forms: blockIdx.y selects the job (x = out, y = in, f = aux).
+template <typename T>
+__global__ __launch_bounds__(256) void axpy_batch_kernel(const XJob *__restrict__ jobs, T tau,
+                                                         int kit) {
+  __shared__ double red[4];
+  const XJob J = jobs[blockIdx.y];
+  T *x = static_cast<T *>(J.out);
+  const T *y = static_cast<const T *>(J.in);
+  const T *f = static_cast<const T *>(J.aux);
+  const size_t total = (size_t)J.n1 * J.n2;
+  double ss = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const T xn = x[e] + tau * y[e];
+    x[e] = xn;
+    if (f) {
+      const double df = (double)xn - (double)f[e];
+      ss += df * df;
+    }
+  }
+  if (J.part) {
+    const double s = block_sum(ss, red);
+    if (threadIdx.x == 0) J.part[(size_t)kit * J.nblk + blockIdx.x] = s;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_batch_kernel(const XJob *__restrict__ jobs) {
+  __shared__ double red[4];
+  const XJob J = jobs[blockIdx.y];
+  const T *x = static_cast<const T *>(J.in);
+  const size_t total = (size_t)J.n1 * J.n2;
+  double ss = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double v = (double)x[e];
+    ss += v * v;
+  }
+  const double s = block_sum(ss, red);
+  if (threadIdx.x == 0 && J.part) J.part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void reduce_batch_kernel(const RedJob *__restrict__ jobs) {
+  __shared__ double red[4];
+  const RedJob J = jobs[blockIdx.y];
+  const double *row = J.part + (size_t)blockIdx.x * J.nblk;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < J.nblk; c += blockDim.x) s += row[c];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) J.out[blockIdx.x] = t;
+}
+
 int elem_blocks(size_t total) {
   size_t b = (total + 255) / 256;
   if (b > kElemBlocks) b = kElemBlocks;
@@ -210,6 +262,38 @@ int filter_launch(ar_plan_s *p, int filter, double param, hipStream_t st) {
 }
 
 int axpy_blocks(const ar_plan_s *p) { return elem_blocks((size_t)p->n1 * p->n2); }
+
+int elem_blocks_n(size_t total) { return elem_blocks(total); }
+
+int axpy_batch_launch(int dtype, const XJob *jobs, int count, int nblk, double tau, int k,
+                      hipStream_t st) {
+  if (count == 0) return AR_OK;
+  const dim3 grid(nblk, count);
+  if (dtype == AR_F64)
+    hipLaunchKernelGGL(axpy_batch_kernel<double>, grid, dim3(256), 0, st, jobs, tau, k);
+  else
+    hipLaunchKernelGGL(axpy_batch_kernel<float>, grid, dim3(256), 0, st, jobs, (float)tau, k);
+  AR_HIP(hipGetLastError());
+  return AR_OK;
+}
+
+int sumsq_batch_launch(int dtype, const XJob *jobs, int count, int nblk, hipStream_t st) {
+  if (count == 0) return AR_OK;
+  const dim3 grid(nblk, count);
+  if (dtype == AR_F64)
+    hipLaunchKernelGGL(sumsq_batch_kernel<double>, grid, dim3(256), 0, st, jobs);
+  else
+    hipLaunchKernelGGL(sumsq_batch_kernel<float>, grid, dim3(256), 0, st, jobs);
+  AR_HIP(hipGetLastError());
+  return AR_OK;
+}
+
+int reduce_batch_launch(const RedJob *jobs, int count, int rows, hipStream_t st) {
+  if (count == 0 || rows == 0) return AR_OK;
+  hipLaunchKernelGGL(reduce_batch_kernel, dim3(rows, count), dim3(256), 0, st, jobs);
+  AR_HIP(hipGetLastError());
+  return AR_OK;
+}
 
 int axpy_launch(const ar_plan_s *p, void *x, const void *yv, double tau, const void *f_true,
                 double *partial, int *nblocks_out, hipStream_t st) {

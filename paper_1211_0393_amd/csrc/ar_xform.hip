@@ -343,8 +343,16 @@ __global__ __launch_bounds__(256) void rows_w_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int n1, int m, WDesc wd,
     const V2<T> *__restrict__ tw, const int *__restrict__ drev, const V2<T> *__restrict__ post,
     const V2<T> *__restrict__ chirp, const V2<T> *__restrict__ bhat, T alpha, T scale, T tau,
-    const TS *__restrict__ f_true, double *__restrict__ partial) {
+    const TS *__restrict__ f_true, double *__restrict__ partial, const XJob *__restrict__ jobs,
+    int kit) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (jobs) {  // batched launch: problem blockIdx.y
+    const XJob J = jobs[blockIdx.y];
+    in = static_cast<const TS *>(J.in);
+    out = static_cast<TS *>(J.out);
+    f_true = static_cast<const TS *>(J.aux);
+    partial = J.part ? J.part + (size_t)kit * J.nblk : nullptr;
+  }
   const int M = wd.M, N = wd.N;
   const int W = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -431,8 +439,14 @@ __global__ __launch_bounds__(256) void cols_w_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int m, int n2, WDesc wd,
     const V2<T> *__restrict__ tw, const int *__restrict__ drev, const V2<T> *__restrict__ post,
     const V2<T> *__restrict__ chirp, const V2<T> *__restrict__ bhat, T alpha, T scale,
-    const T *__restrict__ dflt) {
+    const T *__restrict__ dflt, const XJob *__restrict__ jobs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (jobs) {  // batched launch: problem blockIdx.y
+    const XJob J = jobs[blockIdx.y];
+    in = static_cast<const TS *>(J.in);
+    out = static_cast<TS *>(J.out);
+    dflt = static_cast<const T *>(J.aux);
+  }
   const int M = wd.M, N = wd.N;
   const int W = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -778,10 +792,12 @@ int wave_cols_algo(const ar_plan_s *p) {
 
 template <typename TS, typename T, bool BS>
 static int wave_rows_t(const ar_plan_s *p, const WavePlan &w, const void *in, void *out, int mode,
-                       double tau, const void *f_true, double *partial, hipStream_t st) {
+                       double tau, const void *f_true, double *partial, const XJob *jobs,
+                       int count, int kit, hipStream_t st) {
   const int m = p->n2, M = w.M;
   const int W = rows_waves(p, w);
   const int blocks = (p->n1 + W - 1) / W;
+  const dim3 grid(blocks, count);
   const size_t smem =
       excl_pad(wlds_bytes(w.twn, M, w.N, W, sizeof(T), rows_aux(p)), p->tune[AR_TUNE_ROW_EXCL]);
   const WDesc wd = make_wdesc(w);
@@ -798,9 +814,9 @@ static int wave_rows_t(const ar_plan_s *p, const WavePlan &w, const void *in, vo
 #define AR_WROWS(MODE)                                                                          \
   e = allow_lds_w(rows_w_kernel<TS, T, MODE, BS>, smem);                                        \
   if (e == hipSuccess) {                                                                        \
-    hipLaunchKernelGGL((rows_w_kernel<TS, T, MODE, BS>), dim3(blocks), dim3(64 * W), smem, st,  \
-                       ti, to, p->n1, m, wd, tw, w.drev, post, chirp, bhat, alpha, scale,        \
-                       T(tau), tf, partial);                                                    \
+    hipLaunchKernelGGL((rows_w_kernel<TS, T, MODE, BS>), grid, dim3(64 * W), smem, st, ti, to, \
+                       p->n1, m, wd, tw, w.drev, post, chirp, bhat, alpha, scale, T(tau), tf,    \
+                       partial, jobs, kit);                                                     \
     e = hipGetLastError();                                                                      \
   }
   switch (mode) {
@@ -815,27 +831,47 @@ static int wave_rows_t(const ar_plan_s *p, const WavePlan &w, const void *in, vo
 
 template <typename TS, typename T>
 static int wave_rows_d(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
-                       const void *f_true, double *partial, hipStream_t st) {
+                       const void *f_true, double *partial, const XJob *jobs, int count, int kit,
+                       hipStream_t st) {
   const WavePlan &w = *row_plan(p);
-  if (w.bs) return wave_rows_t<TS, T, true>(p, w, in, out, mode, tau, f_true, partial, st);
-  return wave_rows_t<TS, T, false>(p, w, in, out, mode, tau, f_true, partial, st);
+  if (w.bs)
+    return wave_rows_t<TS, T, true>(p, w, in, out, mode, tau, f_true, partial, jobs, count, kit,
+                                    st);
+  return wave_rows_t<TS, T, false>(p, w, in, out, mode, tau, f_true, partial, jobs, count, kit,
+                                   st);
+}
+
+static int wave_rows_any(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
+                         const void *f_true, double *partial, const XJob *jobs, int count,
+                         int kit, hipStream_t st) {
+  if (p->dtype == AR_F64)
+    return wave_rows_d<double, double>(p, in, out, mode, tau, f_true, partial, jobs, count, kit,
+                                       st);
+  if (p->dtype == AR_F32_ACC64)
+    return wave_rows_d<float, double>(p, in, out, mode, tau, f_true, partial, jobs, count, kit,
+                                      st);
+  return wave_rows_d<float, float>(p, in, out, mode, tau, f_true, partial, jobs, count, kit, st);
 }
 
 int wave_rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                      const void *f_true, double *partial, hipStream_t st) {
-  if (p->dtype == AR_F64)
-    return wave_rows_d<double, double>(p, in, out, mode, tau, f_true, partial, st);
-  if (p->dtype == AR_F32_ACC64)
-    return wave_rows_d<float, double>(p, in, out, mode, tau, f_true, partial, st);
-  return wave_rows_d<float, float>(p, in, out, mode, tau, f_true, partial, st);
+  return wave_rows_any(p, in, out, mode, tau, f_true, partial, nullptr, 1, 0, st);
+}
+
+int wave_rows_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, int mode,
+                           double tau, int k, hipStream_t st) {
+  if (count == 0) return AR_OK;
+  if (!wave_rows_ok(lead)) return fail(AR_EUNSUPPORTED, "batched transform: row length too large");
+  return wave_rows_any(lead, nullptr, nullptr, mode, tau, nullptr, nullptr, jobs, count, k, st);
 }
 
 template <typename TS, typename T, bool BS>
 static int wave_cols_t(const ar_plan_s *p, const WavePlan &w, const void *in, void *out, int mode,
-                       hipStream_t st) {
+                       const XJob *jobs, int count, hipStream_t st) {
   const int m = p->n1, M = w.M;
   const int W = cols_waves(p, w);
   const int blocks = (p->n2 + W - 1) / W;
+  const dim3 grid(blocks, count);
   const size_t smem =
       excl_pad(wlds_bytes(w.twn, M, w.N, W, sizeof(T), cols_aux(p)), p->tune[AR_TUNE_COL_EXCL]);
   const WDesc wd = make_wdesc(w);
@@ -852,8 +888,8 @@ static int wave_cols_t(const ar_plan_s *p, const WavePlan &w, const void *in, vo
 #define AR_WCOLS(MODE)                                                                          \
   e = allow_lds_w(cols_w_kernel<TS, T, MODE, BS>, smem);                                        \
   if (e == hipSuccess) {                                                                        \
-    hipLaunchKernelGGL((cols_w_kernel<TS, T, MODE, BS>), dim3(blocks), dim3(64 * W), smem, st,  \
-                       ti, to, m, p->n2, wd, tw, w.drev, post, chirp, bhat, alpha, scale, td);  \
+    hipLaunchKernelGGL((cols_w_kernel<TS, T, MODE, BS>), grid, dim3(64 * W), smem, st, ti, to, \
+                       m, p->n2, wd, tw, w.drev, post, chirp, bhat, alpha, scale, td, jobs);   \
     e = hipGetLastError();                                                                      \
   }
   switch (mode) {
@@ -867,16 +903,31 @@ static int wave_cols_t(const ar_plan_s *p, const WavePlan &w, const void *in, vo
 }
 
 template <typename TS, typename T>
-static int wave_cols_d(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
+static int wave_cols_d(const ar_plan_s *p, const void *in, void *out, int mode, const XJob *jobs,
+                       int count, hipStream_t st) {
   const WavePlan &w = *col_plan(p);
-  if (w.bs) return wave_cols_t<TS, T, true>(p, w, in, out, mode, st);
-  return wave_cols_t<TS, T, false>(p, w, in, out, mode, st);
+  if (w.bs) return wave_cols_t<TS, T, true>(p, w, in, out, mode, jobs, count, st);
+  return wave_cols_t<TS, T, false>(p, w, in, out, mode, jobs, count, st);
+}
+
+static int wave_cols_any(const ar_plan_s *p, const void *in, void *out, int mode,
+                         const XJob *jobs, int count, hipStream_t st) {
+  if (p->dtype == AR_F64) return wave_cols_d<double, double>(p, in, out, mode, jobs, count, st);
+  if (p->dtype == AR_F32_ACC64)
+    return wave_cols_d<float, double>(p, in, out, mode, jobs, count, st);
+  return wave_cols_d<float, float>(p, in, out, mode, jobs, count, st);
 }
 
 int wave_cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
-  if (p->dtype == AR_F64) return wave_cols_d<double, double>(p, in, out, mode, st);
-  if (p->dtype == AR_F32_ACC64) return wave_cols_d<float, double>(p, in, out, mode, st);
-  return wave_cols_d<float, float>(p, in, out, mode, st);
+  return wave_cols_any(p, in, out, mode, nullptr, 1, st);
+}
+
+int wave_cols_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, int mode,
+                           hipStream_t st) {
+  if (count == 0) return AR_OK;
+  if (!wave_cols_ok(lead))
+    return fail(AR_EUNSUPPORTED, "batched transform: column length too large");
+  return wave_cols_any(lead, nullptr, nullptr, mode, jobs, count, st);
 }
 
 }  // namespace ar

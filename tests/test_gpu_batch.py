@@ -1,0 +1,237 @@
+"""Batched executor (ar_batch_*) through the C ABI.
+
+Every problem of a batch runs the same recurrence as ar_deblur_iterate on
+its own plan, so
+  * the iterates equal the single-plan runs bitwise (same kernels, same
+    per-element arithmetic, same launch settings per shape group), and the
+    FP64 scalars agree to 1e-12 (partial sums are grouped differently);
+  * FP64 batches match the oracle's trajectory to 1e-12 per problem;
+  * FP32 batches meet the one-step parity bound of the single-plan tests
+    on sampled problems of the full 256-problem workload.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_1211_0393_amd as P  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TDT = {"f32": torch.float32, "f32x": torch.float32, "f64": torch.float64}
+NDT = {"f32": np.float32, "f32x": np.float32, "f64": np.float64}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dt):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype=dt)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+# (n1, n2, q1, q2): two problems share a shape, three share q2, one is
+# rectangular with q1 != q2, one needs the Bluestein FFT (n - 1 = 127)
+SMALL = [(33, 40, 3, 4), (48, 48, 2, 2), (33, 40, 1, 4), (64, 64, 4, 4), (29, 61, 5, 4),
+         (128, 20, 3, 1)]
+
+
+def small_problems(dt):
+    out = []
+    for i, (n1, n2, q1, q2) in enumerate(SMALL):
+        H = synth.psf_gauss_shifted(q1, q2, 1.0 + 0.3 * i, 1.5, shift=(0.3, -0.4))
+        F = synth.phantom(n1, n2, 4, 2, seed=50 + i).astype(NDT[dt]).astype(np.float64)
+        E = synth.noise_field(n1, n2, seed=70 + i)
+        G = O.observe(F, H, E, 0.01).astype(NDT[dt]).astype(np.float64)
+        out.append((F, H, G, 0.05 + 0.02 * i))
+    return out
+
+
+@pytest.mark.parametrize("dt", ["f32", "f32x", "f64"])
+@pytest.mark.parametrize("tmode", [P.AR_REBLUR, P.AR_ADJOINT])
+@pytest.mark.parametrize("precondition", [True, False])
+def test_batch_equals_single_plans(dt, tmode, precondition):
+    say(f"batch vs single {dt} tmode={tmode} pre={precondition}")
+    K = 4
+    probs = small_problems(dt)
+    plans = [P.Plan(G.shape[0], G.shape[1], H, dtype=dt) for (F, H, G, a) in probs]
+    try:
+        for pl, (F, H, G, a) in zip(plans, probs):
+            pl.ar_precond_set(P.AR_FILTER_TIKHONOV, a)
+        gs = [dev(G, TDT[dt]) for (F, H, G, a) in probs]
+        fs = [dev(F, TDT[dt]) for (F, H, G, a) in probs]
+        xs = [torch.zeros_like(g) for g in gs]
+        with P.Batch(plans) as b:
+            rc, res, rre, best = b.ar_batch_iterate(gs, xs, K, tmode=tmode,
+                                                    precondition=precondition, f_true=fs,
+                                                    want_resnorm=True, want_rre=True)
+            assert rc == 0
+            for i, pl in enumerate(plans):
+                x1 = torch.zeros_like(gs[i])
+                rc1, r1, e1, b1 = pl.ar_deblur_iterate(gs[i], x1, K, tmode=tmode,
+                                                       precondition=precondition, f_true=fs[i],
+                                                       want_resnorm=True, want_rre=True)
+                assert rc1 == 0
+                assert np.array_equal(host(xs[i]), host(x1)), i
+                assert np.max(np.abs(res[i] - r1) / r1) <= 1e-12
+                assert np.max(np.abs(rre[i] - e1) / e1) <= 1e-12
+                assert best[i] == b1
+            # a second call with other buffers reuses the captured graph
+            xs2 = [torch.zeros_like(g) for g in gs]
+            rc, res2, _, _ = b.ar_batch_iterate(gs, xs2, K, tmode=tmode,
+                                                precondition=precondition, f_true=fs,
+                                                want_resnorm=True, want_rre=True)
+            assert rc == 0
+            for i in range(len(probs)):
+                assert np.array_equal(host(xs2[i]), host(xs[i]))
+            assert np.array_equal(res2, res)
+    finally:
+        for pl in plans:
+            pl.close()
+
+
+@pytest.mark.parametrize("tmode", [P.AR_REBLUR, P.AR_ADJOINT])
+def test_batch_f64_matches_oracle(tmode):
+    """FP64 batch against the oracle's trajectory, every problem, 1e-12."""
+    K = 5
+    tm = "reblur" if tmode == P.AR_REBLUR else "adjoint"
+    probs = small_problems("f64")
+    plans = [P.Plan(G.shape[0], G.shape[1], H, dtype="f64") for (F, H, G, a) in probs]
+    try:
+        for pl, (F, H, G, a) in zip(plans, probs):
+            pl.ar_precond_set(P.AR_FILTER_TIKHONOV, a)
+        gs = [dev(G, torch.float64) for (F, H, G, a) in probs]
+        fs = [dev(F, torch.float64) for (F, H, G, a) in probs]
+        xs = [torch.zeros_like(g) for g in gs]
+        with P.Batch(plans) as b:
+            rc, res, rre, best = b.ar_batch_iterate(gs, xs, K, tmode=tmode, f_true=fs,
+                                                    want_resnorm=True, want_rre=True)
+            assert rc == 0
+        for i, (F, H, G, a) in enumerate(probs):
+            ref = O.iterate(G, H, K, alpha=a, F_true=F, tmode=tm)
+            e = rel(host(xs[i]), ref["x"])
+            say(f"  problem {i} {G.shape} rel err {e:.2e}")
+            assert e <= 1e-12
+            assert np.max(np.abs(res[i] - ref["resnorm"]) / ref["resnorm"]) <= 1e-12
+            assert np.max(np.abs(rre[i] - ref["rre"]) / ref["rre"]) <= 1e-12
+            assert best[i] == ref["best_it"]
+    finally:
+        for pl in plans:
+            pl.close()
+
+
+def test_batch_autotune_and_recapture():
+    """Autotuning changes launch settings only within parity; a different
+    iteration count captures a new graph; zero iterations leave x alone."""
+    probs = small_problems("f64")
+    plans = [P.Plan(G.shape[0], G.shape[1], H, dtype="f64") for (F, H, G, a) in probs]
+    try:
+        for pl, (F, H, G, a) in zip(plans, probs):
+            pl.ar_precond_set(P.AR_FILTER_TIKHONOV, a)
+        gs = [dev(G, torch.float64) for (F, H, G, a) in probs]
+        with P.Batch(plans) as b:
+            us = b.ar_batch_autotune()
+            assert us > 0
+            for K in (3, 1, 3):
+                xs = [torch.zeros_like(g) for g in gs]
+                rc, _, _, _ = b.ar_batch_iterate(gs, xs, K)
+                assert rc == 0
+                for i, (F, H, G, a) in enumerate(probs):
+                    ref = O.iterate(G, H, K, alpha=a)
+                    assert rel(host(xs[i]), ref["x"]) <= 1e-12
+            xs = [torch.ones_like(g) for g in gs]
+            rc, _, _, _ = b.ar_batch_iterate(gs, xs, 0)
+            assert rc == 0 and all(bool(torch.all(x == 1)) for x in xs)
+    finally:
+        for pl in plans:
+            pl.close()
+
+
+def test_batch_errors():
+    H = synth.psf_random(1, 1, seed=3)
+    a = P.Plan(16, 16, H, dtype="f32")
+    c = P.Plan(16, 16, H, dtype="f64")
+    try:
+        with pytest.raises(P.ArError) as ei:
+            P.Batch([a, a])
+        assert ei.value.status == -1
+        with pytest.raises(P.ArError) as ei:
+            P.Batch([a, c])
+        assert ei.value.status == -1
+        with P.Batch([a]) as b:
+            g = torch.zeros(16, 16, device=DEV)
+            with pytest.raises(P.ArError) as ei:
+                b.ar_batch_iterate([g], [g], 2)
+            assert ei.value.status == -4
+    finally:
+        a.close()
+        c.close()
+
+
+def test_batch_full_256_problems():
+    """The 256-problem workload (n in {128,...,512}, Gaussian PSFs 7..21,
+    alpha 5e-3, FP32) in the launch configuration the benchmark times:
+    sampled problems equal their single-plan runs bitwise after 3
+    iterations, and meet the FP32 one-step parity bound (6e-5, as the
+    single-plan 1024^2 test) against the oracle."""
+    count, K = 256, 3
+    sample = [0, 1, 2, 3]
+    probs = [synth.batch_problem(i) for i in range(count)]
+    say(f"batch of {count}: sizes {sorted(set(p[3]['n'] for p in probs))}")
+    plans = []
+    try:
+        gs, xs = [], []
+        Gs = {}
+        for i, (F, H, E, prm) in enumerate(probs):
+            n = prm["n"]
+            pl = P.Plan(n, n, H, dtype="f32")
+            pl.ar_precond_set(P.AR_FILTER_TIKHONOV, prm["alpha"])
+            plans.append(pl)
+            if i in sample:
+                G = O.observe(F, H, E, prm["nu"]).astype(np.float32).astype(np.float64)
+                Gs[i] = G
+                g = dev(G, torch.float32)
+            else:
+                f = dev(F, torch.float32)
+                g = torch.empty_like(f)
+                pl.ar_blur_apply(f, g)
+            gs.append(g)
+            xs.append(torch.zeros_like(g))
+        with P.Batch(plans) as b:
+            b.ar_batch_autotune()
+            rc, res, _, _ = b.ar_batch_iterate(gs, xs, K - 1, want_resnorm=True)
+            assert rc == 0 and np.all(np.isfinite(res))
+            Xk = {i: host(xs[i]) for i in sample}
+            rc, _, _, _ = b.ar_batch_iterate(gs, xs, 1)
+            assert rc == 0
+        for i in sample:
+            F, H, E, prm = probs[i]
+            n = prm["n"]
+            d = O.tikhonov(O.eigenvalues(H, n, n), prm["alpha"])
+            Xo, _ = O.landweber_step(Xk[i], Gs[i], H, d=d)
+            e = rel(host(xs[i]), Xo)
+            say(f"  problem {i} n={n} psf={H.shape} one-step rel err {e:.2e}")
+            assert e <= 6e-5
+            # the same problem on its own plan, bitwise
+            x1 = torch.zeros_like(gs[i])
+            plans[i].ar_deblur_iterate(gs[i], x1, K)
+            assert np.array_equal(host(x1), host(xs[i]))
+    finally:
+        for pl in plans:
+            pl.close()

@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="skip the plan autotuner")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     return ap.parse_args()
 
 
@@ -91,6 +92,58 @@ def cpu_baseline(F, H, E, p, iters):
             "sample": f"{iters} FP64 D-Landweber iterations of the 1024x1024 15x15-PSF workload "
                       f"after 1 warm-up ({dt:.1f} s); numpy/scipy single-threaded "
                       f"(host os.cpu_count()={os.cpu_count()})"}
+
+
+def bench_batch(torch, P, iters, count=256):
+    """The batched workload: `count` problems (n in {128,...,512}, own
+    Gaussian PSF 7..21 and noise level, Tikhonov alpha 5e-3, FP32), `iters`
+    preconditioned iterations in one graph launch, after a warm-up call
+    that captures the graph.  Inputs are resident on the GPU."""
+    import synth
+    plans, gs, xs = [], [], []
+    px = 0
+    for i in range(count):
+        F, H, E, prm = synth.batch_problem(i)
+        n = prm["n"]
+        pl = P.Plan(n, n, H, dtype="f32")
+        pl.ar_precond_set(P.AR_FILTER_TIKHONOV, prm["alpha"])
+        f = torch.from_numpy(F).to("cuda:0", torch.float32)
+        e = torch.from_numpy(E).to("cuda:0", torch.float32)
+        b = torch.empty_like(f)
+        pl.ar_blur_apply(f, b)
+        g = b + (prm["nu"] * torch.linalg.vector_norm(b.double()) /
+                 torch.linalg.vector_norm(e.double())).float() * e
+        plans.append(pl)
+        gs.append(g)
+        xs.append(torch.zeros_like(g))
+        px += n * n
+    batch = P.Batch(plans)
+    tuned = batch.ar_batch_autotune()
+    batch.ar_batch_iterate(gs, xs, iters)            # warm-up: captures the graph
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    rc, res, _, _ = batch.ar_batch_iterate(gs, xs, iters, want_resnorm=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t = max(wall, ev0.elapsed_time(ev1) / 1e3)
+    out = {"workload": f"{count} problems, n in {{128,192,256,384,512}} (seed 404 + i), "
+                       "Gaussian PSFs 7..21, noise 0.1%..2%, Tikhonov alpha 5e-3, FP32, "
+                       f"{iters} D-Landweber iterations in one graph launch",
+           "value": round(px * iters / t / 1e6, 1), "unit": "Mpixel-iters/s",
+           "pixels_per_iteration": px, "seconds": round(t, 5),
+           "us_per_batch_iteration": round(t / iters * 1e6, 2),
+           "status": rc, "autotuned_precond_us": round(tuned, 2)}
+    batch.close()
+    for pl in plans:
+        pl.close()
+    return out
 
 
 def main():
@@ -171,6 +224,8 @@ def main():
     roof = dict(rooflines[dom])
     roof["hbm_frac_of_step"] = round(npx * 36 / t_step / 1e9 / HBM_PEAK_GBS, 4)
 
+    batch = None if a.no_batch else bench_batch(torch, P, a.steps)
+
     cpu = None
     if not a.no_cpu and int(os.environ.get("RANK", "0")) == 0:
         cpu = cpu_baseline(F, H, E, p, a.cpu_iters)
@@ -196,6 +251,7 @@ def main():
         "roofline": roof,
         "kernels": rooflines,
         "cpu_baseline": cpu,
+        "batch": batch,
     }
     print(json.dumps(out, allow_nan=False), flush=True)
     plan.close()

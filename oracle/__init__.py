@@ -4,3 +4,4 @@ Test infrastructure only: imported by the test-suite, the smoke check and
 the CPU-baseline leg of the benchmark, never by the product library."""
 from .ar_oracle import *  # noqa: F401,F403
 from .ar_oracle import __all__  # noqa: F401
+from . import learned_oracle as learned  # noqa: F401,E402

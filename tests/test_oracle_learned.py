@@ -1,0 +1,197 @@
+"""Pins of the learned-filter oracle (CPU only).
+
+Each definition of oracle.learned is checked against something other than
+itself: brute-force loops over small grids, closed forms, statistical laws
+with known constants, and central finite differences for the gradient."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+L = O.learned
+
+
+def test_radial_rho_bruteforce():
+    """rho(k1, k2) written out point by point from the grid of Theorem 2."""
+    n1, n2 = 7, 10
+    rho = L.radial_rho(n1, n2)
+    for k1 in range(n1):
+        x1 = 0.0 if k1 in (0, n1 - 1) else k1 / (n1 - 1)
+        for k2 in range(n2):
+            x2 = 0.0 if k2 in (0, n2 - 1) else k2 / (n2 - 1)
+            assert abs(rho[k1, k2] - ((x1 * x1 + x2 * x2) / 2.0) ** 0.5) < 1e-15
+    assert rho.max() < 1.0 and rho.min() == 0.0
+
+
+def test_radial_profile_bruteforce_and_constants():
+    rng = np.random.default_rng(3)
+    n1, n2 = 40, 33
+    V = rng.standard_normal((n1, n2))
+    prof = L.radial_profile(V)
+    rho = L.radial_rho(n1, n2)
+    for b in range(L.NB):
+        vals = [V[i, j] for i in range(n1) for j in range(n2)
+                if min(int(np.floor(64 * rho[i, j])), 63) == b]
+        want = sum(vals) / len(vals) if vals else 0.0
+        assert abs(prof[b] - want) <= 1e-14 * (1 + abs(want))
+    # a constant field gives that constant in every non-empty bin
+    prof = L.radial_profile(np.full((300, 300), 2.5))
+    assert np.all(prof == 2.5)
+    # a tiny grid leaves empty bins at 0
+    prof = L.radial_profile(np.ones((4, 4)))
+    assert prof[0] == 1.0 and np.any(prof == 0.0)
+
+
+def test_eigenvalue_profile_starts_at_one():
+    """lambda(0, 0) = sum h = 1 and the four corner coefficients share x = 0,
+    so bin 0 averages 1 with the smallest interior frequencies."""
+    H = synth.psf_gauss_shifted(3, 3, 1.0, 1.0, shift=(0, 0))
+    lam = O.eigenvalues(H, 256, 256)
+    prof = L.radial_profile(lam)
+    assert 0.98 < prof[0] <= 1.0
+    assert prof[-1] < prof[0]
+
+
+def test_lower_median_bruteforce():
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 3, 10, 11, 100):
+        v = rng.standard_normal(n)
+        assert L.lower_median(v) == sorted(v)[(n - 1) // 2]
+
+
+def test_laplacian_of_quadratic():
+    """The 5-point Laplacian is exact on quadratics: 2a + 2c for
+    a i^2 + b i j + c j^2 + linear terms."""
+    i, j = np.meshgrid(np.arange(20.0), np.arange(17.0), indexing="ij")
+    G = 0.5 * i * i - 0.3 * i * j + 1.25 * j * j + 2 * i - j + 4
+    Lg = L.laplacian(G)
+    assert Lg.shape == (18, 15)
+    assert np.allclose(Lg, 2 * 0.5 + 2 * 1.25, atol=1e-10)
+
+
+def test_noise_estimate_on_white_noise():
+    """For g = c + sigma e (e iid N(0,1)) the Laplacian is a sum of 5 noise
+    samples with variance 20 sigma^2, MAD / 0.6745 estimates its standard
+    deviation, and nu_hat = sigma sqrt(N) / ||g|| (law of large numbers,
+    a few percent at 512^2)."""
+    rng = np.random.default_rng(11)
+    n = 512
+    for sigma in (0.01, 0.05):
+        G = 1.0 + sigma * rng.standard_normal((n, n))
+        want = sigma * n / np.linalg.norm(G)
+        got = L.noise_estimate(G)
+        assert abs(got / want - 1.0) < 0.03, (got, want)
+
+
+def test_noise_estimate_tracks_observation_level():
+    """On a blurred phantom with the repository's observation model the
+    estimate grows with nu (a monotone, roughly proportional response)."""
+    F = synth.phantom(256, 256, 10, 5, seed=1)
+    H = synth.psf_gauss_shifted(4, 4, 1.5, 1.5, shift=(0, 0))
+    E = synth.noise_field(256, 256, seed=2)
+    est = [L.noise_estimate(O.observe(F, H, E, nu)) for nu in (0.005, 0.01, 0.02)]
+    assert est[0] < est[1] < est[2]
+    assert 1.5 < est[2] / est[1] < 2.5
+
+
+def test_gains_filter_special_cases():
+    H = synth.psf_gauss_shifted(2, 3, 1.2, 0.8, shift=(0.2, 0.1))
+    lam = O.eigenvalues(H, 30, 40)
+    # Tikhonov's gains lambda^2 / (lambda^2 + alpha), when constant over a bin,
+    # reproduce eq. (TikFilter); with a single bin value phi the filter is phi / lambda^2
+    phi = np.full(L.NB, 0.5)
+    d = L.gains_filter(lam, phi, 1e4)
+    l2 = lam * lam
+    big = 0.5 < 1e4 * l2
+    assert np.allclose(d[big], 0.5 / l2[big], rtol=1e-15)
+    assert np.all(d[~big] == 1e4)
+    # zero gains give a zero filter, even where lambda = 0
+    lam0 = lam.copy()
+    lam0[3, 4] = 0.0
+    assert np.all(L.gains_filter(lam0, np.zeros(L.NB), 1e4) == 0.0)
+    assert L.gains_filter(lam0, phi, 1e4)[3, 4] == 1e4
+    # label of the Tikhonov filter: bin means of lambda^2 / (lambda^2 + alpha)
+    lab = L.gains_label(lam, O.tikhonov(lam, 1e-2))
+    assert np.all((lab >= 0) & (lab < 1))
+
+
+def test_bf16_round():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -2.5, 3.14159265, 0.0])
+    r = L.bf16_round(x)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                       # tie, to even
+    assert r[2] == 1.0 + 2 ** -7             # above the tie
+    assert r[3] == -2.5
+    assert abs(r[4] - 3.140625) < 1e-12
+    assert r[5] == 0.0
+
+
+def _theta(seed):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for (o, i) in L.SIZES:
+        parts.append(rng.standard_normal(o * i) * np.sqrt(2.0 / i))
+        parts.append(rng.standard_normal(o) * 0.1)
+    return np.concatenate(parts)
+
+
+def test_mlp_shapes_and_param_count():
+    assert L.NPARAM == 33216
+    th = _theta(0)
+    Y, _ = L.mlp_forward(th, np.random.default_rng(1).standard_normal((5, 65)))
+    assert Y.shape == (5, 64) and np.all((Y > 0) & (Y < 1))
+
+
+def test_mlp_gradient_finite_differences():
+    """Backpropagation against central differences on 60 random coordinates
+    spread over every layer (relative error <= 1e-6)."""
+    rng = np.random.default_rng(2)
+    th = _theta(1)
+    X = rng.standard_normal((7, 65))
+    T = rng.uniform(0, 1, (7, 64))
+    loss, g = L.mlp_loss_grad(th, X, T)
+    h = 1e-6
+    idx = rng.choice(L.NPARAM, 60, replace=False)
+    for k in idx:
+        e = np.zeros(L.NPARAM)
+        e[k] = h
+        fd = (L.mlp_loss_grad(th + e, X, T)[0] - L.mlp_loss_grad(th - e, X, T)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g[k])) + 1e-11, (k, fd, g[k])
+
+
+def test_mlp_loss_value():
+    """Loss is the mean of squared errors: zero at the network's own output."""
+    th = _theta(3)
+    X = np.random.default_rng(4).standard_normal((3, 65))
+    Y, _ = L.mlp_forward(th, X)
+    loss, g = L.mlp_loss_grad(th, X, Y)
+    assert loss == 0.0 and np.all(g == 0.0)
+
+
+def test_adam_first_step_is_sign_step():
+    """With zero moments the bias-corrected first Adam step is
+    -lr g / (|g| + eps)."""
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    th, m, v = L.adam_step(np.zeros(4), np.zeros(4), np.zeros(4), g, 1, 0.01)
+    assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_sweep_label_prefers_best_run():
+    """The sweep returns the candidate whose own run has the smallest RRE,
+    checked against running each candidate separately; its label is the
+    bin average of lambda^2 d of that candidate."""
+    n = 24
+    F = synth.phantom(n, n, 3, 2, seed=9)
+    H = synth.psf_gauss_shifted(2, 2, 1.0, 1.0, shift=(0.3, 0.0))
+    E = synth.noise_field(n, n, seed=10)
+    G = O.observe(F, H, E, 0.01)
+    alphas, ts = [1e-2, 1e-1], [0.05, 0.2]
+    kind, prm, e, lab = L.sweep_label(G, H, F, alphas, ts, 8)
+    lam = O.eigenvalues(H, n, n)
+    runs = {("tikhonov", a): O.tikhonov(lam, a) for a in alphas}
+    runs.update({("threshold", t): O.threshold_filter(lam, t) for t in ts})
+    errs = {k: O.iterate(G, H, 8, d=d, F_true=F)["rre"].min() for k, d in runs.items()}
+    assert e == min(errs.values()) and errs[(kind, prm)] == e
+    assert np.allclose(lab, L.gains_label(lam, runs[(kind, prm)]))

@@ -139,7 +139,8 @@ def bench_batch(torch, P, iters, count=256):
            "value": round(px * iters / t / 1e6, 1), "unit": "Mpixel-iters/s",
            "pixels_per_iteration": px, "seconds": round(t, 5),
            "us_per_batch_iteration": round(t / iters * 1e6, 2),
-           "status": rc, "autotuned_precond_us": round(tuned, 2)}
+           "status": rc, "autotuned_precond_us": round(tuned, 2),
+           "diverged_problems": int(np.sum(~np.all(np.isfinite(res), axis=1)))}
     batch.close()
     for pl in plans:
         pl.close()

@@ -58,8 +58,10 @@ enum ar_tmode { AR_REBLUR = 0, AR_ADJOINT = 1 };
  *  TIKHONOV : d = 1 / (lambda^2 + param)          (eq. (TikFilter))
  *  THRESHOLD: d = 1 / lambda^2 if |lambda| >= param, else 1
  *             (truncated-spectrum filter; not in the paper)
+ *  GAINS    : learned per-radial-bin gains phi (set by ar_precond_set_gains)
  *  IDENTITY : d = 1 (D = I, plain Landweber)                           */
-enum ar_filter { AR_FILTER_TIKHONOV = 0, AR_FILTER_THRESHOLD = 1, AR_FILTER_IDENTITY = 3 };
+enum ar_filter { AR_FILTER_TIKHONOV = 0, AR_FILTER_THRESHOLD = 1, AR_FILTER_GAINS = 2,
+                 AR_FILTER_IDENTITY = 3 };
 
 enum ar_status {
   AR_OK = 0,
@@ -247,6 +249,84 @@ int ar_batch_iterate(ar_batch_t b, const void *const *g, void *const *x, int ite
 
 /* Release a batch (not its plans).  NULL is a no-op returning AR_OK. */
 int ar_batch_destroy(ar_batch_t b);
+
+/* Replace the PSF of a plan (S0-S2 again: weights, symmetrized PSF,
+ * eigenvalues, and the current filter re-applied) without reallocating.
+ * The new half-widths must not exceed those the plan was created with;
+ * the PSF rules of ar_plan_create apply.  Synchronizes `stream`.  A batch
+ * that includes the plan must be re-created if q1 or q2 changes.
+ * Errors: AR_EINVAL, AR_ESHAPE (q larger than at creation), AR_EPSF. */
+int ar_plan_set_psf(ar_plan_t p, const double *psf_host, int q1, int q2, void *stream);
+
+/* ------------------------------------------------------------------
+ * Learned preconditioner filter (not part of the paper's method: the
+ * paper's filter is Tikhonov, eq. (TikFilter)).  A small network maps
+ * per-problem features to 64 gains g_b in [0, 1] that set a Tikhonov
+ * parameter per eigenvalue-magnitude bin:
+ *   d = 1 / (lambda^2 + a_b),  a_b = 10^(-6 + 6 g_b),
+ *   b = ebin(lambda) = #{j in 1..63 : |lambda| >= 10^(-4 + j/16)}.
+ * Radial bins of the features: coefficient (k1, k2) has x_j = r_j pi /
+ * (n_j - 1) with r_j = k_j on interior columns of T and 0 on the first and
+ * last one (the grid of Theorem 2); rho = sqrt((x1/pi)^2 + (x2/pi)^2) /
+ * sqrt(2) and rbin = min(floor(64 rho), 63), decided exactly in integers.
+ * ------------------------------------------------------------------ */
+enum { AR_FNET_BINS = 64, AR_FNET_IN = 65, AR_FNET_HIDDEN = 128, AR_FNET_NPARAM = 33216 };
+
+/* Features of one problem into feat_dev (device, 65 floats):
+ *  [0, 64): mean FP64 eigenvalue lambda of the plan per radial bin (0 for
+ *           an empty bin);
+ *  64     : log(nu_hat), the noise estimate of g: L = 5-point Laplacian
+ *           (0 1 0 / 1 -4 1 / 0 1 0) on the interior pixels, sigma =
+ *           lmed(|L - lmed(L)|) / 0.6745 / sqrt(20) with lmed the lower
+ *           median (rank floor((N-1)/2)), nu_hat = sigma sqrt(n1 n2) / ||g||_F.
+ * g: device, n1*n2, plan dtype.  Uses the plan's scratch.  Errors: AR_EINVAL. */
+int ar_features(ar_plan_t p, const void *g, float *feat_dev, void *stream);
+
+/* Set the spectrum from gains (device, 64 floats in [0, 1]) as above, in
+ * FP64; the filter becomes AR_FILTER_GAINS and is kept across
+ * ar_plan_set_psf.  Errors: AR_EINVAL. */
+int ar_precond_set_gains(ar_plan_t p, const float *gains_dev, void *stream);
+
+/* Training label of the plan's current filter (64 floats, device): with
+ * the bin centre c_b = 10^(-4 + (b + 1/2)/16) and a_b = 1/d(c_b) - c_b^2
+ * (Tikhonov: alpha; threshold: 0 above t, 1 - c_b^2 below; identity:
+ * 1 - c_b^2), label_b = (log10(clip(a_b, 1e-6, 1)) + 6) / 6. */
+int ar_gains_label(ar_plan_t p, float *label_dev, void *stream);
+
+/* Filter network 65 -> 128 -> 128 -> 64 (ReLU, ReLU, logistic sigmoid).
+ * Parameters (AR_FNET_NPARAM floats, host, in this order): W1 (128 x 65),
+ * b1 (128), W2 (128 x 128), b2 (128), W3 (64 x 128), b3 (64); each W is
+ * (out, in) row-major.  The network keeps FP32 master weights and Adam
+ * moments; its forward pass uses the weights rounded to BF16 (round to
+ * nearest even) on MFMA with FP32 accumulation, activations entering a
+ * layer split into two BF16 terms (hi + lo); biases stay FP32. */
+typedef struct ar_fnet_s *ar_fnet_t;
+
+/* Create a network on `device` from initial parameters (host); the random
+ * initialisation is the caller's.  Errors: AR_EINVAL, AR_EDEVICE, AR_ENOMEM. */
+int ar_fnet_create(ar_fnet_t *out, const float *params_host, int device);
+
+/* Release a network.  NULL is a no-op. */
+int ar_fnet_destroy(ar_fnet_t net);
+
+/* Copy the FP32 master parameters to the host (synchronizes the device). */
+int ar_fnet_get_params(ar_fnet_t net, float *params_host);
+
+/* y (batch x 64) = network(x (batch x 65)); device FP32 buffers, batch >= 1. */
+int ar_fnet_infer(ar_fnet_t net, const float *x_dev, float *y_dev, int batch, void *stream);
+
+/* Gradient of the loss mean((y - t)^2) over batch x 64 with respect to the
+ * parameters (layout above) at the current BF16 weights, into grad_dev
+ * (device, AR_FNET_NPARAM floats); the loss into loss_dev (device float,
+ * may be NULL).  x: batch x 65, t: batch x 64, device FP32. */
+int ar_fnet_grad(ar_fnet_t net, const float *x_dev, const float *t_dev, int batch,
+                 float *grad_dev, float *loss_dev, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step
+ * counter kept by the network) on the gradient above with learning rate
+ * lr; refreshes the BF16 weights.  loss_dev as in ar_fnet_grad. */
+int ar_fnet_train_step(ar_fnet_t net, const float *x_dev, const float *t_dev, int batch,
+                       float lr, float *loss_dev, void *stream);
 
 /* Thread-local message describing the last failure ("" if none). */
 const char *ar_last_error(void);

@@ -12,7 +12,7 @@ in the paper, so each definition below is this repository's own:
         rho = sqrt((x1 / pi)^2 + (x2 / pi)^2) / sqrt(2)  in [0, 1),
     x_j the evaluation point of column k_j of T (the grid of Theorem 2:
     0 for the first and last column, r pi / (n - 1) inside);
-    bin(k1, k2) = min(floor(64 rho), 63);
+    bin(k1, k2) = min(floor(64 rho), 63), decided exactly in integers;
   * features (65): the mean eigenvalue lambda per radial bin (0 for an
     empty bin), then log(nu_hat), nu_hat the noise estimate below;
   * noise estimate: L = 3x3 Laplacian (0 1 0 / 1 -4 1 / 0 1 0) of g on the
@@ -25,11 +25,18 @@ in the paper, so each definition below is this repository's own:
     parameter vector is [W1 (128 x 65), b1, W2 (128 x 128), b2, W3 (64 x 128),
     b3], each W stored (out, in) row-major; outputs are per-bin gains
     phi in [0, 1];
-  * gains filter: d = phi_b / lambda^2, capped at dmax (d = dmax where
-    phi_b >= dmax lambda^2 and phi_b > 0; d = 0 where phi_b = 0);
-  * label of a training problem: the gains phi = lambda^2 d of the plain
-    filter (Tikhonov or threshold, swept over its parameter) whose run
-    reaches the smallest RRE within K iterations, averaged per radial bin;
+  * eigenvalue bins: beta_j = 10^(-4 + j / 16), j = 1..63, and
+    ebin(lambda) = #{j : |lambda| >= beta_j} in [0, 63]; bin centre
+    c_b = 10^(-4 + (b + 1/2) / 16);
+  * gains filter: the network's outputs g_b in [0, 1] set a per-bin
+    regularization a_b = 10^(-6 + 6 g_b) and d = 1 / (lambda^2 + a_ebin(lambda))
+    (the Tikhonov filter with a parameter that depends on |lambda|);
+  * label of a training problem: among Tikhonov (d = 1 / (lambda^2 + alpha))
+    and threshold (d = 1 / lambda^2 for |lambda| >= t, else 1) filters swept
+    over their parameter, the one whose run reaches the smallest RRE within
+    K iterations; its label is g_b = (log10(clip(a_b, 1e-6, 1)) + 6) / 6 with
+    a_b = 1 / d(c_b) - c_b^2, the regularization that reproduces the filter
+    at the bin centre (Tikhonov: a_b = alpha; threshold: 0 or 1 - c_b^2);
   * loss: mean squared error over batch and bins; optimizer: Adam with bias
     correction (Kingma & Ba, 2015).
 """
@@ -48,7 +55,8 @@ NPARAM = sum(o * i + o for o, i in SIZES)
 __all__ = [
     "NB", "NF", "NPARAM", "SIZES",
     "radial_rho", "radial_bins", "radial_profile", "laplacian", "lower_median",
-    "noise_estimate", "features", "gains_filter", "gains_label", "unpack",
+    "noise_estimate", "features", "ebin_edges", "ebin_centres", "ebins", "gains_filter",
+    "gains_label", "unpack",
     "bf16_round", "mlp_forward", "mlp_loss_grad", "adam_step", "sweep_label",
 ]
 
@@ -61,7 +69,23 @@ def radial_rho(n1, n2):
 
 
 def radial_bins(n1, n2):
-    return np.minimum(np.floor(NB * radial_rho(n1, n2)).astype(np.int64), NB - 1)
+    """bin = min(floor(64 rho), 63), decided exactly: with r_j = k_j inside
+    and 0 on the first and last column, N_j = n_j - 1,
+    (64 rho)^2 = S / D, S = 2048 (r1^2 N2^2 + r2^2 N1^2), D = N1^2 N2^2, and
+    floor(sqrt(S / D)) = isqrt(S // D) (integers; no rounding at bin edges)."""
+    def r(n):
+        k = np.arange(n, dtype=np.int64)
+        k[0] = 0
+        k[n - 1] = 0
+        return k
+    N1, N2 = n1 - 1, n2 - 1
+    r1, r2 = r(n1)[:, None], r(n2)[None, :]
+    S = 2048 * (r1 * r1 * (N2 * N2) + r2 * r2 * (N1 * N1))
+    q = S // ((N1 * N1) * (N2 * N2))
+    k = np.floor(np.sqrt(q.astype(np.float64))).astype(np.int64)
+    k = np.where(k * k > q, k - 1, k)
+    k = np.where((k + 1) * (k + 1) <= q, k + 1, k)
+    return np.minimum(k, NB - 1)
 
 
 def radial_profile(V):
@@ -107,21 +131,38 @@ def features(H, G):
     return np.concatenate([radial_profile(lam), [np.log(noise_estimate(G))]])
 
 
-def gains_filter(lam, phi, dmax):
-    """d from per-bin gains phi (module docstring)."""
-    lam = np.asarray(lam, dtype=np.float64)
-    p = np.asarray(phi, dtype=np.float64)[radial_bins(*lam.shape)]
-    l2 = lam * lam
-    capped = p >= dmax * l2
-    with np.errstate(divide="ignore", invalid="ignore"):
-        d = np.where(capped, np.where(p > 0, dmax, 0.0), p / np.where(capped, 1.0, l2))
-    return d
+def ebin_edges():
+    """beta_j = 10^(-4 + j/16), j = 1..63."""
+    return np.array([10.0 ** (-4.0 + j / 16.0) for j in range(1, NB)])
 
 
-def gains_label(lam, d):
-    """phi = lambda^2 d averaged per radial bin."""
+def ebin_centres():
+    return np.array([10.0 ** (-4.0 + (b + 0.5) / 16.0) for b in range(NB)])
+
+
+def ebins(lam):
+    """ebin(lambda) = number of edges beta_j <= |lambda|."""
+    a = np.abs(np.asarray(lam, dtype=np.float64))
+    return (a[..., None] >= ebin_edges()).sum(axis=-1)
+
+
+def gains_filter(lam, gains):
+    """d = 1 / (lambda^2 + a_ebin(lambda)), a_b = 10^(-6 + 6 g_b)."""
     lam = np.asarray(lam, dtype=np.float64)
-    return radial_profile(lam * lam * np.asarray(d, dtype=np.float64))
+    a = 10.0 ** (-6.0 + 6.0 * np.asarray(gains, dtype=np.float64))
+    return 1.0 / (lam * lam + a[ebins(lam)])
+
+
+def gains_label(kind, param):
+    """Label of a plain filter: g_b = (log10(clip(1/d(c_b) - c_b^2, 1e-6, 1)) + 6) / 6."""
+    c = ebin_centres()
+    if kind == "tikhonov":
+        a = np.full(NB, float(param))
+    elif kind == "threshold":
+        a = np.where(c >= param, 0.0, 1.0 - c * c)
+    else:
+        raise ValueError(kind)
+    return (np.log10(np.clip(a, 1e-6, 1.0)) + 6.0) / 6.0
 
 
 def unpack(theta):
@@ -207,6 +248,6 @@ def sweep_label(G, H, F, alphas, thresholds, K):
         r = r[np.isfinite(r)]
         e = float(r.min()) if r.size else np.inf
         if best is None or e < best[2]:
-            best = (kind, prm, e, d)
-    kind, prm, e, d = best
-    return kind, prm, e, gains_label(lam, d)
+            best = (kind, prm, e)
+    kind, prm, e = best
+    return kind, prm, e, gains_label(kind, prm)

@@ -11,7 +11,11 @@ from ._lib import (  # noqa: F401
     AR_F32_ACC64,
     AR_F64,
     DTYPES,
+    AR_FILTER_GAINS,
     AR_FILTER_IDENTITY,
+    AR_FNET_BINS,
+    AR_FNET_IN,
+    AR_FNET_NPARAM,
     AR_FILTER_THRESHOLD,
     AR_FILTER_TIKHONOV,
     AR_REBLUR,
@@ -23,6 +27,7 @@ from ._lib import (  # noqa: F401
     AR_TUNE_ROW_WAVES,
     ArError,
     Batch,
+    FNet,
     LIB_PATH,
     Plan,
     SIGNATURES,

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libardeblur.so")
 AR_F32, AR_F64, AR_F32_ACC64 = 0, 1, 2
 DTYPES = {"f32": AR_F32, "f64": AR_F64, "f32x": AR_F32_ACC64}
 AR_REBLUR, AR_ADJOINT = 0, 1
-AR_FILTER_TIKHONOV, AR_FILTER_THRESHOLD, AR_FILTER_IDENTITY = 0, 1, 3
+AR_FILTER_TIKHONOV, AR_FILTER_THRESHOLD, AR_FILTER_GAINS, AR_FILTER_IDENTITY = 0, 1, 2, 3
+AR_FNET_BINS, AR_FNET_IN, AR_FNET_HIDDEN, AR_FNET_NPARAM = 64, 65, 128, 33216
 AR_TUNE_ROW_WAVES, AR_TUNE_COL_WAVES, AR_TUNE_ROW_EXCL, AR_TUNE_COL_EXCL = 0, 1, 2, 3
 AR_TUNE_ROW_ALGO, AR_TUNE_COL_ALGO = 4, 5
 
@@ -53,6 +54,16 @@ SIGNATURES = [
     ("ar_batch_iterate", _I, [_VP, C.POINTER(_VP), C.POINTER(_VP), _I, _D, _I, _I,
                               C.POINTER(_VP), C.POINTER(_D), C.POINTER(_D), C.POINTER(_I), _VP]),
     ("ar_batch_destroy", _I, [_VP]),
+    ("ar_plan_set_psf", _I, [_VP, C.POINTER(_D), _I, _I, _VP]),
+    ("ar_features", _I, [_VP, _VP, _VP, _VP]),
+    ("ar_precond_set_gains", _I, [_VP, _VP, _VP]),
+    ("ar_gains_label", _I, [_VP, _VP, _VP]),
+    ("ar_fnet_create", _I, [C.POINTER(_VP), C.POINTER(C.c_float), _I]),
+    ("ar_fnet_destroy", _I, [_VP]),
+    ("ar_fnet_get_params", _I, [_VP, C.POINTER(C.c_float)]),
+    ("ar_fnet_infer", _I, [_VP, _VP, _VP, _I, _VP]),
+    ("ar_fnet_grad", _I, [_VP, _VP, _VP, _I, _VP, _VP, _VP]),
+    ("ar_fnet_train_step", _I, [_VP, _VP, _VP, _I, C.c_float, _VP, _VP]),
     ("ar_last_error", C.c_char_p, []),
     ("ar_version", C.c_char_p, []),
 ]
@@ -192,6 +203,24 @@ class Plan:
         _check(load().ar_precond_solve(self._h, _ptr(y), _ptr(z), _stream(stream)))
         return z
 
+    def ar_plan_set_psf(self, psf, stream=None):
+        psf = np.ascontiguousarray(psf, dtype=np.float64)
+        q1, q2 = (psf.shape[0] - 1) // 2, (psf.shape[1] - 1) // 2
+        _check(load().ar_plan_set_psf(self._h, psf.ctypes.data_as(C.POINTER(C.c_double)),
+                                      q1, q2, _stream(stream)))
+        self.q1, self.q2 = q1, q2
+
+    def ar_features(self, g, feat, stream=None):
+        _check(load().ar_features(self._h, _ptr(g), _ptr(feat), _stream(stream)))
+        return feat
+
+    def ar_precond_set_gains(self, gains, stream=None):
+        _check(load().ar_precond_set_gains(self._h, _ptr(gains), _stream(stream)))
+
+    def ar_gains_label(self, label, stream=None):
+        _check(load().ar_gains_label(self._h, _ptr(label), _stream(stream)))
+        return label
+
     def ar_deblur_iterate(self, g, x, iters, tau=1.0, tmode=AR_REBLUR, precondition=True,
                           f_true=None, want_resnorm=False, want_rre=False, stream=None):
         """Returns (status, resnorm or None, rre or None, best_it or None)."""
@@ -276,6 +305,54 @@ class Batch:
                 np.array(res[:]).reshape(n, iters) if res is not None else None,
                 np.array(rre[:]).reshape(n, iters) if rre is not None else None,
                 np.array(best[:]) if best is not None else None)
+
+
+class FNet:
+    """Owns an ``ar_fnet_t`` (the filter network) on one device."""
+
+    def __init__(self, params, device=0):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        if params.size != AR_FNET_NPARAM:
+            raise ValueError(f"expected {AR_FNET_NPARAM} parameters")
+        self.device = int(device)
+        self._h = C.c_void_p()
+        _check(load().ar_fnet_create(C.byref(self._h),
+                                     params.ctypes.data_as(C.POINTER(C.c_float)), self.device))
+
+    def close(self):
+        if self._h:
+            load().ar_fnet_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def ar_fnet_get_params(self):
+        out = np.empty(AR_FNET_NPARAM, dtype=np.float32)
+        _check(load().ar_fnet_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def ar_fnet_infer(self, x, y, stream=None):
+        _check(load().ar_fnet_infer(self._h, _ptr(x), _ptr(y), int(x.shape[0]), _stream(stream)))
+        return y
+
+    def ar_fnet_grad(self, x, t, grad, loss=None, stream=None):
+        _check(load().ar_fnet_grad(self._h, _ptr(x), _ptr(t), int(x.shape[0]), _ptr(grad),
+                                   _ptr(loss), _stream(stream)))
+        return grad
+
+    def ar_fnet_train_step(self, x, t, lr, loss=None, stream=None):
+        _check(load().ar_fnet_train_step(self._h, _ptr(x), _ptr(t), int(x.shape[0]),
+                                         float(lr), _ptr(loss), _stream(stream)))
 
 
 def version():

@@ -133,6 +133,9 @@ struct ar_plan_s {
   double filter_param = 1e-2;
   // launch tunables (0 = automatic), set by ar_plan_tune / ar_plan_autotune
   int tune[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int q1cap = 0, q2cap = 0;    // half-widths the PSF buffers were sized for
+  float *gains = nullptr;      // last gains of AR_FILTER_GAINS (64 floats)
+  void *lscr = nullptr;        // scratch of the learned-filter kernels
 };
 
 namespace ar {
@@ -228,6 +231,8 @@ int wave_cols_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, i
 // plan-time and helper kernels (ar_plan.hip)
 int spectrum_launch(ar_plan_s *p, hipStream_t st);
 int filter_launch(ar_plan_s *p, int filter, double param, hipStream_t st);
+// learned-filter kernels (ar_learned.hip)
+int gains_filter_launch(ar_plan_s *p, const float *gains, hipStream_t st);
 int axpy_launch(const ar_plan_s *p, void *x, const void *yv, double tau, const void *f_true,
                 double *partial, int *nblocks_out, hipStream_t st);
 int axpy_blocks(const ar_plan_s *p);

@@ -343,8 +343,9 @@ static void plan_free(ar_plan_s *p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
   (void)hipDeviceSynchronize();
-  void *bufs[] = {p->H64, p->S64, p->w_fwd, p->w_rev, p->lambda, p->d64, p->d,
-                  p->r,   p->y,   p->c,     p->ext,   p->partials, p->scalars};
+  void *bufs[] = {p->H64, p->S64, p->w_fwd, p->w_rev,    p->lambda,  p->d64, p->d,
+                  p->r,   p->y,   p->c,     p->ext,      p->partials, p->scalars,
+                  p->gains, p->lscr};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   fft_plan_free(p->fft_row);
@@ -386,6 +387,8 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
   p->n2 = n2;
   p->q1 = q1;
   p->q2 = q2;
+  p->q1cap = q1;
+  p->q2cap = q2;
   p->dtype = dtype;
   p->device = device;
   p->esize = esize;
@@ -431,6 +434,35 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
     return rc;
   }
   *out = p;
+  return AR_OK;
+}
+
+extern "C" int ar_plan_set_psf(ar_plan_t p, const double *psf_host, int q1, int q2,
+                               void *stream) {
+  if (!p || !psf_host) return fail(AR_EINVAL, "ar_plan_set_psf: null argument");
+  if (q1 < 0 || q2 < 0 || q1 > p->q1cap || q2 > p->q2cap)
+    return fail(AR_ESHAPE, "ar_plan_set_psf: half-widths exceed those of the plan's creation");
+  const int K1 = 2 * q1 + 1, K2 = 2 * q2 + 1, P = K1 * K2;
+  double sum = 0.0;
+  for (int e = 0; e < P; ++e) {
+    const double v = psf_host[e];
+    if (!std::isfinite(v) || v < 0.0)
+      return fail(AR_EPSF, "ar_plan_set_psf: PSF entries must be finite and nonnegative");
+    sum += v;
+  }
+  if (std::fabs(sum - 1.0) > 1e-12 * P) return fail(AR_EPSF, "ar_plan_set_psf: PSF must sum to 1");
+  AR_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  AR_HIP(hipStreamSynchronize(st));  // kernels of the old PSF may still read the buffers
+  AR_HIP(hipMemcpy(p->H64, psf_host, P * sizeof(double), hipMemcpyHostToDevice));
+  p->q1 = q1;
+  p->q2 = q2;
+  int rc = spectrum_launch(p, st);
+  if (rc != AR_OK) return rc;
+  rc = p->filter == AR_FILTER_GAINS ? gains_filter_launch(p, p->gains, st)
+                                    : filter_launch(p, p->filter, p->filter_param, st);
+  if (rc != AR_OK) return rc;
+  AR_HIP(hipStreamSynchronize(st));
   return AR_OK;
 }
 

@@ -30,6 +30,8 @@ __all__ = [
     "WORKLOADS",
     "workload",
     "batch_problem",
+    "psf_mixture",
+    "learned_problem",
 ]
 
 
@@ -91,7 +93,8 @@ def psf_motion(q=7, length=11.0, angle_deg=30.0, sigma=1.0, samples=1101):
     cropped to (2q+1)^2 and normalised.  Centro-symmetric, not strongly
     symmetric."""
     size = 2 * q + 1
-    big = size + 8
+    big = max(size, int(np.ceil(length)) + 4) + 8
+    big += (big - size) % 2          # keep the canvas centre on a pixel
     c = (big - 1) / 2.0
     L = np.zeros((big, big))
     th = np.deg2rad(angle_deg)
@@ -187,3 +190,49 @@ def batch_problem(i, base_seed=404):
     F = phantom(n, n, blobs, rects, seed=base_seed * 1000 + i)
     E = noise_field(n, n, seed=base_seed * 1000 + 500 + i)
     return F, H, E, dict(n=n, nu=nu, alpha=5e-3, iters=100)
+
+
+def psf_mixture(rng, sizes=(15, 17, 19, 21, 23, 25, 27, 29, 31)):
+    """Random non-symmetric PSF from three families with equal probability:
+    line motion (length U[5,15], angle U[0,180), Gaussian sigma U[0.5,2]),
+    one-sided exponential tail (scale U[2,6], random axis and direction,
+    cross sigma U[1,3]) and a shifted Gaussian (sigma U[1,4] per axis,
+    centre offsets U[-3,3]); odd square side drawn from ``sizes``."""
+    S = int(rng.choice(sizes))
+    q = (S - 1) // 2
+    fam = int(rng.integers(0, 3))
+    if fam == 0:
+        length = rng.uniform(5.0, 15.0)
+        angle = rng.uniform(0.0, 180.0)
+        sigma = rng.uniform(0.5, 2.0)
+        return psf_motion(q, length, angle, sigma, samples=401)
+    if fam == 1:
+        tail = rng.uniform(2.0, 6.0)
+        sigma = rng.uniform(1.0, 3.0)
+        H = psf_tail(q, tail, sigma)
+        if rng.integers(0, 2):
+            H = H[::-1, :]
+        if rng.integers(0, 2):
+            H = H.T
+        return _normalise(np.ascontiguousarray(H))
+    sg1, sg2 = rng.uniform(1.0, 4.0, size=2)
+    o1, o2 = rng.uniform(-3.0, 3.0, size=2)
+    s1 = np.arange(-q, q + 1, dtype=np.float64).reshape(-1, 1)
+    s2 = np.arange(-q, q + 1, dtype=np.float64).reshape(1, -1)
+    return _normalise(np.exp(-((s1 - o1) ** 2) / (2 * sg1 * sg1)
+                             - ((s2 - o2) ** 2) / (2 * sg2 * sg2)))
+
+
+def learned_problem(i, n=256, base_seed=5_000_000, sizes=(15, 17, 19, 21, 23, 25, 27, 29, 31)):
+    """Problem ``i`` of the learned-filter sets: phantom (10 blobs, 5
+    rectangles at 256^2, scaled with n), PSF from ``psf_mixture``, noise
+    level log-uniform in [1e-3, 2e-2].  Training uses base seed 5,000,000,
+    the 1024^2 inference set 6,000,000."""
+    rng = np.random.default_rng(base_seed + i)
+    H = psf_mixture(rng, sizes)
+    nu = float(np.exp(rng.uniform(np.log(1e-3), np.log(2e-2))))
+    blobs = max(4, int(round(10 * n / 256)))
+    rects = max(2, int(round(5 * n / 256)))
+    F = phantom(n, n, blobs, rects, seed=base_seed + 7919 * i + 1)
+    E = noise_field(n, n, seed=base_seed + 7919 * i + 2)
+    return F, H, E, dict(n=n, nu=nu)

@@ -25,15 +25,35 @@ def test_radial_rho_bruteforce():
     assert rho.max() < 1.0 and rho.min() == 0.0
 
 
+def test_radial_bins_exact_at_edges():
+    """Bins from exact rational arithmetic (Fraction) on a grid that hits
+    bin edges exactly (n - 1 = 128: x / pi = k / 64 on the diagonal)."""
+    from fractions import Fraction
+    from math import isqrt
+    n = 129
+    b = L.radial_bins(n, n)
+    for k1 in list(range(0, n, 7)) + [2, 4, 64, 126, 127, 128]:
+        for k2 in list(range(0, n, 5)) + [2, 4, 64, 127, 128]:
+            r1 = 0 if k1 in (0, n - 1) else k1
+            r2 = 0 if k2 in (0, n - 1) else k2
+            v = 2048 * (Fraction(r1, n - 1) ** 2 + Fraction(r2, n - 1) ** 2)
+            want = min(isqrt(v.numerator // v.denominator), 63)
+            assert b[k1, k2] == want, (k1, k2)
+    assert b[2, 2] == 1 and b[64, 64] == 32
+    # away from edges the exact rule agrees with floor(64 rho) in floating point
+    rho = L.radial_rho(57, 91)
+    fl = np.minimum(np.floor(64 * rho), 63).astype(int)
+    assert np.mean(fl == L.radial_bins(57, 91)) > 0.999
+
+
 def test_radial_profile_bruteforce_and_constants():
     rng = np.random.default_rng(3)
     n1, n2 = 40, 33
     V = rng.standard_normal((n1, n2))
     prof = L.radial_profile(V)
-    rho = L.radial_rho(n1, n2)
+    bins = L.radial_bins(n1, n2)
     for b in range(L.NB):
-        vals = [V[i, j] for i in range(n1) for j in range(n2)
-                if min(int(np.floor(64 * rho[i, j])), 63) == b]
+        vals = [V[i, j] for i in range(n1) for j in range(n2) if bins[i, j] == b]
         want = sum(vals) / len(vals) if vals else 0.0
         assert abs(prof[b] - want) <= 1e-14 * (1 + abs(want))
     # a constant field gives that constant in every non-empty bin
@@ -96,25 +116,37 @@ def test_noise_estimate_tracks_observation_level():
     assert 1.5 < est[2] / est[1] < 2.5
 
 
-def test_gains_filter_special_cases():
+def test_ebins_and_edges():
+    e = L.ebin_edges()
+    assert e.size == 63 and np.all(np.diff(e) > 0)
+    assert abs(e[15] - 1e-3) < 1e-18 and abs(e[47] - 0.1) < 1e-16
+    lam = np.array([0.0, 5e-5, 1e-4, 1.0001e-4 * 10 ** (1 / 16), 1e-3, -0.5, 1.0])
+    b = L.ebins(lam)
+    assert list(b[:3]) == [0, 0, 0] and b[3] == 1 and b[4] == 16
+    assert b[5] == int(np.floor(16 * (4 + np.log10(0.5)))) and b[6] == 63
+    c = L.ebin_centres()
+    assert np.all(L.ebins(c) == np.arange(64))
+
+
+def test_gains_filter_reproduces_plain_filters():
+    """Constant gains give eq. (TikFilter) exactly; the labels of the plain
+    filters reproduce them at every bin centre (within the clip range)."""
     H = synth.psf_gauss_shifted(2, 3, 1.2, 0.8, shift=(0.2, 0.1))
     lam = O.eigenvalues(H, 30, 40)
-    # Tikhonov's gains lambda^2 / (lambda^2 + alpha), when constant over a bin,
-    # reproduce eq. (TikFilter); with a single bin value phi the filter is phi / lambda^2
-    phi = np.full(L.NB, 0.5)
-    d = L.gains_filter(lam, phi, 1e4)
-    l2 = lam * lam
-    big = 0.5 < 1e4 * l2
-    assert np.allclose(d[big], 0.5 / l2[big], rtol=1e-15)
-    assert np.all(d[~big] == 1e4)
-    # zero gains give a zero filter, even where lambda = 0
-    lam0 = lam.copy()
-    lam0[3, 4] = 0.0
-    assert np.all(L.gains_filter(lam0, np.zeros(L.NB), 1e4) == 0.0)
-    assert L.gains_filter(lam0, phi, 1e4)[3, 4] == 1e4
-    # label of the Tikhonov filter: bin means of lambda^2 / (lambda^2 + alpha)
-    lab = L.gains_label(lam, O.tikhonov(lam, 1e-2))
-    assert np.all((lab >= 0) & (lab < 1))
+    for alpha in (1e-4, 3e-3, 0.1):
+        g = np.full(L.NB, (np.log10(alpha) + 6) / 6)
+        assert np.allclose(L.gains_filter(lam, g), O.tikhonov(lam, alpha), rtol=1e-12)
+        assert np.allclose(L.gains_label("tikhonov", alpha), g, rtol=1e-14)
+    c = L.ebin_centres()
+    for t in (1e-3, 0.05, 0.3):
+        g = L.gains_label("threshold", t)
+        d = L.gains_filter(c, g)
+        want = O.threshold_filter(c, t)
+        big = c >= t
+        # above t: a = 0 clipped to 1e-6, d = 1 / (c^2 + 1e-6)
+        assert np.allclose(d[big], 1.0 / (c[big] ** 2 + 1e-6), rtol=1e-12)
+        assert np.allclose(d[~big], want[~big], rtol=1e-12)
+        assert np.all((g >= 0) & (g <= 1))
 
 
 def test_bf16_round():
@@ -180,8 +212,8 @@ def test_adam_first_step_is_sign_step():
 
 def test_sweep_label_prefers_best_run():
     """The sweep returns the candidate whose own run has the smallest RRE,
-    checked against running each candidate separately; its label is the
-    bin average of lambda^2 d of that candidate."""
+    checked against running each candidate separately, and that candidate's
+    label."""
     n = 24
     F = synth.phantom(n, n, 3, 2, seed=9)
     H = synth.psf_gauss_shifted(2, 2, 1.0, 1.0, shift=(0.3, 0.0))
@@ -194,4 +226,4 @@ def test_sweep_label_prefers_best_run():
     runs.update({("threshold", t): O.threshold_filter(lam, t) for t in ts})
     errs = {k: O.iterate(G, H, 8, d=d, F_true=F)["rre"].min() for k, d in runs.items()}
     assert e == min(errs.values()) and errs[(kind, prm)] == e
-    assert np.allclose(lab, L.gains_label(lam, runs[(kind, prm)]))
+    assert np.array_equal(lab, L.gains_label(kind, prm))

@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="skip the plan autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--learned-images", type=int, default=64,
+                    help="images of the learned-vs-plain leg (0 skips it)")
     return ap.parse_args()
 
 
@@ -147,6 +149,82 @@ def bench_batch(torch, P, iters, count=256):
     return out
 
 
+def bench_learned(torch, P, images, iters):
+    """GPU time to the best relative error, learned filter vs the plain
+    method, on `images` problems at 1024^2 (PSFs 15..31 from three
+    non-symmetric families, seeds 6,000,000 + i, noise 0.1%..2%).
+    Plain: the whole 32-filter sweep (16 Tikhonov, 16 threshold
+    parameters), `iters` iterations each, gives RRE* = its best RRE.
+    Learned: features + network + gains filter + the iterations until
+    RRE <= 1.02 RRE* (or its whole run when it never gets there).  Times
+    are GPU event times on the current stream."""
+    import synth
+    from paper_1211_0393_amd import learned as LR
+    try:
+        params = LR.load_params()
+    except (OSError, ValueError) as e:
+        return {"status": f"no trained weights ({e})"}
+    stream = torch.cuda.current_stream()
+    net = P.FNet(params)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    plain_s = learned_s = 0.0
+    reached, ratios, fb_ratios = 0, [], []
+    qcap = 15
+    plan = P.Plan(1024, 1024, LR._dummy_psf(qcap), dtype="f32")
+    plan.ar_plan_autotune()
+    for i in range(images):
+        F, H, E, prm = synth.learned_problem(i, n=1024, base_seed=6_000_000)
+        plan.ar_plan_set_psf(H)
+        f, g = LR.observe_gpu(plan, F, E, prm["nu"], torch.float32)
+        x = torch.zeros_like(g)
+        torch.cuda.synchronize()
+        best = np.inf
+        ev[0].record(stream)
+        for kind, prm_s in LR.SETTINGS:
+            plan.ar_precond_set(kind, prm_s)
+            x.zero_()
+            _, _, rre, _ = plan.ar_deblur_iterate(g, x, iters, f_true=f, want_rre=True)
+            m = finite_min(rre)
+            if m is not None:
+                best = min(best, m)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        plain_s += ev[0].elapsed_time(ev[1]) / 1e3
+        x.zero_()
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        LR.apply_learned(net, plan, g)
+        ev[1].record(stream)
+        _, _, rre, _ = plan.ar_deblur_iterate(g, x, iters, f_true=f, want_rre=True)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        t_setup = ev[0].elapsed_time(ev[1]) / 1e3
+        t_run = ev[1].elapsed_time(ev[2]) / 1e3
+        ok = np.nonzero(np.isfinite(rre) & (rre <= 1.02 * best))[0]
+        if ok.size:
+            reached += 1
+            learned_s += t_setup + t_run * (ok[0] + 1) / iters
+        else:
+            learned_s += t_setup + t_run
+        mb = finite_min(rre)
+        ratios.append((mb if mb is not None else np.inf) / best)
+        plan.ar_precond_set(*LR.FALLBACK)
+        x.zero_()
+        _, _, rre, _ = plan.ar_deblur_iterate(g, x, iters, f_true=f, want_rre=True)
+        mb = finite_min(rre)
+        fb_ratios.append((mb if mb is not None else np.inf) / best)
+    plan.close()
+    net.close()
+    return {"images": images, "n": 1024, "iterations": iters,
+            "plain_sweep_gpu_s": round(plain_s, 4), "learned_gpu_s": round(learned_s, 4),
+            "speedup": round(plain_s / learned_s, 2) if learned_s > 0 else None,
+            "reached_within_2pct": reached,
+            "median_best_rre_ratio_learned": round(float(np.median(ratios)), 4),
+            "median_best_rre_ratio_fallback": round(float(np.median(fb_ratios)), 4),
+            "workload": "1024x1024 phantoms, PSFs 15..31 (motion / exponential tail / "
+                        "shifted Gaussian), noise log-uniform 0.1%..2%, seeds 6,000,000 + i"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -226,6 +304,7 @@ def main():
     roof["hbm_frac_of_step"] = round(npx * 36 / t_step / 1e9 / HBM_PEAK_GBS, 4)
 
     batch = None if a.no_batch else bench_batch(torch, P, a.steps)
+    learned = bench_learned(torch, P, a.learned_images, a.steps) if a.learned_images > 0 else None
 
     cpu = None
     if not a.no_cpu and int(os.environ.get("RANK", "0")) == 0:
@@ -253,6 +332,7 @@ def main():
         "kernels": rooflines,
         "cpu_baseline": cpu,
         "batch": batch,
+        "learned_vs_plain": learned,
     }
     print(json.dumps(out, allow_nan=False), flush=True)
     plan.close()

@@ -77,6 +77,9 @@ def load(path: str | None = None):
     if _lib is not None and path is None:
         return _lib
     p = path or LIB_PATH
+    # load torch's HIP runtime first so that the library binds to the same
+    # runtime instance as the tensors and streams it is handed
+    import torch  # noqa: F401
     if not os.path.exists(p):
         raise ImportError(f"{p} is not built; run `python -m paper_1211_0393_amd.build`")
     lib = C.CDLL(p)

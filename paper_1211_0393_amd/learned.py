@@ -55,16 +55,18 @@ def _dummy_psf(q):
     return H
 
 
-def sweep_labels(problems, K=100, chunk=8, dtype="f32", log=None):
+def sweep_labels(problems, K=100, chunk=8, dtype="f32", log=None, qcap=None):
     """Features (N x 65), labels (N x 64), best RRE and best setting index of
     each problem (F, H, E, nu) by the plain sweep; all problems share one
-    size n x n."""
+    size n x n.  ``problems`` is a sequence (or an object with __len__ and
+    __getitem__ that builds problems on demand); ``qcap`` bounds the PSF
+    half-widths (default: the largest of the sequence)."""
     torch = _torch()
     tdt = torch.float64 if dtype == "f64" else torch.float32
     n = problems[0][0].shape[0]
     S = len(SETTINGS)
-    qcap = max((H.shape[0] - 1) // 2 for (_, H, _, _) in problems)
-    qcap = max(qcap, max((H.shape[1] - 1) // 2 for (_, H, _, _) in problems))
+    if qcap is None:
+        qcap = max(max(H.shape) for (_, H, _, _) in problems) // 2
     pool = [L.Plan(n, n, _dummy_psf(qcap), dtype=dtype) for _ in range(chunk * S)]
     N = len(problems)
     feats = torch.zeros((N, L.AR_FNET_IN), device="cuda:0", dtype=torch.float32)
@@ -74,7 +76,7 @@ def sweep_labels(problems, K=100, chunk=8, dtype="f32", log=None):
     t0 = time.perf_counter()
     try:
         for c0 in range(0, N, chunk):
-            sub = problems[c0:c0 + chunk]
+            sub = [problems[i] for i in range(c0, min(N, c0 + chunk))]
             plans = pool[:len(sub) * S]
             gs, fs = [], []
             for j, (F, H, E, nu) in enumerate(sub):
@@ -162,8 +164,23 @@ def load_params(path=WEIGHTS):
     return p
 
 
+class Problems:
+    """Training problems built on demand (synth.learned_problem)."""
+
+    def __init__(self, count, n=256, seed0=5_000_000, sizes=None, first=0):
+        self.count, self.n, self.seed0, self.sizes, self.first = count, n, seed0, sizes, first
+
+    def __len__(self):
+        return self.count
+
+    def __getitem__(self, i):
+        import synth
+        kw = {} if self.sizes is None else {"sizes": self.sizes}
+        F, H, E, prm = synth.learned_problem(self.first + i, n=self.n, base_seed=self.seed0, **kw)
+        return F, H, E, prm["nu"]
+
+
 def main(argv=None):
-    import synth
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--tuples", type=int, default=20000)
     ap.add_argument("--n", type=int, default=256)
@@ -172,6 +189,10 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed0", type=int, default=5_000_000)
+    ap.add_argument("--first", type=int, default=0, help="index of the first problem")
+    ap.add_argument("--data", nargs="*", default=[],
+                    help="train on saved features/labels (.npz) instead of sweeping")
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--save-data", default=None, help="also save features/labels (.npz)")
     a = ap.parse_args(argv)
@@ -180,17 +201,22 @@ def main(argv=None):
     def log(m):
         print(m, flush=True)
 
-    probs = []
-    for i in range(a.tuples):
-        F, H, E, prm = synth.learned_problem(i, n=a.n)
-        probs.append((F, H, E, prm["nu"]))
-    log(f"{a.tuples} problems at {a.n}^2 generated")
-    feats, labels, best, sel = sweep_labels(probs, K=a.iters, chunk=a.chunk, log=log)
-    log(f"labels done; mean best RRE {np.mean(best):.4f}; "
-        f"Tikhonov chosen {np.mean(sel < 16):.2f} of the time")
-    if a.save_data:
-        np.savez(a.save_data, feats=feats.cpu().numpy(), labels=labels.cpu().numpy(),
-                 best=best, sel=sel)
+    torch = _torch()
+    if a.data:
+        parts = [np.load(f, allow_pickle=False) for f in a.data]
+        feats = torch.from_numpy(np.concatenate([p["feats"] for p in parts])).to("cuda:0")
+        labels = torch.from_numpy(np.concatenate([p["labels"] for p in parts])).to("cuda:0")
+        log(f"{feats.shape[0]} saved examples loaded")
+    else:
+        probs = Problems(a.tuples, a.n, a.seed0, first=a.first)
+        feats, labels, best, sel = sweep_labels(probs, K=a.iters, chunk=a.chunk, log=log, qcap=15)
+        log(f"labels done; mean best RRE {np.mean(best):.4f}; "
+            f"Tikhonov chosen {np.mean(sel < 16):.2f} of the time")
+        if a.save_data:
+            np.savez(a.save_data, feats=feats.cpu().numpy(), labels=labels.cpu().numpy(),
+                     best=best, sel=sel)
+    if a.steps <= 0:
+        return
     net = train(feats, labels, steps=a.steps, batch=a.batch, lr=a.lr, log=log)
     save_params(a.out, net.ar_fnet_get_params())
     log(f"saved {a.out}")

@@ -13,8 +13,8 @@
  *    corner).  Element (i1, i2) sits at offset i1 * n2 + i2.
  *  - Image buffers are DEVICE pointers on the plan's device, owned by the
  *    caller; the library never frees them.  Their element type is the plan's
- *    storage type (AR_F32 and AR_F32_ACC64 -> float, AR_F64 -> double)
- *    unless stated otherwise.
+ *    storage type (double for AR_F64, float for the other dtypes) unless
+ *    stated otherwise.
  *  - The PSF is a HOST array of (2 q1 + 1) x (2 q2 + 1) doubles, row-major,
  *    psf[(q1 + s1) * (2 q2 + 1) + (q2 + s2)] = h_{s1,s2} (eq.
  *    (coefficienti_psf)).  It must be finite, nonnegative, sum to 1 within
@@ -46,8 +46,13 @@ typedef struct ar_plan_s *ar_plan_t;
  *  AR_F32_ACC64 : float images; blur accumulation, boundary extension and
  *                 transforms computed in double (full rate on gfx950 when
  *                 packed FP32 is not used), intermediates stored as float.
+ *  AR_F32_BF16X3: float images and blur; each axis of the AR transform is
+ *                 applied as one dense m x m matrix product on the matrix
+ *                 cores, operands split into two BF16 terms (hi + lo, three
+ *                 products hi*hi + hi*lo + lo*hi), FP32 accumulation; about
+ *                 1e-5 relative error per transform pass.
  * Eigenvalues, the filter division and all norms are FP64 in every mode. */
-enum ar_dtype { AR_F32 = 0, AR_F64 = 1, AR_F32_ACC64 = 2 };
+enum ar_dtype { AR_F32 = 0, AR_F64 = 1, AR_F32_ACC64 = 2, AR_F32_BF16X3 = 3 };
 
 /* Transpose used by the iteration: the reblurring A' = A(PSF rotated by
  * 180 degrees) that the paper's experiments use (Sec. 4), or the exact
@@ -84,7 +89,7 @@ enum ar_status {
  * and the default Tikhonov filter with param = 1e-2.  Device scratch for
  * the iteration is allocated here and owned by the plan.
  *   out    : receives the plan (set to NULL on failure)
- *   dtype  : AR_F32, AR_F64 or AR_F32_ACC64 (see enum ar_dtype)
+ *   dtype  : an ar_dtype
  *   device : HIP device ordinal the plan lives on
  * Errors: AR_EINVAL, AR_ESHAPE, AR_EPSF, AR_EDEVICE, AR_ENOMEM. */
 int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_host,
@@ -209,7 +214,7 @@ int ar_iterate_profile(ar_plan_t p, const void *g, const void *x, int tmode, int
 typedef struct ar_batch_s *ar_batch_t;
 
 /* Create a batch over `count` plans (host array).  The plans must be
- * distinct, share one dtype and device, and outlive the batch; the batch
+ * distinct, share one dtype (not AR_F32_BF16X3) and device, and outlive the batch; the batch
  * runs on their scratch buffers, so a plan must not be used on its own
  * while a batch call that includes it is in flight.  Every image shape of
  * the batch must fit the wave-per-sequence transform (n <= 2048 for

@@ -9,6 +9,7 @@ from ._lib import (  # noqa: F401
     AR_ADJOINT,
     AR_F32,
     AR_F32_ACC64,
+    AR_F32_BF16X3,
     AR_F64,
     DTYPES,
     AR_FILTER_GAINS,

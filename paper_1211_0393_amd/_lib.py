@@ -17,8 +17,8 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libardeblur.so")
 
-AR_F32, AR_F64, AR_F32_ACC64 = 0, 1, 2
-DTYPES = {"f32": AR_F32, "f64": AR_F64, "f32x": AR_F32_ACC64}
+AR_F32, AR_F64, AR_F32_ACC64, AR_F32_BF16X3 = 0, 1, 2, 3
+DTYPES = {"f32": AR_F32, "f64": AR_F64, "f32x": AR_F32_ACC64, "bf16x3": AR_F32_BF16X3}
 AR_REBLUR, AR_ADJOINT = 0, 1
 AR_FILTER_TIKHONOV, AR_FILTER_THRESHOLD, AR_FILTER_GAINS, AR_FILTER_IDENTITY = 0, 1, 2, 3
 AR_FNET_BINS, AR_FNET_IN, AR_FNET_HIDDEN, AR_FNET_NPARAM = 64, 65, 128, 33216

@@ -388,6 +388,8 @@ extern "C" int ar_batch_create(ar_batch_t *out, int count, const ar_plan_t *plan
     if (std::adjacent_find(s.begin(), s.end()) != s.end())
       return fail(AR_EINVAL, "ar_batch_create: a plan appears twice");
   }
+  if (plans[0]->dtype == AR_F32_BF16X3)
+    return fail(AR_EUNSUPPORTED, "ar_batch_create: dense-transform plans are not batched");
   for (int i = 0; i < count; ++i)
     if (!wave_rows_ok(plans[i]) || !wave_cols_ok(plans[i]))
       return fail(AR_EUNSUPPORTED, "ar_batch_create: image too large for the batched transform");

@@ -541,6 +541,7 @@ void fft_plan_free(FftPlan &fp) {
 }
 
 int rows_blocks(const ar_plan_s *p) {
+  if (p->dtype == AR_F32_BF16X3) return dense_blocks(p);
   if (wave_rows_ok(p)) return wave_rows_blocks(p);
   const int B = rows_per_block(p->fft_row.M, p->csize);
   return (p->n1 + B - 1) / B;
@@ -591,6 +592,8 @@ static int rows_launch_t(const ar_plan_s *p, const void *in, void *out, int mode
 int rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                 const void *f_true, double *partial, int *nblocks_out, hipStream_t st) {
   if (nblocks_out) *nblocks_out = rows_blocks(p);
+  if (p->dtype == AR_F32_BF16X3)
+    return dense_rows_launch(p, in, out, mode, tau, f_true, partial, st);
   if (wave_rows_ok(p)) return wave_rows_launch(p, in, out, mode, tau, f_true, partial, st);
   if (p->dtype == AR_F64)
     return rows_launch_t<double, double>(p, in, out, mode, tau, f_true, partial, st);
@@ -636,6 +639,7 @@ static int cols_launch_t(const ar_plan_s *p, const void *in, void *out, int mode
 }
 
 int cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
+  if (p->dtype == AR_F32_BF16X3) return dense_cols_launch(p, in, out, mode, st);
   if (wave_cols_ok(p)) return wave_cols_launch(p, in, out, mode, st);
   if (p->dtype == AR_F64) return cols_launch_t<double, double>(p, in, out, mode, st);
   if (p->dtype == AR_F32_ACC64) return cols_launch_t<float, double>(p, in, out, mode, st);

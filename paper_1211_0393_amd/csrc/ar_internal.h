@@ -133,6 +133,11 @@ struct ar_plan_s {
   double filter_param = 1e-2;
   // launch tunables (0 = automatic), set by ar_plan_tune / ar_plan_autotune
   int tune[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // dense transform matrices of AR_F32_BF16X3 (FP32, m x m): T~_{n1}, T_{n1},
+  // T~_{n2}^T, T_{n2}^T, and an n1 x n2 scratch
+  float *mat_fwd_col = nullptr, *mat_inv_col = nullptr;
+  float *mat_fwdT_row = nullptr, *mat_invT_row = nullptr;
+  void *dscr = nullptr;
   int q1cap = 0, q2cap = 0;    // half-widths the PSF buffers were sized for
   float *gains = nullptr;      // last gains of AR_FILTER_GAINS (64 floats)
   void *lscr = nullptr;        // scratch of the learned-filter kernels
@@ -227,6 +232,13 @@ int wave_rows_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, i
                            double tau, int k, hipStream_t st);
 int wave_cols_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, int mode,
                            hipStream_t st);
+
+// dense BF16x3 MFMA transforms of AR_F32_BF16X3 plans (ar_dense.hip)
+int dense_setup(ar_plan_s *p, hipStream_t st);
+int dense_blocks(const ar_plan_s *p);
+int dense_rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
+                      const void *f_true, double *partial, hipStream_t st);
+int dense_cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st);
 
 // plan-time and helper kernels (ar_plan.hip)
 int spectrum_launch(ar_plan_s *p, hipStream_t st);

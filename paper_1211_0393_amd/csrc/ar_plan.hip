@@ -343,9 +343,11 @@ static void plan_free(ar_plan_s *p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
   (void)hipDeviceSynchronize();
-  void *bufs[] = {p->H64, p->S64, p->w_fwd, p->w_rev,    p->lambda,  p->d64, p->d,
-                  p->r,   p->y,   p->c,     p->ext,      p->partials, p->scalars,
-                  p->gains, p->lscr};
+  void *bufs[] = {p->H64,         p->S64,         p->w_fwd,        p->w_rev,
+                  p->lambda,      p->d64,         p->d,            p->r,
+                  p->y,           p->c,           p->ext,          p->partials,
+                  p->scalars,     p->gains,       p->lscr,         p->mat_fwd_col,
+                  p->mat_inv_col, p->mat_fwdT_row, p->mat_invT_row, p->dscr};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   fft_plan_free(p->fft_row);
@@ -358,10 +360,10 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
   if (!out) return fail(AR_EINVAL, "ar_plan_create: out is NULL");
   *out = nullptr;
   if (!psf_host) return fail(AR_EINVAL, "ar_plan_create: psf is NULL");
-  if (dtype != AR_F32 && dtype != AR_F64 && dtype != AR_F32_ACC64)
+  if (dtype != AR_F32 && dtype != AR_F64 && dtype != AR_F32_ACC64 && dtype != AR_F32_BF16X3)
     return fail(AR_EINVAL, "ar_plan_create: bad dtype");
   const size_t esize = dtype == AR_F64 ? 8 : 4;
-  const size_t csize = dtype == AR_F32 ? 4 : 8;
+  const size_t csize = (dtype == AR_F32 || dtype == AR_F32_BF16X3) ? 4 : 8;
   if (q1 < 0 || q2 < 0) return fail(AR_ESHAPE, "ar_plan_create: negative PSF half-width");
   if (n1 < 3 || n2 < 3) return fail(AR_ESHAPE, "ar_plan_create: need n1, n2 >= 3");
   if (q1 > n1 - 3 || q2 > n2 - 3)
@@ -423,7 +425,8 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
   }
   if ((rc = spectrum_launch(p, st)) != AR_OK || (rc = filter_launch(p, AR_FILTER_TIKHONOV, 1e-2, st)) != AR_OK ||
       (rc = fft_plan_build(p->fft_row, n2, csize == 8, st)) != AR_OK ||
-      (rc = fft_plan_build(p->fft_col, n1, csize == 8, st)) != AR_OK) {
+      (rc = fft_plan_build(p->fft_col, n1, csize == 8, st)) != AR_OK ||
+      (dtype == AR_F32_BF16X3 && (rc = dense_setup(p, st)) != AR_OK)) {
     plan_free(p);
     return rc;
   }

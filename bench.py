@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="skip the plan autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 2048^2 BF16x3 precision-variant leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one torch copy of 256 MiB (reference for HBM counters)")
     ap.add_argument("--learned-images", type=int, default=64,
                     help="images of the learned-vs-plain leg (0 skips it)")
     return ap.parse_args()
@@ -66,6 +70,36 @@ def make_inputs(torch, P, dt):
     plan.ar_precond_set(P.AR_FILTER_TIKHONOV, p["alpha"])
     torch.cuda.synchronize()
     return plan, f, g, F, H, E, p
+
+
+def source_digest():
+    """SHA-256 over the library's HIP sources (identifies the kernels that
+    a set of hardware counters was taken on)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1211_0393_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(dtype):
+    """HBM bytes per launch from the committed hardware-counter summary
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, scaled
+    by the same counters of a plain copy of known size), keyed by phase
+    name; empty when the kernels changed since the counters were taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return {}
+    if t.get("source_sha256") != source_digest() or t.get("dtype") != dtype:
+        return {}
+    return {k: v["hbm_bytes_per_launch"] for k, v in t.get("phases", {}).items()}
 
 
 def finite_min(v):
@@ -225,6 +259,67 @@ def bench_learned(torch, P, images, iters):
                         "shifted Gaussian), noise log-uniform 0.1%..2%, seeds 6,000,000 + i"}
 
 
+def bench_precision(torch, P, iters):
+    """The precision variant: 2048^2 FP32 images, 31x31 one-sided
+    exponential-tail PSF, 1% noise, Tikhonov alpha 5e-3, `iters` iterations
+    with every transform pass as a BF16x3 MFMA GEMM (AR_F32_BF16X3).  Its
+    error is reported against the FP64-arithmetic GPU path (AR_F64 on the
+    same data; that path matches the FP64 oracle to 1e-12): relative
+    difference of x_1 and x_10, and the best RRE of both runs."""
+    import synth
+    F, H, E, p = synth.workload("ar2048_f32_tail31")
+    n = p["n"]
+    plan = P.Plan(n, n, H, dtype="bf16x3")
+    plan.ar_precond_set(P.AR_FILTER_TIKHONOV, p["alpha"])
+    f = torch.from_numpy(F).to("cuda:0", torch.float32)
+    e = torch.from_numpy(E).to("cuda:0", torch.float32)
+    b = torch.empty_like(f)
+    plan.ar_blur_apply(f, b)
+    g = b + (p["nu"] * torch.linalg.vector_norm(b.double()) /
+             torch.linalg.vector_norm(e.double())).float() * e
+    x = torch.zeros_like(g)
+    plan.ar_deblur_iterate(g, x, 5)                  # warm-up
+    x.zero_()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    rc, res, _, _ = plan.ar_deblur_iterate(g, x, iters, want_resnorm=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t = ev0.elapsed_time(ev1) / 1e3
+    out = {"workload": "2048x2048 phantom (40 blobs + 20 rectangles, seed 303), 31x31 one-sided "
+                       "exponential tail exp(-s1/4) x Gaussian sigma 2, 1% noise, Tikhonov alpha "
+                       "5e-3, BF16x3 MFMA transforms, FP32 blur, FP64 eigenvalues/filter/norms",
+           "iterations": iters, "value": round(n * n * iters / t / 1e6, 1),
+           "unit": "Mpixel-iters/s", "ms_per_iteration": round(t / iters * 1e3, 4),
+           "status": rc}
+    ref = P.Plan(n, n, H, dtype="f64")
+    ref.ar_precond_set(P.AR_FILTER_TIKHONOV, p["alpha"])
+    g64, f64 = g.double(), f.double()
+    errs = {}
+    xb = torch.zeros_like(g)
+    xr = torch.zeros_like(g64)
+    done = 0
+    for k in (1, 10):
+        plan.ar_deblur_iterate(g, xb, k - done)
+        ref.ar_deblur_iterate(g64, xr, k - done)
+        done = k
+        errs[f"x{k}_rel_err_vs_f64"] = float(torch.linalg.vector_norm(xb.double() - xr) /
+                                            torch.linalg.vector_norm(xr))
+    xb.zero_()
+    xr.zero_()
+    _, _, rre_b, best_b = plan.ar_deblur_iterate(g, xb, iters, f_true=f, want_rre=True)
+    _, _, rre_r, best_r = ref.ar_deblur_iterate(g64, xr, iters, f_true=f64, want_rre=True)
+    out.update(errs)
+    out.update({"best_rre": finite_min(rre_b), "best_it": best_b,
+                "f64_best_rre": finite_min(rre_r), "f64_best_it": best_r})
+    plan.close()
+    ref.close()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -282,21 +377,23 @@ def main():
     es = 4                                           # FP32 images
     ds = 8 if a.dtype == "f32x" else 4               # filter in the compute type
     phases = [
-        ("residual blur r = g - A x", "alu", 2.0 * P_taps * npx, 3 * es * npx),
-        ("reblur y = A' r", "alu", 2.0 * P_taps * npx, 2 * es * npx),
-        ("row pass of T~", "hbm", None, 2 * es * npx),
-        ("column pass T~, d, T", "hbm", None, (2 * es + ds) * npx),
-        ("row pass of T + update", "hbm", None, 3 * es * npx),
+        ("residual blur r = g - A x", "alu", 2.0 * P_taps * npx, 3 * es * npx, "conv_kernel"),
+        ("reblur y = A' r", "alu", 2.0 * P_taps * npx, 2 * es * npx, "conv_kernel"),
+        ("row pass of T~", "hbm", None, 2 * es * npx, "rows_w_kernel"),
+        ("column pass T~, d, T", "hbm", None, (2 * es + ds) * npx, "cols_w_kernel"),
+        ("row pass of T + update", "hbm", None, 3 * es * npx, "rows_w_kernel"),
     ]
+    traffic = measured_traffic(a.dtype)
     rooflines = []
-    for (name, bound, flops, nbytes), us in zip(phases, phase_us):
+    for (name, bound, flops, nbytes, kname), us in zip(phases, phase_us):
         t = us * 1e-6
         if bound == "alu":
             ach, peak, unit = flops / t / 1e12, VALU_PEAK_TFLOPS, "TFLOP/s"
         else:
             ach, peak, unit = nbytes / t / 1e9, HBM_PEAK_GBS, "GB/s"
         rooflines.append({"kernel": name, "bound": bound, "achieved": round(ach, 2), "peak": peak,
-                          "unit": unit, "frac": round(ach / peak, 4), "traffic": None,
+                          "unit": unit, "frac": round(ach / peak, 4),
+                          "traffic": traffic.get(name),
                           "kernel_us": round(us, 2),
                           "algorithmic": {"flops": flops, "bytes": nbytes}})
     dom = int(np.argmax(phase_us))
@@ -305,6 +402,12 @@ def main():
 
     batch = None if a.no_batch else bench_batch(torch, P, a.steps)
     learned = bench_learned(torch, P, a.learned_images, a.steps) if a.learned_images > 0 else None
+    precision = None if a.no_precision else bench_precision(torch, P, 200)
+    if a.copy_probe:
+        src = torch.ones(64 << 20, device="cuda:0", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     cpu = None
     if not a.no_cpu and int(os.environ.get("RANK", "0")) == 0:
@@ -333,6 +436,7 @@ def main():
         "cpu_baseline": cpu,
         "batch": batch,
         "learned_vs_plain": learned,
+        "precision_variant": precision,
     }
     print(json.dumps(out, allow_nan=False), flush=True)
     plan.close()

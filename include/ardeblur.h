@@ -188,10 +188,11 @@ int ar_plan_get_tune(ar_plan_t p, int key, int *value);
  * overwrites the plan's scratch; synchronizes `stream`. */
 int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream);
 
-/* Phase profiler of one (D-)Landweber iteration: runs `reps` iterations on
- * copies of the plan's scratch (x and g are read, x is left unchanged) and
- * records HIP events on `stream` around each kernel, returning the average
- * duration in microseconds of each phase in phase_us[0..4]:
+/* Phase profiler of one (D-)Landweber iteration: after one untimed
+ * iteration (on a private copy of x; x and g are only read), each phase's
+ * kernel is launched `reps` times back to back between two HIP events on
+ * `stream`; phase_us[0..4] receives the average duration per launch in
+ * microseconds:
  *   0: r = g - A x (residual blur with FP64 norm partials)
  *   1: y = A' r or A^T r (transpose blur; correlation + fold for A^T)
  *   2: row pass of T~ (0 when precondition == 0)

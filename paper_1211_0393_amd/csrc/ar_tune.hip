@@ -141,45 +141,52 @@ extern "C" int ar_iterate_profile(ar_plan_t p, const void *g, const void *x, int
   void *xw = nullptr;
   AR_HIP(hipMalloc(&xw, bytes));
   AR_HIP(hipMemcpyAsync(xw, x, bytes, hipMemcpyDeviceToDevice, st));
-  hipEvent_t ev[6];
-  for (auto &e : ev) AR_HIP(hipEventCreate(&e));
-  double acc[5] = {0, 0, 0, 0, 0};
-  int rc = AR_OK;
-  for (int it = -1; it < reps && rc == AR_OK; ++it) {  // it = -1: warm-up
-    (void)hipEventRecord(ev[0], st);
-    rc = conv_launch(p, xw, p->r, p->w_fwd, 0, 0, p->n1, p->n2, false, g, nullptr, nullptr, st);
-    (void)hipEventRecord(ev[1], st);
-    if (rc == AR_OK) {
-      if (tmode == AR_REBLUR) {
-        rc = conv_launch(p, p->r, p->y, p->w_rev, 0, 0, p->n1, p->n2, false, nullptr, nullptr,
-                         nullptr, st);
-      } else {
-        rc = conv_launch(p, p->r, p->ext, p->w_rev, -p->q1, -p->q2, p->n1 + 2 * p->q1,
-                         p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st, true);
-        if (rc == AR_OK) rc = fold_launch(p, p->ext, p->y, st);
-      }
+  // the five phases of one iteration; each is timed as `reps` back-to-back
+  // launches between two events (its inputs are left in place by one
+  // untimed iteration first, and no timed launch overwrites its own input)
+  auto phase = [&](int k) -> int {
+    switch (k) {
+      case 0:
+        return conv_launch(p, xw, p->r, p->w_fwd, 0, 0, p->n1, p->n2, false, g, nullptr, nullptr,
+                           st);
+      case 1:
+        if (tmode == AR_REBLUR)
+          return conv_launch(p, p->r, p->y, p->w_rev, 0, 0, p->n1, p->n2, false, nullptr,
+                             nullptr, nullptr, st);
+        else {
+          int rc = conv_launch(p, p->r, p->ext, p->w_rev, -p->q1, -p->q2, p->n1 + 2 * p->q1,
+                               p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st, true);
+          return rc != AR_OK ? rc : fold_launch(p, p->ext, p->y, st);
+        }
+      case 2:
+        return precondition ? rows_launch(p, p->y, p->c, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st)
+                            : AR_OK;
+      case 3:  // out of place into r (free after the transpose blur)
+        return precondition ? cols_launch(p, p->c, p->r, COL_FWD_D_INV, st) : AR_OK;
+      default:
+        return precondition
+                   ? rows_launch(p, p->c, xw, ROW_INV_UPDATE, 1.0, nullptr, nullptr, nullptr, st)
+                   : axpy_launch(p, xw, p->y, 1.0, nullptr, nullptr, nullptr, st);
     }
-    (void)hipEventRecord(ev[2], st);
-    if (rc == AR_OK && precondition)
-      rc = rows_launch(p, p->y, p->c, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
-    (void)hipEventRecord(ev[3], st);
-    if (rc == AR_OK && precondition) rc = cols_launch(p, p->c, p->c, COL_FWD_D_INV, st);
-    (void)hipEventRecord(ev[4], st);
-    if (rc == AR_OK)
-      rc = precondition ? rows_launch(p, p->c, xw, ROW_INV_UPDATE, 1.0, nullptr, nullptr, nullptr, st)
-                        : axpy_launch(p, xw, p->y, 1.0, nullptr, nullptr, nullptr, st);
-    (void)hipEventRecord(ev[5], st);
-    (void)hipEventSynchronize(ev[5]);
-    if (it >= 0)
-      for (int k = 0; k < 5; ++k) {
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-        acc[k] += 1e3 * ms;
-      }
+  };
+  hipEvent_t ev[2];
+  for (auto &e : ev) AR_HIP(hipEventCreate(&e));
+  int rc = AR_OK;
+  for (int k = 0; k < 5 && rc == AR_OK; ++k) rc = phase(k);  // untimed iteration
+  for (int k = 0; k < 5 && rc == AR_OK; ++k) {
+    if (k == 3) rc = phase(2);  // c holds the row pass output again
+    if (rc != AR_OK) break;
+    rc = phase(k);  // warm-up launch
+    (void)hipEventRecord(ev[0], st);
+    for (int i = 0; i < reps && rc == AR_OK; ++i) rc = phase(k);
+    (void)hipEventRecord(ev[1], st);
+    (void)hipEventSynchronize(ev[1]);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    phase_us[k] = 1e3 * ms / reps;
+    if (k >= 2 && !precondition && k < 4) phase_us[k] = 0.0;
   }
   for (auto &e : ev) (void)hipEventDestroy(e);
   (void)hipFree(xw);
-  if (rc != AR_OK) return rc;
-  for (int k = 0; k < 5; ++k) phase_us[k] = acc[k] / reps;
-  return AR_OK;
+  return rc;
 }

@@ -339,7 +339,8 @@ def main():
     tuning = {k: plan.ar_plan_get_tune(v) for k, v in
               [("row_waves", P.AR_TUNE_ROW_WAVES), ("col_waves", P.AR_TUNE_COL_WAVES),
                ("row_excl", P.AR_TUNE_ROW_EXCL), ("col_excl", P.AR_TUNE_COL_EXCL),
-               ("row_fft", P.AR_TUNE_ROW_ALGO), ("col_fft", P.AR_TUNE_COL_ALGO)]}
+               ("row_fft", P.AR_TUNE_ROW_ALGO), ("col_fft", P.AR_TUNE_COL_ALGO),
+               ("row_lanes", P.AR_TUNE_ROW_LANES), ("col_lanes", P.AR_TUNE_COL_LANES)]}
     x = torch.zeros_like(g)
 
     # warm-up (untimed)

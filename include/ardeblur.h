@@ -170,9 +170,13 @@ int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters, double tau
  *      workgroup of that pass (spreads few workgroups over all CUs)
  *  AR_TUNE_ROW_ALGO / AR_TUNE_COL_ALGO   : FFT of the DST-I, 1 = mixed
  *      radix (only when every prime factor of n - 1 is <= 31), 2 = Bluestein
- *      chirp-z with a power-of-two FFT (any length); 0 = auto            */
+ *      chirp-z with a power-of-two FFT (any length); 0 = auto
+ *  AR_TUNE_ROW_LANES / AR_TUNE_COL_LANES : wavefronts per sequence, 1 or 2
+ *      (0 = 1); with 2, a row's (column's) butterflies and elements are
+ *      dealt to 128 lanes                                                */
 enum ar_tune_key { AR_TUNE_ROW_WAVES = 0, AR_TUNE_COL_WAVES = 1, AR_TUNE_ROW_EXCL = 2,
-                   AR_TUNE_COL_EXCL = 3, AR_TUNE_ROW_ALGO = 4, AR_TUNE_COL_ALGO = 5 };
+                   AR_TUNE_COL_EXCL = 3, AR_TUNE_ROW_ALGO = 4, AR_TUNE_COL_ALGO = 5,
+                   AR_TUNE_ROW_LANES = 6, AR_TUNE_COL_LANES = 7 };
 
 /* Set one tunable (value 0 restores the automatic choice).  Errors:
  * AR_EINVAL for an unknown key or value. */

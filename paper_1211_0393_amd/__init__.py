@@ -22,9 +22,11 @@ from ._lib import (  # noqa: F401
     AR_REBLUR,
     AR_TUNE_COL_ALGO,
     AR_TUNE_COL_EXCL,
+    AR_TUNE_COL_LANES,
     AR_TUNE_COL_WAVES,
     AR_TUNE_ROW_ALGO,
     AR_TUNE_ROW_EXCL,
+    AR_TUNE_ROW_LANES,
     AR_TUNE_ROW_WAVES,
     ArError,
     Batch,

@@ -653,14 +653,17 @@ extern "C" int ar_batch_autotune(ar_batch_t b, double *best_us, void *stream) {
     XJob *jc = jarr<XJob>(b, b->off_xcol, true) + G.job_off;
     XJob *ji = jarr<XJob>(b, b->off_xinv, true) + G.job_off;
     double best_r = DBL_MAX, best_c = DBL_MAX;
-    int br[3] = {0, 0, 0}, bc[3] = {0, 0, 0};
+    int br[4] = {0, 0, 0, 0}, bc[4] = {0, 0, 0, 0};
     for (int a = 1; a <= 2; ++a) {
       lead->tune[AR_TUNE_ROW_ALGO] = a;
       lead->tune[AR_TUNE_COL_ALGO] = a;
       const bool row_ok = wave_rows_algo(lead) == a, col_ok = wave_cols_algo(lead) == a;
+      for (int gl = 1; gl <= 2; ++gl)
       for (int w : waves)
         for (int xx = 0; xx < 2; ++xx) {
           double us = 0;
+          lead->tune[AR_TUNE_ROW_LANES] = gl;
+          lead->tune[AR_TUNE_COL_LANES] = gl;
           if (row_ok) {
             lead->tune[AR_TUNE_ROW_WAVES] = w;
             lead->tune[AR_TUNE_ROW_EXCL] = xx;
@@ -671,7 +674,7 @@ extern "C" int ar_batch_autotune(ar_batch_t b, double *best_us, void *stream) {
                 },
                 st, reps, &us);
             if (rc != AR_OK) return rc;
-            if (us < best_r) { best_r = us; br[0] = a; br[1] = w; br[2] = xx; }
+            if (us < best_r) { best_r = us; br[0] = a; br[1] = w; br[2] = xx; br[3] = gl; }
           }
           if (col_ok) {
             lead->tune[AR_TUNE_COL_WAVES] = w;
@@ -680,7 +683,7 @@ extern "C" int ar_batch_autotune(ar_batch_t b, double *best_us, void *stream) {
                 [&]() { return wave_cols_launch_batch(lead, jc, cnt, COL_FWD_D_INV, st); }, st,
                 reps, &us);
             if (rc != AR_OK) return rc;
-            if (us < best_c) { best_c = us; bc[0] = a; bc[1] = w; bc[2] = xx; }
+            if (us < best_c) { best_c = us; bc[0] = a; bc[1] = w; bc[2] = xx; bc[3] = gl; }
           }
         }
     }
@@ -692,6 +695,8 @@ extern "C" int ar_batch_autotune(ar_batch_t b, double *best_us, void *stream) {
       p->tune[AR_TUNE_COL_ALGO] = bc[0];
       p->tune[AR_TUNE_COL_WAVES] = bc[1];
       p->tune[AR_TUNE_COL_EXCL] = bc[2];
+      p->tune[AR_TUNE_ROW_LANES] = br[3];
+      p->tune[AR_TUNE_COL_LANES] = bc[3];
     }
     total += (best_r < DBL_MAX ? best_r : 0) + (best_c < DBL_MAX ? best_c : 0);
   }

@@ -22,6 +22,8 @@ static bool tune_valid(int key, int value) {
       return value == 0 || value == 1;
     case AR_TUNE_ROW_ALGO:
     case AR_TUNE_COL_ALGO:
+    case AR_TUNE_ROW_LANES:
+    case AR_TUNE_COL_LANES:
       return value == 0 || value == 1 || value == 2;
     default:
       return false;
@@ -37,7 +39,7 @@ extern "C" int ar_plan_tune(ar_plan_t p, int key, int value) {
 
 extern "C" int ar_plan_get_tune(ar_plan_t p, int key, int *value) {
   if (!p || !value) return fail(AR_EINVAL, "ar_plan_get_tune: null argument");
-  if (key < 0 || key > AR_TUNE_COL_ALGO) return fail(AR_EINVAL, "ar_plan_get_tune: bad key");
+  if (key < 0 || key > AR_TUNE_COL_LANES) return fail(AR_EINVAL, "ar_plan_get_tune: bad key");
   *value = p->tune[key];
   return AR_OK;
 }
@@ -79,11 +81,14 @@ extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
   // rows: forward and inverse pass
   double best_r = DBL_MAX;
   int br_a = 0, br_w = 0, br_x = 0;
+  int br_g = 0, bc_g = 0;
   for (int a = 1; a <= 2; ++a) {
     p->tune[AR_TUNE_ROW_ALGO] = a;
     if (wave_rows_algo(p) != a) continue;  // that FFT form is not available here
+    for (int gl = 1; gl <= 2; ++gl)
     for (int w : waves)
       for (int x = 0; x < 2; ++x) {
+        p->tune[AR_TUNE_ROW_LANES] = gl;
         p->tune[AR_TUNE_ROW_WAVES] = w;
         p->tune[AR_TUNE_ROW_EXCL] = x;
         double us = 0;
@@ -96,10 +101,11 @@ extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
             },
             st, reps, &us);
         if (rc != AR_OK) return rc;
-        if (us < best_r) { best_r = us; br_a = a; br_w = w; br_x = x; }
+        if (us < best_r) { best_r = us; br_a = a; br_w = w; br_x = x; br_g = gl; }
       }
   }
   p->tune[AR_TUNE_ROW_ALGO] = br_a;
+  p->tune[AR_TUNE_ROW_LANES] = br_g;
   p->tune[AR_TUNE_ROW_WAVES] = br_w;
   p->tune[AR_TUNE_ROW_EXCL] = br_x;
   if (best_r == DBL_MAX) best_r = 0;  // block-wide engine only
@@ -109,18 +115,21 @@ extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
   for (int a = 1; a <= 2; ++a) {
     p->tune[AR_TUNE_COL_ALGO] = a;
     if (wave_cols_algo(p) != a) continue;
+    for (int gl = 1; gl <= 2; ++gl)
     for (int w : waves)
       for (int x = 0; x < 2; ++x) {
+        p->tune[AR_TUNE_COL_LANES] = gl;
         p->tune[AR_TUNE_COL_WAVES] = w;
         p->tune[AR_TUNE_COL_EXCL] = x;
         double us = 0;
         int rc = time_us([&]() { return cols_launch(p, p->c, p->c, COL_FWD_D_INV, st); }, st,
                          reps, &us);
         if (rc != AR_OK) return rc;
-        if (us < best_c) { best_c = us; bc_a = a; bc_w = w; bc_x = x; }
+        if (us < best_c) { best_c = us; bc_a = a; bc_w = w; bc_x = x; bc_g = gl; }
       }
   }
   p->tune[AR_TUNE_COL_ALGO] = bc_a;
+  p->tune[AR_TUNE_COL_LANES] = bc_g;
   p->tune[AR_TUNE_COL_WAVES] = bc_w;
   p->tune[AR_TUNE_COL_EXCL] = bc_x;
   if (best_c == DBL_MAX) best_c = 0;

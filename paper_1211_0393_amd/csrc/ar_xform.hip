@@ -46,28 +46,37 @@ template <int R> struct Chunk { static constexpr int value = R <= 4 ? 4 : (R <= 
 
 // One stage.  DIT: twiddle the inputs, then the DFT.  DIF (the transpose
 // of the DIT stage): the DFT, then twiddle the outputs.
-template <typename T, int R, bool DIF>
+template <typename T, int R, bool DIF, int G>
 __device__ __forceinline__ void bfly(V2<T> *U, int N, int L, const V2<T> *__restrict__ tw,
                                      int lane) {
   constexpr int NB = Chunk<R>::value;
+  constexpr int SL = 64 * G;  // lanes working on one sequence
+  // small radices keep their twiddles in registers across the DFT; large
+  // ones read them where they are used (register pressure)
+  constexpr bool PRE = R <= 11;
   const int nb = N / R;
-  for (int j0 = lane; j0 < nb; j0 += 64 * NB) {
+  for (int j0 = lane; j0 < nb; j0 += SL * NB) {
     V2<T> v[NB][R];
-    V2<T> t[NB][R - 1];
-    int base[NB];
+    V2<T> t[NB][PRE ? R - 1 : 1];
+    int base[NB], kk[NB];
     bool ok[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-      const int jr = j0 + 64 * c;
+      const int jr = j0 + SL * c;
       ok[c] = jr < nb;
       const int j = ok[c] ? jr : j0;
       const int g = j / L, k = j - g * L;
       base[c] = g * L * R + k;
+      kk[c] = k;
       static_for<R>([&](auto r) { v[c][r] = U[base[c] + r * L]; });
       if (L > 1) {
-        static_for<R - 1>([&](auto r) { t[c][r] = tw[r * L + k]; });
-        if constexpr (!DIF)
-          static_for<R - 1>([&](auto r) { v[c][r + 1] = cmul(v[c][r + 1], t[c][r]); });
+        if constexpr (PRE) {
+          static_for<R - 1>([&](auto r) { t[c][r] = tw[r * L + k]; });
+          if constexpr (!DIF)
+            static_for<R - 1>([&](auto r) { v[c][r + 1] = cmul(v[c][r + 1], t[c][r]); });
+        } else if constexpr (!DIF) {
+          static_for<R - 1>([&](auto r) { v[c][r + 1] = cmul(v[c][r + 1], tw[r * L + k]); });
+        }
       }
     }
 #pragma unroll
@@ -78,8 +87,12 @@ __device__ __forceinline__ void bfly(V2<T> *U, int N, int L, const V2<T> *__rest
       } else {
         dft_emit<R, T>(v[c], [&](auto K, V2<T> x) {
           constexpr int r = decltype(K)::value;
-          if constexpr (r > 0)
-            if (L > 1) x = cmul(x, t[c][r - 1]);
+          if constexpr (r > 0) {
+            if (L > 1) {
+              if constexpr (PRE) x = cmul(x, t[c][r - 1]);
+              else x = cmul(x, tw[(r - 1) * L + kk[c]]);
+            }
+          }
           U[base[c] + r * L] = x;
         });
       }
@@ -87,10 +100,20 @@ __device__ __forceinline__ void bfly(V2<T> *U, int N, int L, const V2<T> *__rest
   }
 }
 
+// Radix sets: a kernel compiled for a set contains only those codelets
+// (smaller code); the launcher picks a set that covers the plan's radices.
+constexpr int rbit(int r) {
+  return r == 2 ? 0 : r == 3 ? 1 : r == 4 ? 2 : r == 5 ? 3 : r == 7 ? 4 : r == 11 ? 5 : r == 13 ? 6
+       : r == 17 ? 7 : r == 19 ? 8 : r == 23 ? 9 : r == 29 ? 10 : 11;
+}
+constexpr int kMaskAll = 0xfff;
+constexpr int kMask3_11_31 = (1 << rbit(3)) | (1 << rbit(11)) | (1 << rbit(31));  // 1023
+constexpr bool in_mask(int mask, int r) { return (mask >> rbit(r)) & 1; }
+
 // DIT runs stages 0..nst-1 (digit-reversed in, natural out); DIF runs them
 // backwards (natural in, digit-reversed out).  Bluestein plans use radices
 // 4 and 2 only.
-template <typename T, bool DIF, bool BS>
+template <typename T, bool DIF, bool BS, int G, int MASK>
 __device__ __forceinline__ void fft_run(V2<T> *U, const WDesc &wd, const V2<T> *__restrict__ tw,
                                         int lane) {
   const int N = wd.N;
@@ -100,44 +123,48 @@ __device__ __forceinline__ void fft_run(V2<T> *U, const WDesc &wd, const V2<T> *
     const int L = wd.L[st];
     if constexpr (BS) {
       if (wd.R[st] == 4)
-        bfly<T, 4, DIF>(U, N, L, tt, lane);
+        bfly<T, 4, DIF, G>(U, N, L, tt, lane);
       else
-        bfly<T, 2, DIF>(U, N, L, tt, lane);
+        bfly<T, 2, DIF, G>(U, N, L, tt, lane);
     } else {
       switch (wd.R[st]) {
-        case 2: bfly<T, 2, DIF>(U, N, L, tt, lane); break;
-        case 3: bfly<T, 3, DIF>(U, N, L, tt, lane); break;
-        case 4: bfly<T, 4, DIF>(U, N, L, tt, lane); break;
-        case 5: bfly<T, 5, DIF>(U, N, L, tt, lane); break;
-        case 7: bfly<T, 7, DIF>(U, N, L, tt, lane); break;
-        case 11: bfly<T, 11, DIF>(U, N, L, tt, lane); break;
-        case 13: bfly<T, 13, DIF>(U, N, L, tt, lane); break;
-        case 17: bfly<T, 17, DIF>(U, N, L, tt, lane); break;
-        case 19: bfly<T, 19, DIF>(U, N, L, tt, lane); break;
-        case 23: bfly<T, 23, DIF>(U, N, L, tt, lane); break;
-        case 29: bfly<T, 29, DIF>(U, N, L, tt, lane); break;
-        default: bfly<T, 31, DIF>(U, N, L, tt, lane); break;
+        case 2: if constexpr (in_mask(MASK, 2)) bfly<T, 2, DIF, G>(U, N, L, tt, lane); break;
+        case 3: if constexpr (in_mask(MASK, 3)) bfly<T, 3, DIF, G>(U, N, L, tt, lane); break;
+        case 4: if constexpr (in_mask(MASK, 4)) bfly<T, 4, DIF, G>(U, N, L, tt, lane); break;
+        case 5: if constexpr (in_mask(MASK, 5)) bfly<T, 5, DIF, G>(U, N, L, tt, lane); break;
+        case 7: if constexpr (in_mask(MASK, 7)) bfly<T, 7, DIF, G>(U, N, L, tt, lane); break;
+        case 11: if constexpr (in_mask(MASK, 11)) bfly<T, 11, DIF, G>(U, N, L, tt, lane); break;
+        case 13: if constexpr (in_mask(MASK, 13)) bfly<T, 13, DIF, G>(U, N, L, tt, lane); break;
+        case 17: if constexpr (in_mask(MASK, 17)) bfly<T, 17, DIF, G>(U, N, L, tt, lane); break;
+        case 19: if constexpr (in_mask(MASK, 19)) bfly<T, 19, DIF, G>(U, N, L, tt, lane); break;
+        case 23: if constexpr (in_mask(MASK, 23)) bfly<T, 23, DIF, G>(U, N, L, tt, lane); break;
+        case 29: if constexpr (in_mask(MASK, 29)) bfly<T, 29, DIF, G>(U, N, L, tt, lane); break;
+        default: if constexpr (in_mask(MASK, 31)) bfly<T, 31, DIF, G>(U, N, L, tt, lane); break;
       }
     }
     __syncthreads();
   }
 }
 
-constexpr int kRowChunk = 16;  // elements per lane per batch (covers 1024 per wave)
+// Elements per lane per batch of the sequence-wide loops (1024 per sequence
+// at once): G lanes-per-sequence groups of 64 share them.
+template <int G> struct RC { static constexpr int value = 16 / G; };
+template <int G> struct PC { static constexpr int value = 8 / G; };
 
 // Bluestein middle step, natural order, in place: U_k <- conj(U_k bhat_k)
-template <typename T>
+template <typename T, int G>
 __device__ __forceinline__ void bs_mid(V2<T> *U, int N, const V2<T> *__restrict__ bhat, int lane) {
-  for (int k0 = lane; k0 < N; k0 += 64 * kRowChunk) {
-    V2<T> b[kRowChunk];
+  constexpr int C = RC<G>::value, SL = 64 * G;
+  for (int k0 = lane; k0 < N; k0 += SL * C) {
+    V2<T> b[C];
 #pragma unroll
-    for (int c = 0; c < kRowChunk; ++c) {
-      const int k = k0 + 64 * c;
+    for (int c = 0; c < C; ++c) {
+      const int k = k0 + SL * c;
       b[c] = bhat[k < N ? k : k0];
     }
 #pragma unroll
-    for (int c = 0; c < kRowChunk; ++c) {
-      const int k = k0 + 64 * c;
+    for (int c = 0; c < C; ++c) {
+      const int k = k0 + SL * c;
       if (k < N) {
         const V2<T> z = cmul(U[k], b[c]);
         U[k] = {z.x, -z.y};
@@ -147,14 +174,14 @@ __device__ __forceinline__ void bs_mid(V2<T> *U, int N, const V2<T> *__restrict_
 }
 
 // The DFT of the packed sequence held in U.
-template <typename T, bool BS>
+template <typename T, bool BS, int G, int MASK>
 __device__ __forceinline__ void fft_full(V2<T> *U, const WDesc &wd, const V2<T> *tw,
                                          const V2<T> *__restrict__ bhat, int lane) {
-  fft_run<T, false, BS>(U, wd, tw, lane);
+  fft_run<T, false, BS, G, MASK>(U, wd, tw, lane);
   if constexpr (BS) {
-    bs_mid<T>(U, wd.N, bhat, lane);
+    bs_mid<T, G>(U, wd.N, bhat, lane);
     __syncthreads();
-    fft_run<T, true, BS>(U, wd, tw, lane);
+    fft_run<T, true, BS, G, MASK>(U, wd, tw, lane);
   }
 }
 
@@ -196,8 +223,6 @@ __device__ __forceinline__ T wcoef(const V2<T> *U, const int *s_drev, const V2<T
   const T in = d + y0 * (T(M - k) * invM) + y1 * (T(k) * invM);
   return k == 0 ? y0 : (k == M ? y1 : in);
 }
-
-constexpr int kPostChunk = 8;
 
 __device__ __forceinline__ double wg_sum(double v, double *red) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -273,15 +298,16 @@ __device__ __forceinline__ void load_tables(const WLayout<T> &Ly, const V2<T> *_
 // One chunk of the packed sequence: raw interior values x_j for j = 2t and
 // 2t + 1 (mirrored past M) and, for Bluestein, the chirp w_t; clamped
 // indices so that every load is unconditional.
-template <typename TSRC, typename T, bool BS>
+template <typename TSRC, typename T, bool BS, int G>
 struct PackChunk {
-  T xr[kRowChunk], xi[kRowChunk];
-  V2<T> w[BS ? kRowChunk : 1];
+  static constexpr int C = RC<G>::value, SL = 64 * G;
+  T xr[C], xi[C];
+  V2<T> w[BS ? C : 1];
   __device__ __forceinline__ void load(const TSRC *src, long stride, int t0, int M,
                                        const V2<T> *__restrict__ chirp) {
 #pragma unroll
-    for (int c = 0; c < kRowChunk; ++c) {
-      const int t = t0 + 64 * c;
+    for (int c = 0; c < C; ++c) {
+      const int t = t0 + SL * c;
       int j0 = 2 * t, j1 = 2 * t + 1;
       j0 = j0 < M ? j0 : 2 * M - j0;
       j1 = j1 < M ? j1 : 2 * M - j1;
@@ -305,14 +331,14 @@ __device__ __forceinline__ T zfrom(T x, int tau, int M, bool ramp, T e0, T e1, T
 }
 
 // Store one chunk at digit-reversed positions; Bluestein zero-pads t >= M.
-template <typename TSRC, typename T, bool BS>
+template <typename TSRC, typename T, bool BS, int G>
 __device__ __forceinline__ void pack_store(V2<T> *U, const int *s_drev,
-                                           const PackChunk<TSRC, T, BS> &pc, int t0, int M, int N,
-                                           bool active, bool ramp, T e0, T e1) {
+                                           const PackChunk<TSRC, T, BS, G> &pc, int t0, int M,
+                                           int N, bool active, bool ramp, T e0, T e1) {
   const T invM = T(1) / T(M);
 #pragma unroll
-  for (int c = 0; c < kRowChunk; ++c) {
-    const int t = t0 + 64 * c;
+  for (int c = 0; c < PackChunk<TSRC, T, BS, G>::C; ++c) {
+    const int t = t0 + 64 * G * c;
     if (t >= N) continue;
     V2<T> u{T(0), T(0)};
     if (active && t < M) {
@@ -325,21 +351,23 @@ __device__ __forceinline__ void pack_store(V2<T> *U, const int *s_drev,
 }
 
 // Pack the whole sequence (chunk 0 already loaded into pc).
-template <typename TSRC, typename T, bool BS>
-__device__ __forceinline__ void pack_all(V2<T> *U, const int *s_drev, PackChunk<TSRC, T, BS> &pc,
-                                         const TSRC *src, long stride, int lane, int M, int N,
-                                         const V2<T> *chirp, bool active, bool ramp, T e0, T e1) {
-  pack_store<TSRC, T, BS>(U, s_drev, pc, lane, M, N, active, ramp, e0, e1);
-  for (int t0 = lane + 64 * kRowChunk; t0 < N; t0 += 64 * kRowChunk) {
+template <typename TSRC, typename T, bool BS, int G>
+__device__ __forceinline__ void pack_all(V2<T> *U, const int *s_drev,
+                                         PackChunk<TSRC, T, BS, G> &pc, const TSRC *src,
+                                         long stride, int lane, int M, int N, const V2<T> *chirp,
+                                         bool active, bool ramp, T e0, T e1) {
+  constexpr int step = 64 * G * RC<G>::value;
+  pack_store<TSRC, T, BS, G>(U, s_drev, pc, lane, M, N, active, ramp, e0, e1);
+  for (int t0 = lane + step; t0 < N; t0 += step) {
     pc.load(src, stride, t0, M, chirp);
-    pack_store<TSRC, T, BS>(U, s_drev, pc, t0, M, N, active, ramp, e0, e1);
+    pack_store<TSRC, T, BS, G>(U, s_drev, pc, t0, M, N, active, ramp, e0, e1);
   }
 }
 
 // ---------------------------------------------------------------- rows
 
-template <typename TS, typename T, int MODE, bool BS>
-__global__ __launch_bounds__(256) void rows_w_kernel(
+template <typename TS, typename T, int MODE, bool BS, int G, int MASK>
+__global__ __launch_bounds__(256 * G) void rows_w_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int n1, int m, WDesc wd,
     const V2<T> *__restrict__ tw, const int *__restrict__ drev, const V2<T> *__restrict__ post,
     const V2<T> *__restrict__ chirp, const V2<T> *__restrict__ bhat, T alpha, T scale, T tau,
@@ -354,8 +382,11 @@ __global__ __launch_bounds__(256) void rows_w_kernel(
     partial = J.part ? J.part + (size_t)kit * J.nblk : nullptr;
   }
   const int M = wd.M, N = wd.N;
-  const int W = blockDim.x >> 6;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // G wavefronts per sequence; butterflies and elements are dealt to the
+  // 64 G lanes of a sequence interleaved (lane-major across its waves)
+  const int W = (blockDim.x >> 6) / G;
+  const int wave = (threadIdx.x >> 6) / G;
+  const int lane = (threadIdx.x & 63) * G + (threadIdx.x >> 6) % G;
   const int row = xcd_remap(blockIdx.x, gridDim.x) * W + wave;
   const bool active = row < n1;
   const size_t auxb = MODE == ROW_INV_UPDATE ? 2 * (size_t)m * sizeof(TS) : 0;
@@ -366,22 +397,22 @@ __global__ __launch_bounds__(256) void rows_w_kernel(
   TS *sx = reinterpret_cast<TS *>(Ly.aux);
   TS *sf = sx + m;
   // one batch of global loads: this wave's row, x and f (update), tables
-  PackChunk<TS, T, BS> pc;
+  PackChunk<TS, T, BS, G> pc;
   pc.load(src, 1, lane, M, chirp);
   const T e0 = T(src[0]), e1 = T(src[m - 1]);
   if (MODE == ROW_INV_UPDATE) {
-    for (int k0 = lane; k0 < m; k0 += 64 * kRowChunk) {
-      TS a[kRowChunk], b[kRowChunk];
+    for (int k0 = lane; k0 < m; k0 += 64 * G * RC<G>::value) {
+      TS a[RC<G>::value], b[RC<G>::value];
 #pragma unroll
-      for (int c = 0; c < kRowChunk; ++c) {
-        const int kr = k0 + 64 * c;
+      for (int c = 0; c < RC<G>::value; ++c) {
+        const int kr = k0 + 64 * G * c;
         const int k = kr < m ? kr : m - 1;
         a[c] = dst[k];
         b[c] = fr ? fr[k] : TS(0);
       }
 #pragma unroll
-      for (int c = 0; c < kRowChunk; ++c) {
-        const int k = k0 + 64 * c;
+      for (int c = 0; c < RC<G>::value; ++c) {
+        const int k = k0 + 64 * G * c;
         if (k < m) {
           sx[k] = a[c];
           sf[k] = b[c];
@@ -391,25 +422,25 @@ __global__ __launch_bounds__(256) void rows_w_kernel(
   }
   load_tables<T>(Ly, tw, wd.twn, post, M, drev, N);
   __syncthreads();
-  pack_all<TS, T, BS>(Ly.U, Ly.drev, pc, src, 1, lane, M, N, chirp, active, MODE == ROW_FWD, e0,
+  pack_all<TS, T, BS, G>(Ly.U, Ly.drev, pc, src, 1, lane, M, N, chirp, active, MODE == ROW_FWD, e0,
                       e1);
   __syncthreads();
-  fft_full<T, BS>(Ly.U, wd, Ly.tw, bhat, lane);
+  fft_full<T, BS, G, MASK>(Ly.U, wd, Ly.tw, bhat, lane);
   double ss = 0.0;
   if (active) {
     const T invM = T(1) / T(M);
-    for (int k0 = lane; k0 < m; k0 += 64 * kPostChunk) {
-      T val[kPostChunk];
+    for (int k0 = lane; k0 < m; k0 += 64 * G * PC<G>::value) {
+      T val[PC<G>::value];
 #pragma unroll
-      for (int c = 0; c < kPostChunk; ++c) {
-        const int kr = k0 + 64 * c;
+      for (int c = 0; c < PC<G>::value; ++c) {
+        const int kr = k0 + 64 * G * c;
         const int k = kr < m ? kr : k0;
         val[c] = wcoef<T, MODE != ROW_FWD, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha,
                                                e0, e1, invM);
       }
 #pragma unroll
-      for (int c = 0; c < kPostChunk; ++c) {
-        const int k = k0 + 64 * c;
+      for (int c = 0; c < PC<G>::value; ++c) {
+        const int k = k0 + 64 * G * c;
         if (k >= m) continue;
         if (MODE == ROW_INV_UPDATE) {
           const TS xn = TS(T(sx[k]) + tau * val[c]);
@@ -434,8 +465,8 @@ __global__ __launch_bounds__(256) void rows_w_kernel(
 
 // ------------------------------------------------------------- columns
 
-template <typename TS, typename T, int MODE, bool BS>
-__global__ __launch_bounds__(256) void cols_w_kernel(
+template <typename TS, typename T, int MODE, bool BS, int G, int MASK>
+__global__ __launch_bounds__(256 * G) void cols_w_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int m, int n2, WDesc wd,
     const V2<T> *__restrict__ tw, const int *__restrict__ drev, const V2<T> *__restrict__ post,
     const V2<T> *__restrict__ chirp, const V2<T> *__restrict__ bhat, T alpha, T scale,
@@ -448,8 +479,11 @@ __global__ __launch_bounds__(256) void cols_w_kernel(
     dflt = static_cast<const T *>(J.aux);
   }
   const int M = wd.M, N = wd.N;
-  const int W = blockDim.x >> 6;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // G wavefronts per sequence; butterflies and elements are dealt to the
+  // 64 G lanes of a sequence interleaved (lane-major across its waves)
+  const int W = (blockDim.x >> 6) / G;
+  const int wave = (threadIdx.x >> 6) / G;
+  const int lane = (threadIdx.x & 63) * G + (threadIdx.x >> 6) % G;
   const int col = xcd_remap(blockIdx.x, gridDim.x) * W + wave;
   const bool active = col < n2;
   const size_t auxb = MODE == COL_FWD_D_INV ? (size_t)m * sizeof(T) : 0;
@@ -457,75 +491,82 @@ __global__ __launch_bounds__(256) void cols_w_kernel(
   T *S = reinterpret_cast<T *>(Ly.aux);
   const long ld = n2;
   const TS *src = in + (active ? col : 0);
-  PackChunk<TS, T, BS> pc;
+  PackChunk<TS, T, BS, G> pc;
   pc.load(src, ld, lane, M, chirp);
   T e0 = T(src[0]);
   T e1 = T(src[(long)(m - 1) * ld]);
   if (MODE == COL_FWD_D_INV) {
     // filter column into the staging row (overwritten in place below)
     const T *dcol = dflt + (active ? col : 0);
-    for (int k0 = lane; k0 < m; k0 += 64 * kRowChunk) {
-      T a[kRowChunk];
+    for (int k0 = lane; k0 < m; k0 += 64 * G * RC<G>::value) {
+      T a[RC<G>::value];
 #pragma unroll
-      for (int c = 0; c < kRowChunk; ++c) {
-        const int kr = k0 + 64 * c;
+      for (int c = 0; c < RC<G>::value; ++c) {
+        const int kr = k0 + 64 * G * c;
         a[c] = dcol[(long)(kr < m ? kr : m - 1) * ld];
       }
 #pragma unroll
-      for (int c = 0; c < kRowChunk; ++c) {
-        const int k = k0 + 64 * c;
+      for (int c = 0; c < RC<G>::value; ++c) {
+        const int k = k0 + 64 * G * c;
         if (k < m) S[k] = a[c];
       }
     }
   }
   load_tables<T>(Ly, tw, wd.twn, post, M, drev, N);
   __syncthreads();
-  pack_all<TS, T, BS>(Ly.U, Ly.drev, pc, src, ld, lane, M, N, chirp, active, MODE != COL_INV, e0,
-                      e1);
-  __syncthreads();
-  fft_full<T, BS>(Ly.U, wd, Ly.tw, bhat, lane);
   const T invM = T(1) / T(M);
-  if (MODE == COL_FWD_D_INV) {
-    // S[k] <- d_k * (T~ y)_k (each lane reads and writes only its own S[k])
-    for (int k0 = lane; k0 < m; k0 += 64 * kPostChunk) {
-      T val[kPostChunk];
-#pragma unroll
-      for (int c = 0; c < kPostChunk; ++c) {
-        const int kr = k0 + 64 * c;
-        const int k = kr < m ? kr : k0;
-        val[c] = wcoef<T, false, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha, e0, e1,
-                                     invM);
-      }
-#pragma unroll
-      for (int c = 0; c < kPostChunk; ++c) {
-        const int k = k0 + 64 * c;
-        if (k < m) S[k] = val[c] * S[k];
+  // the fused pass runs the transform twice through one call site (forward
+  // with the ramp removed, then the inverse of the filtered coefficients)
+  constexpr int NPASS = MODE == COL_FWD_D_INV ? 2 : 1;
+#pragma nounroll
+  for (int pass = 0; pass < NPASS; ++pass) {
+    if (pass == 0) {
+      pack_all<TS, T, BS, G>(Ly.U, Ly.drev, pc, src, ld, lane, M, N, chirp, active,
+                             MODE != COL_INV, e0, e1);
+    } else {
+      e0 = S[0];
+      e1 = S[m - 1];
+      PackChunk<T, T, BS, G> ps;
+      for (int t0 = lane; t0 < N; t0 += 64 * G * RC<G>::value) {
+        ps.load(S, 1, t0, M, chirp);
+        pack_store<T, T, BS, G>(Ly.U, Ly.drev, ps, t0, M, N, active, false, e0, e1);
       }
     }
     __syncthreads();
-    e0 = S[0];
-    e1 = S[m - 1];
-    PackChunk<T, T, BS> ps;
-    for (int t0 = lane; t0 < N; t0 += 64 * kRowChunk) {
-      ps.load(S, 1, t0, M, chirp);
-      pack_store<T, T, BS>(Ly.U, Ly.drev, ps, t0, M, N, active, false, e0, e1);
+    fft_full<T, BS, G, MASK>(Ly.U, wd, Ly.tw, bhat, lane);
+    if (pass + 1 < NPASS) {
+      // S[k] <- d_k * (T~ y)_k (each lane reads and writes only its own S[k])
+      for (int k0 = lane; k0 < m; k0 += 64 * G * PC<G>::value) {
+        T val[PC<G>::value];
+#pragma unroll
+        for (int c = 0; c < PC<G>::value; ++c) {
+          const int kr = k0 + 64 * G * c;
+          const int k = kr < m ? kr : k0;
+          val[c] = wcoef<T, false, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha, e0, e1,
+                                       invM);
+        }
+#pragma unroll
+        for (int c = 0; c < PC<G>::value; ++c) {
+          const int k = k0 + 64 * G * c;
+          if (k < m) S[k] = val[c] * S[k];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    fft_full<T, BS>(Ly.U, wd, Ly.tw, bhat, lane);
   }
   if (active) {
-    for (int k0 = lane; k0 < m; k0 += 64 * kPostChunk) {
-      T val[kPostChunk];
+    for (int k0 = lane; k0 < m; k0 += 64 * G * PC<G>::value) {
+      T val[PC<G>::value];
 #pragma unroll
-      for (int c = 0; c < kPostChunk; ++c) {
-        const int kr = k0 + 64 * c;
+      for (int c = 0; c < PC<G>::value; ++c) {
+        const int kr = k0 + 64 * G * c;
         const int k = kr < m ? kr : k0;
         val[c] = wcoef<T, MODE != COL_FWD, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha,
                                                e0, e1, invM);
       }
 #pragma unroll
-      for (int c = 0; c < kPostChunk; ++c) {
-        const int k = k0 + 64 * c;
+      for (int c = 0; c < PC<G>::value; ++c) {
+        const int k = k0 + 64 * G * c;
         if (k < m) out[(long)k * ld + col] = TS(val[c]);
       }
     }
@@ -738,6 +779,13 @@ void wave_plan_free(WavePlan &w) {
   w.ok = false;
 }
 
+// Radices a plan uses, as a radix-set mask.
+static int plan_mask(const WavePlan &w) {
+  int m = 0;
+  for (int s = 0; s < w.nst; ++s) m |= 1 << rbit(w.R[s]);
+  return m;
+}
+
 static size_t rows_aux(const ar_plan_s *p) { return 2 * (size_t)p->n2 * p->esize; }
 static size_t cols_aux(const ar_plan_s *p) { return (size_t)p->n1 * p->csize; }
 
@@ -790,7 +838,7 @@ int wave_cols_algo(const ar_plan_s *p) {
   return w ? (w->bs ? 2 : 1) : 0;
 }
 
-template <typename TS, typename T, bool BS>
+template <typename TS, typename T, bool BS, int G, int MASK>
 static int wave_rows_t(const ar_plan_s *p, const WavePlan &w, const void *in, void *out, int mode,
                        double tau, const void *f_true, double *partial, const XJob *jobs,
                        int count, int kit, hipStream_t st) {
@@ -812,9 +860,10 @@ static int wave_rows_t(const ar_plan_s *p, const WavePlan &w, const void *in, vo
   auto tf = static_cast<const TS *>(f_true);
   hipError_t e = hipSuccess;
 #define AR_WROWS(MODE)                                                                          \
-  e = allow_lds_w(rows_w_kernel<TS, T, MODE, BS>, smem);                                        \
+  e = allow_lds_w(rows_w_kernel<TS, T, MODE, BS, G, MASK>, smem);                                     \
   if (e == hipSuccess) {                                                                        \
-    hipLaunchKernelGGL((rows_w_kernel<TS, T, MODE, BS>), grid, dim3(64 * W), smem, st, ti, to, \
+    hipLaunchKernelGGL((rows_w_kernel<TS, T, MODE, BS, G, MASK>), grid, dim3(64 * W * G), smem, st,  \
+                       ti, to,                                                                  \
                        p->n1, m, wd, tw, w.drev, post, chirp, bhat, alpha, scale, T(tau), tf,    \
                        partial, jobs, kit);                                                     \
     e = hipGetLastError();                                                                      \
@@ -834,11 +883,15 @@ static int wave_rows_d(const ar_plan_s *p, const void *in, void *out, int mode, 
                        const void *f_true, double *partial, const XJob *jobs, int count, int kit,
                        hipStream_t st) {
   const WavePlan &w = *row_plan(p);
-  if (w.bs)
-    return wave_rows_t<TS, T, true>(p, w, in, out, mode, tau, f_true, partial, jobs, count, kit,
-                                    st);
-  return wave_rows_t<TS, T, false>(p, w, in, out, mode, tau, f_true, partial, jobs, count, kit,
-                                   st);
+  const bool g2 = p->tune[AR_TUNE_ROW_LANES] == 2;
+#define AR_R(BS_, G_, MASK_)                                                                   \
+  wave_rows_t<TS, T, BS_, G_, MASK_>(p, w, in, out, mode, tau, f_true, partial, jobs, count,  \
+                                     kit, st)
+  if (w.bs) return g2 ? AR_R(true, 2, 0) : AR_R(true, 1, 0);
+  if (plan_mask(w) & ~kMask3_11_31)
+    return g2 ? AR_R(false, 2, kMaskAll) : AR_R(false, 1, kMaskAll);
+  return g2 ? AR_R(false, 2, kMask3_11_31) : AR_R(false, 1, kMask3_11_31);
+#undef AR_R
 }
 
 static int wave_rows_any(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
@@ -865,7 +918,7 @@ int wave_rows_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, i
   return wave_rows_any(lead, nullptr, nullptr, mode, tau, nullptr, nullptr, jobs, count, k, st);
 }
 
-template <typename TS, typename T, bool BS>
+template <typename TS, typename T, bool BS, int G, int MASK>
 static int wave_cols_t(const ar_plan_s *p, const WavePlan &w, const void *in, void *out, int mode,
                        const XJob *jobs, int count, hipStream_t st) {
   const int m = p->n1, M = w.M;
@@ -886,9 +939,10 @@ static int wave_cols_t(const ar_plan_s *p, const WavePlan &w, const void *in, vo
   auto td = static_cast<const T *>(p->d);
   hipError_t e = hipSuccess;
 #define AR_WCOLS(MODE)                                                                          \
-  e = allow_lds_w(cols_w_kernel<TS, T, MODE, BS>, smem);                                        \
+  e = allow_lds_w(cols_w_kernel<TS, T, MODE, BS, G, MASK>, smem);                                     \
   if (e == hipSuccess) {                                                                        \
-    hipLaunchKernelGGL((cols_w_kernel<TS, T, MODE, BS>), grid, dim3(64 * W), smem, st, ti, to, \
+    hipLaunchKernelGGL((cols_w_kernel<TS, T, MODE, BS, G, MASK>), grid, dim3(64 * W * G), smem, st,  \
+                       ti, to,                                                                  \
                        m, p->n2, wd, tw, w.drev, post, chirp, bhat, alpha, scale, td, jobs);   \
     e = hipGetLastError();                                                                      \
   }
@@ -906,8 +960,13 @@ template <typename TS, typename T>
 static int wave_cols_d(const ar_plan_s *p, const void *in, void *out, int mode, const XJob *jobs,
                        int count, hipStream_t st) {
   const WavePlan &w = *col_plan(p);
-  if (w.bs) return wave_cols_t<TS, T, true>(p, w, in, out, mode, jobs, count, st);
-  return wave_cols_t<TS, T, false>(p, w, in, out, mode, jobs, count, st);
+  const bool g2 = p->tune[AR_TUNE_COL_LANES] == 2;
+#define AR_C(BS_, G_, MASK_) wave_cols_t<TS, T, BS_, G_, MASK_>(p, w, in, out, mode, jobs, count, st)
+  if (w.bs) return g2 ? AR_C(true, 2, 0) : AR_C(true, 1, 0);
+  if (plan_mask(w) & ~kMask3_11_31)
+    return g2 ? AR_C(false, 2, kMaskAll) : AR_C(false, 1, kMaskAll);
+  return g2 ? AR_C(false, 2, kMask3_11_31) : AR_C(false, 1, kMask3_11_31);
+#undef AR_C
 }
 
 static int wave_cols_any(const ar_plan_s *p, const void *in, void *out, int mode,

@@ -357,6 +357,29 @@ def test_batch_sizes_transform_and_blur():
 
 
 @pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("n1,n2", [(1024, 1024), (192, 385), (33, 2048)])
+def test_transform_two_waves_per_sequence(n1, n2, lanes, dt):
+    """Transforms with one or two wavefronts per row / column against the
+    oracle (the default FFT form of each length)."""
+    say(f"lanes {lanes} n=({n1},{n2}) {dt}")
+    rng = np.random.default_rng(n1 * 3 + n2)
+    X = rng.standard_normal((n1, n2)).astype(NDT[dt]).astype(np.float64)
+    with P.Plan(n1, n2, np.ones((1, 1)), dtype=dt) as plan:
+        plan.ar_plan_tune(P.AR_TUNE_ROW_LANES, lanes)
+        plan.ar_plan_tune(P.AR_TUNE_COL_LANES, lanes)
+        x = dev(X, TDT[dt])
+        c = torch.empty_like(x)
+        plan.ar_transform(x, c)
+        e = rel(host(c), O.ar_fwd(X))
+        assert e <= TOL_T[dt], e
+        xr = torch.empty_like(x)
+        plan.ar_transform_inv(c, xr)
+        e = rel(host(xr), X)
+        assert e <= 4 * TOL_T[dt], e
+
+
+@pytest.mark.parametrize("dt", DTS)
 @pytest.mark.parametrize("algo", [1, 2])
 @pytest.mark.parametrize("n1,n2", [(128, 96), (256, 300), (193, 385), (1024, 1024), (512, 129)])
 def test_transform_fft_forms(n1, n2, algo, dt):
@@ -391,11 +414,12 @@ def test_transform_fft_forms(n1, n2, algo, dt):
         assert e <= TOL_D[dt], e
 
 
-@pytest.mark.parametrize("dt", ["f32", "f32x"])
+@pytest.mark.parametrize("dt", ["f32", "f32x", "f64"])
 def test_tunables_do_not_change_results(dt):
-    """For a fixed FFT form every launch setting of the transform engine
-    gives bitwise the same preconditioner output; the autotuner picks one
-    of the settings (and either FFT form)."""
+    """For a fixed FFT form and one wavefront per sequence every launch
+    setting of the transform engine gives bitwise the same preconditioner
+    output (two wavefronts per sequence: equal to rounding); the autotuner
+    picks one of the settings (and either FFT form)."""
     n1, n2 = 300, 256          # n - 1 = 299 = 13 * 23 and 255 = 3 * 5 * 17
     H = synth.psf_random(3, 4, seed=2)
     Y = np.random.default_rng(1).standard_normal((n1, n2))
@@ -408,18 +432,26 @@ def test_tunables_do_not_change_results(dt):
             plan.ar_plan_tune(P.AR_TUNE_ROW_ALGO, algo)
             plan.ar_plan_tune(P.AR_TUNE_COL_ALGO, algo)
             for key in (P.AR_TUNE_ROW_WAVES, P.AR_TUNE_ROW_EXCL, P.AR_TUNE_COL_WAVES,
-                        P.AR_TUNE_COL_EXCL):
+                        P.AR_TUNE_COL_EXCL, P.AR_TUNE_ROW_LANES, P.AR_TUNE_COL_LANES):
                 plan.ar_plan_tune(key, 0)
             plan.ar_precond_solve(y, z)
             ref = refs[algo] = host(z)
-            for w in (1, 2, 4):
-                for x in (0, 1):
-                    for key_w, key_x in ((P.AR_TUNE_ROW_WAVES, P.AR_TUNE_ROW_EXCL),
-                                         (P.AR_TUNE_COL_WAVES, P.AR_TUNE_COL_EXCL)):
-                        plan.ar_plan_tune(key_w, w)
-                        plan.ar_plan_tune(key_x, x)
-                        plan.ar_precond_solve(y, z)
-                        assert np.array_equal(host(z), ref)
+            for g in (1, 2):
+                plan.ar_plan_tune(P.AR_TUNE_ROW_LANES, g)
+                plan.ar_plan_tune(P.AR_TUNE_COL_LANES, g)
+                for w in (1, 2, 4):
+                    for x in (0, 1):
+                        for key_w, key_x in ((P.AR_TUNE_ROW_WAVES, P.AR_TUNE_ROW_EXCL),
+                                             (P.AR_TUNE_COL_WAVES, P.AR_TUNE_COL_EXCL)):
+                            plan.ar_plan_tune(key_w, w)
+                            plan.ar_plan_tune(key_x, x)
+                            plan.ar_precond_solve(y, z)
+                            if g == 1:
+                                assert np.array_equal(host(z), ref), (algo, g, w, x)
+                            else:
+                                # a separately compiled code path: equal up to the
+                                # compiler's FMA contraction choices
+                                assert rel(host(z), ref) <= TOL_D[dt] / 10, (algo, g, w, x)
         assert rel(refs[1], refs[2]) <= TOL_D[dt]
         us = plan.ar_plan_autotune()
         assert us > 0
@@ -428,10 +460,7 @@ def test_tunables_do_not_change_results(dt):
         ca = plan.ar_plan_get_tune(P.AR_TUNE_COL_ALGO)
         assert ra in (1, 2) and ca in (1, 2)
         plan.ar_precond_solve(y, z)
-        if ra == ca:
-            assert np.array_equal(host(z), refs[ra])
-        else:
-            assert rel(host(z), refs[1]) <= TOL_D[dt]
+        assert rel(host(z), refs[1]) <= TOL_D[dt]
         with pytest.raises(P.ArError):
             plan.ar_plan_tune(P.AR_TUNE_ROW_WAVES, 3)
         with pytest.raises(P.ArError):

@@ -91,6 +91,15 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return s;
 }
 
+// Ordering fence: the FMAs that produce `acc` complete before any later
+// memory access is issued (the empty asm reads and writes the accumulators
+// and clobbers memory); it emits no instruction.
+template <typename T, int N>
+__device__ __forceinline__ void after(T (&acc)[N]) {
+#pragma unroll
+  for (int c = 0; c < N; ++c) asm volatile("" : "+v"(acc[c])::"memory");
+}
+
 // TS: storage type of images; T: compute type of the halo tile, weights
 // and accumulators (double for FP64 accumulation of FP32 images).
 // Q2 >= 0: compile-time column half-width (tap loop fully unrolled).
@@ -168,52 +177,75 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
   const int krows = 2 * q1 + 2;
   if constexpr (!GEN) {
     // Software-pipelined sliding window: input row k feeds output row 0
-    // with PSF row k and output row 1 with PSF row k - 1.  The next input
-    // row and PSF row (broadcast reads of the LDS weight copy) are issued
-    // before the current row's FMAs; indices are clamped, not branched.
+    // with PSF row k and output row 1 with PSF row k - 1.  Rows are taken
+    // two at a time (krows = 2 q1 + 2 is even) with ping-pong buffers for
+    // the input rows (va, vb) and the PSF rows (wa, wb), so no register
+    // copies rotate the window: the next input row is issued before the
+    // current row's FMAs, and a PSF row buffer is refilled (broadcast reads
+    // of the LDS weight copy) right after its last use.  `after` pins each
+    // refill behind the FMAs that read the old contents (a hoisted load needs
+    // a third buffer and register copies at the loop edge); indices are
+    // clamped.
     constexpr int KWc = 2 * Q2 + 1;
     constexpr int NV = RX + 2 * Q2;
     const T *sw = tile + (size_t)LH * pitch;
     const int klast = 2 * q1;
-    T vcur[NV], wcur[KWc], wprev[KWc];
+    T va[NV], vb[NV], wa[KWc], wb[KWc];
     {
       const T *rowp = tile + ly * pitch + lx;
 #pragma unroll
-      for (int t = 0; t < NV; ++t) vcur[t] = rowp[t];
+      for (int t = 0; t < NV; ++t) va[t] = rowp[t];
 #pragma unroll
-      for (int b = 0; b < KWc; ++b) {
-        wcur[b] = sw[b];
-        wprev[b] = T(0);
-      }
+      for (int b = 0; b < KWc; ++b) wa[b] = sw[b];
     }
-    for (int k = 0; k < krows; ++k) {
-      const int kn = k + 1 < krows ? k + 1 : k;
-      const int wn = k + 1 <= klast ? k + 1 : klast;
-      T vnext[NV], wnext[KWc];
-      const T *rowp = tile + (ly + kn) * pitch + lx;
+    for (int k = 0; k < krows; k += 2) {
+      // row k: input in va, PSF row k in wa, PSF row k - 1 in wb
+      {
+        const T *rowp = tile + (ly + k + 1) * pitch + lx;
 #pragma unroll
-      for (int t = 0; t < NV; ++t) vnext[t] = rowp[t];
-#pragma unroll
-      for (int b = 0; b < KWc; ++b) wnext[b] = sw[wn * KWc + b];
-      if (k <= klast) {
-#pragma unroll
-        for (int b = 0; b < KWc; ++b)
-#pragma unroll
-          for (int c = 0; c < RX; ++c) acc0[c] = fma(wcur[b], vcur[c + b], acc0[c]);
+        for (int t = 0; t < NV; ++t) vb[t] = rowp[t];
       }
       if (k >= 1) {
 #pragma unroll
         for (int b = 0; b < KWc; ++b)
 #pragma unroll
-          for (int c = 0; c < RX; ++c) acc1[c] = fma(wprev[b], vcur[c + b], acc1[c]);
+          for (int c = 0; c < RX; ++c) acc1[c] = fma(wb[b], va[c + b], acc1[c]);
+      }
+      after(acc1);
+      {
+        const int wn = k + 1 <= klast ? k + 1 : klast;
+#pragma unroll
+        for (int b = 0; b < KWc; ++b) wb[b] = sw[wn * KWc + b];
       }
 #pragma unroll
-      for (int b = 0; b < KWc; ++b) {
-        wprev[b] = wcur[b];
-        wcur[b] = wnext[b];
+      for (int b = 0; b < KWc; ++b)
+#pragma unroll
+        for (int c = 0; c < RX; ++c) acc0[c] = fma(wa[b], va[c + b], acc0[c]);
+      // row k + 1: input in vb, PSF row k + 1 in wb, PSF row k in wa
+      after(acc0);
+      {
+        const int kn = k + 2 < krows ? k + 2 : krows - 1;
+        const T *rowp = tile + (ly + kn) * pitch + lx;
+#pragma unroll
+        for (int t = 0; t < NV; ++t) va[t] = rowp[t];
       }
 #pragma unroll
-      for (int t = 0; t < NV; ++t) vcur[t] = vnext[t];
+      for (int b = 0; b < KWc; ++b)
+#pragma unroll
+        for (int c = 0; c < RX; ++c) acc1[c] = fma(wa[b], vb[c + b], acc1[c]);
+      after(acc1);
+      {
+        const int wn = k + 2 <= klast ? k + 2 : klast;
+#pragma unroll
+        for (int b = 0; b < KWc; ++b) wa[b] = sw[wn * KWc + b];
+      }
+      if (k + 1 <= klast) {
+#pragma unroll
+        for (int b = 0; b < KWc; ++b)
+#pragma unroll
+          for (int c = 0; c < RX; ++c) acc0[c] = fma(wb[b], vb[c + b], acc0[c]);
+      }
+      after(acc0);
     }
   } else {
     for (int k = 0; k < krows; ++k) {

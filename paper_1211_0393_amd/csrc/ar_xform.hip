@@ -465,6 +465,47 @@ __global__ __launch_bounds__(256 * G) void rows_w_kernel(
 
 // ------------------------------------------------------------- columns
 
+// Column block I/O (mixed-radix plans): the W columns of a workgroup are
+// read and written row by row by all its threads (thread t always serves
+// column t mod W), so one memory instruction covers 64 / W rows of W
+// adjacent elements instead of 64 rows of one element.  Row r of column c
+// is the odd-extension value z_r: it goes to the real or imaginary half of
+// the packed entry u_{r/2} (digit-reversed position) and, negated, to that
+// of u_{(2M - r)/2}.
+template <typename TS, int C>
+struct BlockChunk {
+  TS v[C];
+  __device__ __forceinline__ void load(const TS *col, long ld, int r0, int rstep, int m) {
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+      const int r = r0 + rstep * i;
+      v[i] = col[(long)(r < m ? r : m - 1) * ld];
+    }
+  }
+};
+
+template <typename TS, typename T, int C>
+__device__ __forceinline__ void block_scatter(V2<T> *Uc, const int *s_drev,
+                                              const BlockChunk<TS, C> &bc, int r0, int rstep,
+                                              int M, bool cact, bool ramp, T e0, T e1, T invM) {
+  T *Uf = reinterpret_cast<T *>(Uc);
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int r = r0 + rstep * i;
+    if (r > M) continue;
+    T z = T(bc.v[i]);
+    if (ramp) z -= e0 * (T(M - r) * invM) + e1 * (T(r) * invM);
+    z = (cact && r != 0 && r != M) ? z : T(0);
+    Uf[2 * s_drev[r >> 1] + (r & 1)] = z;
+    if (r >= 1 && r <= M - 1) {
+      const int tm = 2 * M - r;
+      Uf[2 * s_drev[tm >> 1] + (tm & 1)] = -z;
+    }
+  }
+}
+
+constexpr int kBlockChunk = 16;  // rows per thread per batch of block I/O
+
 template <typename TS, typename T, int MODE, bool BS, int G, int MASK>
 __global__ __launch_bounds__(256 * G) void cols_w_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int m, int n2, WDesc wd,
@@ -478,51 +519,96 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
     out = static_cast<TS *>(J.out);
     dflt = static_cast<const T *>(J.aux);
   }
+  // block I/O for mixed-radix plans; Bluestein plans (zero padding, chirp
+  // products) pack per wave from strided loads
+  constexpr bool BIO = !BS;
   const int M = wd.M, N = wd.N;
   // G wavefronts per sequence; butterflies and elements are dealt to the
   // 64 G lanes of a sequence interleaved (lane-major across its waves)
   const int W = (blockDim.x >> 6) / G;
   const int wave = (threadIdx.x >> 6) / G;
   const int lane = (threadIdx.x & 63) * G + (threadIdx.x >> 6) % G;
-  const int col = xcd_remap(blockIdx.x, gridDim.x) * W + wave;
+  const int col0 = xcd_remap(blockIdx.x, gridDim.x) * W;
+  const int col = col0 + wave;
   const bool active = col < n2;
-  const size_t auxb = MODE == COL_FWD_D_INV ? (size_t)m * sizeof(T) : 0;
+  // per-wave staging row: the filter column, then (block I/O) the outputs
+  const size_t auxb = (BIO || MODE == COL_FWD_D_INV) ? (size_t)m * sizeof(T) : 0;
   const WLayout<T> Ly(smem_raw, wd.twn, M, N, W, wave, auxb);
   T *S = reinterpret_cast<T *>(Ly.aux);
   const long ld = n2;
   const TS *src = in + (active ? col : 0);
-  PackChunk<TS, T, BS, G> pc;
-  pc.load(src, ld, lane, M, chirp);
   T e0 = T(src[0]);
   T e1 = T(src[(long)(m - 1) * ld]);
-  if (MODE == COL_FWD_D_INV) {
-    // filter column into the staging row (overwritten in place below)
-    const T *dcol = dflt + (active ? col : 0);
-    for (int k0 = lane; k0 < m; k0 += 64 * G * RC<G>::value) {
-      T a[RC<G>::value];
+  const T invM = T(1) / T(M);
+  // block I/O: this thread's column of the block and its rows
+  const int bc_c = threadIdx.x % W, bc_r0 = threadIdx.x / W, bc_step = blockDim.x / W;
+  const bool bc_act = col0 + bc_c < n2;
+  const TS *bsrc = in + (bc_act ? col0 + bc_c : 0);
+  V2<T> *const U0 = Ly.U - (size_t)wave * N;
+  T *const S0 = reinterpret_cast<T *>(Ly.aux - (size_t)wave * auxb);
+  T be0 = T(0), be1 = T(0);
+  BlockChunk<TS, kBlockChunk> bch;
+  PackChunk<TS, T, BS, G> pc;
+  if constexpr (BIO) {
+    bch.load(bsrc, ld, bc_r0, bc_step, m);
+    be0 = T(bsrc[0]);
+    be1 = T(bsrc[(long)(m - 1) * ld]);
+    if (MODE == COL_FWD_D_INV) {
+      // filter block into the staging rows (overwritten in place below)
+      const T *dsrc = dflt + (bc_act ? col0 + bc_c : 0);
+      T *Sc = S0 + (size_t)bc_c * m;
+      for (int r0 = bc_r0; r0 < m; r0 += bc_step * kBlockChunk) {
+        BlockChunk<T, kBlockChunk> dc;
+        dc.load(dsrc, ld, r0, bc_step, m);
 #pragma unroll
-      for (int c = 0; c < RC<G>::value; ++c) {
-        const int kr = k0 + 64 * G * c;
-        a[c] = dcol[(long)(kr < m ? kr : m - 1) * ld];
+        for (int i = 0; i < kBlockChunk; ++i) {
+          const int r = r0 + bc_step * i;
+          if (r < m) Sc[r] = dc.v[i];
+        }
       }
+    }
+  } else {
+    pc.load(src, ld, lane, M, chirp);
+    if (MODE == COL_FWD_D_INV) {
+      // filter column into the staging row (overwritten in place below)
+      const T *dcol = dflt + (active ? col : 0);
+      for (int k0 = lane; k0 < m; k0 += 64 * G * RC<G>::value) {
+        T a[RC<G>::value];
 #pragma unroll
-      for (int c = 0; c < RC<G>::value; ++c) {
-        const int k = k0 + 64 * G * c;
-        if (k < m) S[k] = a[c];
+        for (int c = 0; c < RC<G>::value; ++c) {
+          const int kr = k0 + 64 * G * c;
+          a[c] = dcol[(long)(kr < m ? kr : m - 1) * ld];
+        }
+#pragma unroll
+        for (int c = 0; c < RC<G>::value; ++c) {
+          const int k = k0 + 64 * G * c;
+          if (k < m) S[k] = a[c];
+        }
       }
     }
   }
   load_tables<T>(Ly, tw, wd.twn, post, M, drev, N);
   __syncthreads();
-  const T invM = T(1) / T(M);
   // the fused pass runs the transform twice through one call site (forward
   // with the ramp removed, then the inverse of the filtered coefficients)
   constexpr int NPASS = MODE == COL_FWD_D_INV ? 2 : 1;
 #pragma nounroll
   for (int pass = 0; pass < NPASS; ++pass) {
     if (pass == 0) {
-      pack_all<TS, T, BS, G>(Ly.U, Ly.drev, pc, src, ld, lane, M, N, chirp, active,
-                             MODE != COL_INV, e0, e1);
+      if constexpr (BIO) {
+        V2<T> *Uc = U0 + (size_t)bc_c * N;
+        const bool ramp = MODE != COL_INV;
+        block_scatter<TS, T, kBlockChunk>(Uc, Ly.drev, bch, bc_r0, bc_step, M, bc_act, ramp, be0,
+                                          be1, invM);
+        for (int r0 = bc_r0 + bc_step * kBlockChunk; r0 < m; r0 += bc_step * kBlockChunk) {
+          bch.load(bsrc, ld, r0, bc_step, m);
+          block_scatter<TS, T, kBlockChunk>(Uc, Ly.drev, bch, r0, bc_step, M, bc_act, ramp, be0,
+                                            be1, invM);
+        }
+      } else {
+        pack_all<TS, T, BS, G>(Ly.U, Ly.drev, pc, src, ld, lane, M, N, chirp, active,
+                               MODE != COL_INV, e0, e1);
+      }
     } else {
       e0 = S[0];
       e1 = S[m - 1];
@@ -554,20 +640,42 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
       __syncthreads();
     }
   }
-  if (active) {
-    for (int k0 = lane; k0 < m; k0 += 64 * G * PC<G>::value) {
-      T val[PC<G>::value];
+  // outputs of this wave's column: straight to memory, or (block I/O)
+  // through the staging row and then row by row for the whole block
+  for (int k0 = lane; k0 < m; k0 += 64 * G * PC<G>::value) {
+    T val[PC<G>::value];
 #pragma unroll
-      for (int c = 0; c < PC<G>::value; ++c) {
-        const int kr = k0 + 64 * G * c;
-        const int k = kr < m ? kr : k0;
-        val[c] = wcoef<T, MODE != COL_FWD, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha,
-                                               e0, e1, invM);
-      }
+    for (int c = 0; c < PC<G>::value; ++c) {
+      const int kr = k0 + 64 * G * c;
+      const int k = kr < m ? kr : k0;
+      val[c] = wcoef<T, MODE != COL_FWD, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha,
+                                             e0, e1, invM);
+    }
 #pragma unroll
-      for (int c = 0; c < PC<G>::value; ++c) {
-        const int k = k0 + 64 * G * c;
-        if (k < m) out[(long)k * ld + col] = TS(val[c]);
+    for (int c = 0; c < PC<G>::value; ++c) {
+      const int k = k0 + 64 * G * c;
+      if (k >= m) continue;
+      if constexpr (BIO) S[k] = val[c];
+      else if (active) out[(long)k * ld + col] = TS(val[c]);
+    }
+  }
+  if constexpr (BIO) {
+    __syncthreads();
+    const T *Sc = S0 + (size_t)bc_c * m;
+    TS *bdst = out + col0 + bc_c;
+    if (bc_act) {
+      for (int r0 = bc_r0; r0 < m; r0 += bc_step * kBlockChunk) {
+        T v[kBlockChunk];
+#pragma unroll
+        for (int i = 0; i < kBlockChunk; ++i) {
+          const int r = r0 + bc_step * i;
+          v[i] = Sc[r < m ? r : m - 1];
+        }
+#pragma unroll
+        for (int i = 0; i < kBlockChunk; ++i) {
+          const int r = r0 + bc_step * i;
+          if (r < m) bdst[(long)r * ld] = TS(v[i]);
+        }
       }
     }
   }

@@ -25,6 +25,16 @@ int hip_fail(hipError_t e, const char *what);
     if (e_ != hipSuccess) return ::ar::hip_fail(e_, #call);       \
   } while (0)
 
+// ------------------------------------------------------- global memory
+
+// Global-memory view of a device pointer.  A kernel whose image pointers
+// may come from a job table (batched launches) would otherwise reach them
+// through generic (flat) instructions, which also count against the LDS
+// wait counter, so every LDS wait would wait for outstanding global loads.
+template <typename T> using Gl = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ Gl<T> *gmem(T *p) { return (Gl<T> *)p; }
+
 // ---------------------------------------------------------------- complex
 
 template <typename T> struct V2 { T x, y; };

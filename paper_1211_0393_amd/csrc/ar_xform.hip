@@ -100,15 +100,17 @@ __device__ __forceinline__ void bfly(V2<T> *U, int N, int L, const V2<T> *__rest
   }
 }
 
-// Radix sets: a kernel compiled for a set contains only those codelets
-// (smaller code); the launcher picks a set that covers the plan's radices.
+// Radix sets: a kernel compiled for a set contains only those codelets.
 constexpr int rbit(int r) {
   return r == 2 ? 0 : r == 3 ? 1 : r == 4 ? 2 : r == 5 ? 3 : r == 7 ? 4 : r == 11 ? 5 : r == 13 ? 6
        : r == 17 ? 7 : r == 19 ? 8 : r == 23 ? 9 : r == 29 ? 10 : 11;
 }
 constexpr int kMaskAll = 0xfff;
-constexpr int kMask3_11_31 = (1 << rbit(3)) | (1 << rbit(11)) | (1 << rbit(31));  // 1023
-constexpr bool in_mask(int mask, int r) { return (mask >> rbit(r)) & 1; }
+// M = 1023 = 31 * 11 * 3 (rows or columns of 1024): the three stages are
+// fixed at compile time, so every stride, bound and table offset is a
+// constant.
+constexpr int kPlan1023 = -1;
+constexpr bool in_mask(int mask, int r) { return mask >= 0 && ((mask >> rbit(r)) & 1); }
 
 // DIT runs stages 0..nst-1 (digit-reversed in, natural out); DIF runs them
 // backwards (natural in, digit-reversed out).  Bluestein plans use radices
@@ -116,6 +118,16 @@ constexpr bool in_mask(int mask, int r) { return (mask >> rbit(r)) & 1; }
 template <typename T, bool DIF, bool BS, int G, int MASK>
 __device__ __forceinline__ void fft_run(V2<T> *U, const WDesc &wd, const V2<T> *__restrict__ tw,
                                         int lane) {
+  if constexpr (MASK == kPlan1023) {
+    // stages (R, L, twiddle offset): (31, 1, 0), (11, 31, 30), (3, 341, 340)
+    bfly<T, 31, DIF, G>(U, 1023, 1, tw, lane);
+    __syncthreads();
+    bfly<T, 11, DIF, G>(U, 1023, 31, tw + 30, lane);
+    __syncthreads();
+    bfly<T, 3, DIF, G>(U, 1023, 341, tw + 340, lane);
+    __syncthreads();
+    return;
+  }
   const int N = wd.N;
   for (int s = 0; s < wd.nst; ++s) {
     const int st = DIF ? wd.nst - 1 - s : s;
@@ -303,7 +315,8 @@ struct PackChunk {
   static constexpr int C = RC<G>::value, SL = 64 * G;
   T xr[C], xi[C];
   V2<T> w[BS ? C : 1];
-  __device__ __forceinline__ void load(const TSRC *src, long stride, int t0, int M,
+  template <typename P>
+  __device__ __forceinline__ void load(P src, long stride, int t0, int M,
                                        const V2<T> *__restrict__ chirp) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -336,24 +349,33 @@ __device__ __forceinline__ void pack_store(V2<T> *U, const int *s_drev,
                                            const PackChunk<TSRC, T, BS, G> &pc, int t0, int M,
                                            int N, bool active, bool ramp, T e0, T e1) {
   const T invM = T(1) / T(M);
+  constexpr int C = PackChunk<TSRC, T, BS, G>::C;
+  // all positions are read before the first store: a store to U could
+  // alias the table for the compiler, which would then serialise every
+  // read behind the previous store
+  int pos[C];
 #pragma unroll
-  for (int c = 0; c < PackChunk<TSRC, T, BS, G>::C; ++c) {
+  for (int c = 0; c < C; ++c) {
     const int t = t0 + 64 * G * c;
-    if (t >= N) continue;
+    pos[c] = s_drev[t < N ? t : 0];
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int t = t0 + 64 * G * c;
     V2<T> u{T(0), T(0)};
     if (active && t < M) {
       u.x = zfrom<T>(pc.xr[c], 2 * t, M, ramp, e0, e1, invM);
       u.y = zfrom<T>(pc.xi[c], 2 * t + 1, M, ramp, e0, e1, invM);
       if constexpr (BS) u = cmul(u, pc.w[c]);
     }
-    U[s_drev[t]] = u;
+    if (t < N) U[pos[c]] = u;
   }
 }
 
 // Pack the whole sequence (chunk 0 already loaded into pc).
 template <typename TSRC, typename T, bool BS, int G>
 __device__ __forceinline__ void pack_all(V2<T> *U, const int *s_drev,
-                                         PackChunk<TSRC, T, BS, G> &pc, const TSRC *src,
+                                         PackChunk<TSRC, T, BS, G> &pc, const Gl<TSRC> *src,
                                          long stride, int lane, int M, int N, const V2<T> *chirp,
                                          bool active, bool ramp, T e0, T e1) {
   constexpr int step = 64 * G * RC<G>::value;
@@ -381,7 +403,7 @@ __global__ __launch_bounds__(256 * G) void rows_w_kernel(
     f_true = static_cast<const TS *>(J.aux);
     partial = J.part ? J.part + (size_t)kit * J.nblk : nullptr;
   }
-  const int M = wd.M, N = wd.N;
+  const int M = MASK == kPlan1023 ? 1023 : wd.M, N = MASK == kPlan1023 ? 1023 : wd.N;
   // G wavefronts per sequence; butterflies and elements are dealt to the
   // 64 G lanes of a sequence interleaved (lane-major across its waves)
   const int W = (blockDim.x >> 6) / G;
@@ -391,9 +413,9 @@ __global__ __launch_bounds__(256 * G) void rows_w_kernel(
   const bool active = row < n1;
   const size_t auxb = MODE == ROW_INV_UPDATE ? 2 * (size_t)m * sizeof(TS) : 0;
   const WLayout<T> Ly(smem_raw, wd.twn, M, N, W, wave, auxb);
-  const TS *src = in + (size_t)(active ? row : 0) * m;
-  TS *dst = out + (size_t)(active ? row : 0) * m;
-  const TS *fr = f_true ? f_true + (size_t)(active ? row : 0) * m : nullptr;
+  const Gl<TS> *src = gmem(in) + (size_t)(active ? row : 0) * m;
+  Gl<TS> *dst = gmem(out) + (size_t)(active ? row : 0) * m;
+  const Gl<TS> *fr = f_true ? gmem(f_true) + (size_t)(active ? row : 0) * m : nullptr;
   TS *sx = reinterpret_cast<TS *>(Ly.aux);
   TS *sf = sx + m;
   // one batch of global loads: this wave's row, x and f (update), tables
@@ -459,7 +481,7 @@ __global__ __launch_bounds__(256 * G) void rows_w_kernel(
     __syncthreads();
     double *red = reinterpret_cast<double *>(smem_raw);
     const double s = wg_sum(ss, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (threadIdx.x == 0) gmem(partial)[blockIdx.x] = s;
   }
 }
 
@@ -475,7 +497,7 @@ __global__ __launch_bounds__(256 * G) void rows_w_kernel(
 template <typename TS, int C>
 struct BlockChunk {
   TS v[C];
-  __device__ __forceinline__ void load(const TS *col, long ld, int r0, int rstep, int m) {
+  __device__ __forceinline__ void load(const Gl<TS> *col, long ld, int r0, int rstep, int m) {
 #pragma unroll
     for (int i = 0; i < C; ++i) {
       const int r = r0 + rstep * i;
@@ -489,6 +511,16 @@ __device__ __forceinline__ void block_scatter(V2<T> *Uc, const int *s_drev,
                                               const BlockChunk<TS, C> &bc, int r0, int rstep,
                                               int M, bool cact, bool ramp, T e0, T e1, T invM) {
   T *Uf = reinterpret_cast<T *>(Uc);
+  // positions first (see pack_store), then the stores
+  int p0[C], p1[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int r = r0 + rstep * i;
+    const int rc = r < M ? r : M;
+    const int tm = 2 * M - (r >= 1 && r <= M - 1 ? r : 1);
+    p0[i] = 2 * s_drev[rc >> 1] + (rc & 1);
+    p1[i] = 2 * s_drev[tm >> 1] + (tm & 1);
+  }
 #pragma unroll
   for (int i = 0; i < C; ++i) {
     const int r = r0 + rstep * i;
@@ -496,11 +528,8 @@ __device__ __forceinline__ void block_scatter(V2<T> *Uc, const int *s_drev,
     T z = T(bc.v[i]);
     if (ramp) z -= e0 * (T(M - r) * invM) + e1 * (T(r) * invM);
     z = (cact && r != 0 && r != M) ? z : T(0);
-    Uf[2 * s_drev[r >> 1] + (r & 1)] = z;
-    if (r >= 1 && r <= M - 1) {
-      const int tm = 2 * M - r;
-      Uf[2 * s_drev[tm >> 1] + (tm & 1)] = -z;
-    }
+    Uf[p0[i]] = z;
+    if (r >= 1 && r <= M - 1) Uf[p1[i]] = -z;
   }
 }
 
@@ -522,7 +551,7 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
   // block I/O for mixed-radix plans; Bluestein plans (zero padding, chirp
   // products) pack per wave from strided loads
   constexpr bool BIO = !BS;
-  const int M = wd.M, N = wd.N;
+  const int M = MASK == kPlan1023 ? 1023 : wd.M, N = MASK == kPlan1023 ? 1023 : wd.N;
   // G wavefronts per sequence; butterflies and elements are dealt to the
   // 64 G lanes of a sequence interleaved (lane-major across its waves)
   const int W = (blockDim.x >> 6) / G;
@@ -536,14 +565,14 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
   const WLayout<T> Ly(smem_raw, wd.twn, M, N, W, wave, auxb);
   T *S = reinterpret_cast<T *>(Ly.aux);
   const long ld = n2;
-  const TS *src = in + (active ? col : 0);
+  const Gl<TS> *src = gmem(in) + (active ? col : 0);
   T e0 = T(src[0]);
   T e1 = T(src[(long)(m - 1) * ld]);
   const T invM = T(1) / T(M);
   // block I/O: this thread's column of the block and its rows
   const int bc_c = threadIdx.x % W, bc_r0 = threadIdx.x / W, bc_step = blockDim.x / W;
   const bool bc_act = col0 + bc_c < n2;
-  const TS *bsrc = in + (bc_act ? col0 + bc_c : 0);
+  const Gl<TS> *bsrc = gmem(in) + (bc_act ? col0 + bc_c : 0);
   V2<T> *const U0 = Ly.U - (size_t)wave * N;
   T *const S0 = reinterpret_cast<T *>(Ly.aux - (size_t)wave * auxb);
   T be0 = T(0), be1 = T(0);
@@ -555,7 +584,7 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
     be1 = T(bsrc[(long)(m - 1) * ld]);
     if (MODE == COL_FWD_D_INV) {
       // filter block into the staging rows (overwritten in place below)
-      const T *dsrc = dflt + (bc_act ? col0 + bc_c : 0);
+      const Gl<T> *dsrc = gmem(dflt) + (bc_act ? col0 + bc_c : 0);
       T *Sc = S0 + (size_t)bc_c * m;
       for (int r0 = bc_r0; r0 < m; r0 += bc_step * kBlockChunk) {
         BlockChunk<T, kBlockChunk> dc;
@@ -571,7 +600,7 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
     pc.load(src, ld, lane, M, chirp);
     if (MODE == COL_FWD_D_INV) {
       // filter column into the staging row (overwritten in place below)
-      const T *dcol = dflt + (active ? col : 0);
+      const Gl<T> *dcol = gmem(dflt) + (active ? col : 0);
       for (int k0 = lane; k0 < m; k0 += 64 * G * RC<G>::value) {
         T a[RC<G>::value];
 #pragma unroll
@@ -589,56 +618,51 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
   }
   load_tables<T>(Ly, tw, wd.twn, post, M, drev, N);
   __syncthreads();
-  // the fused pass runs the transform twice through one call site (forward
-  // with the ramp removed, then the inverse of the filtered coefficients)
-  constexpr int NPASS = MODE == COL_FWD_D_INV ? 2 : 1;
-#pragma nounroll
-  for (int pass = 0; pass < NPASS; ++pass) {
-    if (pass == 0) {
-      if constexpr (BIO) {
-        V2<T> *Uc = U0 + (size_t)bc_c * N;
-        const bool ramp = MODE != COL_INV;
-        block_scatter<TS, T, kBlockChunk>(Uc, Ly.drev, bch, bc_r0, bc_step, M, bc_act, ramp, be0,
-                                          be1, invM);
-        for (int r0 = bc_r0 + bc_step * kBlockChunk; r0 < m; r0 += bc_step * kBlockChunk) {
-          bch.load(bsrc, ld, r0, bc_step, m);
-          block_scatter<TS, T, kBlockChunk>(Uc, Ly.drev, bch, r0, bc_step, M, bc_act, ramp, be0,
-                                            be1, invM);
-        }
-      } else {
-        pack_all<TS, T, BS, G>(Ly.U, Ly.drev, pc, src, ld, lane, M, N, chirp, active,
-                               MODE != COL_INV, e0, e1);
+  // pass 0: the column with the ramp removed (forward) or as is (inverse)
+  if constexpr (BIO) {
+    V2<T> *Uc = U0 + (size_t)bc_c * N;
+    const bool ramp = MODE != COL_INV;
+    block_scatter<TS, T, kBlockChunk>(Uc, Ly.drev, bch, bc_r0, bc_step, M, bc_act, ramp, be0, be1,
+                                      invM);
+    for (int r0 = bc_r0 + bc_step * kBlockChunk; r0 < m; r0 += bc_step * kBlockChunk) {
+      bch.load(bsrc, ld, r0, bc_step, m);
+      block_scatter<TS, T, kBlockChunk>(Uc, Ly.drev, bch, r0, bc_step, M, bc_act, ramp, be0, be1,
+                                        invM);
+    }
+  } else {
+    pack_all<TS, T, BS, G>(Ly.U, Ly.drev, pc, src, ld, lane, M, N, chirp, active, MODE != COL_INV,
+                           e0, e1);
+  }
+  __syncthreads();
+  fft_full<T, BS, G, MASK>(Ly.U, wd, Ly.tw, bhat, lane);
+  if constexpr (MODE == COL_FWD_D_INV) {
+    // S[k] <- d_k * (T~ y)_k (each lane reads and writes only its own S[k])
+    for (int k0 = lane; k0 < m; k0 += 64 * G * PC<G>::value) {
+      T val[PC<G>::value];
+#pragma unroll
+      for (int c = 0; c < PC<G>::value; ++c) {
+        const int kr = k0 + 64 * G * c;
+        const int k = kr < m ? kr : k0;
+        val[c] = wcoef<T, false, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha, e0, e1,
+                                     invM);
       }
-    } else {
-      e0 = S[0];
-      e1 = S[m - 1];
-      PackChunk<T, T, BS, G> ps;
-      for (int t0 = lane; t0 < N; t0 += 64 * G * RC<G>::value) {
-        ps.load(S, 1, t0, M, chirp);
-        pack_store<T, T, BS, G>(Ly.U, Ly.drev, ps, t0, M, N, active, false, e0, e1);
+#pragma unroll
+      for (int c = 0; c < PC<G>::value; ++c) {
+        const int k = k0 + 64 * G * c;
+        if (k < m) S[k] = val[c] * S[k];
       }
     }
     __syncthreads();
-    fft_full<T, BS, G, MASK>(Ly.U, wd, Ly.tw, bhat, lane);
-    if (pass + 1 < NPASS) {
-      // S[k] <- d_k * (T~ y)_k (each lane reads and writes only its own S[k])
-      for (int k0 = lane; k0 < m; k0 += 64 * G * PC<G>::value) {
-        T val[PC<G>::value];
-#pragma unroll
-        for (int c = 0; c < PC<G>::value; ++c) {
-          const int kr = k0 + 64 * G * c;
-          const int k = kr < m ? kr : k0;
-          val[c] = wcoef<T, false, BS>(Ly.U, Ly.drev, chirp, k, M, Ly.post, scale, alpha, e0, e1,
-                                       invM);
-        }
-#pragma unroll
-        for (int c = 0; c < PC<G>::value; ++c) {
-          const int k = k0 + 64 * G * c;
-          if (k < m) S[k] = val[c] * S[k];
-        }
-      }
-      __syncthreads();
+    // pass 1: the inverse transform of the filtered coefficients
+    e0 = S[0];
+    e1 = S[m - 1];
+    PackChunk<T, T, BS, G> ps;
+    for (int t0 = lane; t0 < N; t0 += 64 * G * RC<G>::value) {
+      ps.load(S, 1, t0, M, chirp);
+      pack_store<T, T, BS, G>(Ly.U, Ly.drev, ps, t0, M, N, active, false, e0, e1);
     }
+    __syncthreads();
+    fft_full<T, BS, G, MASK>(Ly.U, wd, Ly.tw, bhat, lane);
   }
   // outputs of this wave's column: straight to memory, or (block I/O)
   // through the staging row and then row by row for the whole block
@@ -656,13 +680,13 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
       const int k = k0 + 64 * G * c;
       if (k >= m) continue;
       if constexpr (BIO) S[k] = val[c];
-      else if (active) out[(long)k * ld + col] = TS(val[c]);
+      else if (active) gmem(out)[(long)k * ld + col] = TS(val[c]);
     }
   }
   if constexpr (BIO) {
     __syncthreads();
     const T *Sc = S0 + (size_t)bc_c * m;
-    TS *bdst = out + col0 + bc_c;
+    Gl<TS> *bdst = gmem(out) + col0 + bc_c;
     if (bc_act) {
       for (int r0 = bc_r0; r0 < m; r0 += bc_step * kBlockChunk) {
         T v[kBlockChunk];
@@ -887,11 +911,12 @@ void wave_plan_free(WavePlan &w) {
   w.ok = false;
 }
 
-// Radices a plan uses, as a radix-set mask.
-static int plan_mask(const WavePlan &w) {
-  int m = 0;
-  for (int s = 0; s < w.nst; ++s) m |= 1 << rbit(w.R[s]);
-  return m;
+// The mixed-radix plan of M = 1023 with the stage layout the fixed-plan
+// kernels assume.
+static bool is_plan1023(const WavePlan &w) {
+  return !w.bs && w.M == 1023 && w.N == 1023 && w.nst == 3 && w.R[0] == 31 && w.R[1] == 11 &&
+         w.R[2] == 3 && w.L[0] == 1 && w.L[1] == 31 && w.L[2] == 341 && w.tw_off[0] == 0 &&
+         w.tw_off[1] == 30 && w.tw_off[2] == 340;
 }
 
 static size_t rows_aux(const ar_plan_s *p) { return 2 * (size_t)p->n2 * p->esize; }
@@ -996,9 +1021,8 @@ static int wave_rows_d(const ar_plan_s *p, const void *in, void *out, int mode, 
   wave_rows_t<TS, T, BS_, G_, MASK_>(p, w, in, out, mode, tau, f_true, partial, jobs, count,  \
                                      kit, st)
   if (w.bs) return g2 ? AR_R(true, 2, 0) : AR_R(true, 1, 0);
-  if (plan_mask(w) & ~kMask3_11_31)
-    return g2 ? AR_R(false, 2, kMaskAll) : AR_R(false, 1, kMaskAll);
-  return g2 ? AR_R(false, 2, kMask3_11_31) : AR_R(false, 1, kMask3_11_31);
+  if (is_plan1023(w)) return g2 ? AR_R(false, 2, kPlan1023) : AR_R(false, 1, kPlan1023);
+  return g2 ? AR_R(false, 2, kMaskAll) : AR_R(false, 1, kMaskAll);
 #undef AR_R
 }
 
@@ -1071,9 +1095,8 @@ static int wave_cols_d(const ar_plan_s *p, const void *in, void *out, int mode, 
   const bool g2 = p->tune[AR_TUNE_COL_LANES] == 2;
 #define AR_C(BS_, G_, MASK_) wave_cols_t<TS, T, BS_, G_, MASK_>(p, w, in, out, mode, jobs, count, st)
   if (w.bs) return g2 ? AR_C(true, 2, 0) : AR_C(true, 1, 0);
-  if (plan_mask(w) & ~kMask3_11_31)
-    return g2 ? AR_C(false, 2, kMaskAll) : AR_C(false, 1, kMaskAll);
-  return g2 ? AR_C(false, 2, kMask3_11_31) : AR_C(false, 1, kMask3_11_31);
+  if (is_plan1023(w)) return g2 ? AR_C(false, 2, kPlan1023) : AR_C(false, 1, kPlan1023);
+  return g2 ? AR_C(false, 2, kMaskAll) : AR_C(false, 1, kMaskAll);
 #undef AR_C
 }
 

@@ -62,8 +62,8 @@ __device__ __forceinline__ Rule ar_rule(int i, int n, int q, bool zero_ext) {
 // four distinct terms; corners give the double anti-reflection 4, -2, -2, 1).
 // All four loads are unconditional so a caller can batch them.
 template <typename T, typename TS>
-__device__ __forceinline__ T load_ext(const TS *__restrict__ in, int n1, int n2, int q1, int q2,
-                                      int i, int j, bool zero_ext) {
+__device__ __forceinline__ T load_ext(const Gl<TS> *__restrict__ in, int n1, int n2, int q1,
+                                      int q2, int i, int j, bool zero_ext) {
   const Rule a = ar_rule(i, n1, q1, zero_ext), b = ar_rule(j, n2, q2, zero_ext);
   const T x00 = T(in[(size_t)a.i0 * n2 + b.i0]);
   const T x01 = T(in[(size_t)a.i0 * n2 + b.i1]);
@@ -118,6 +118,8 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
   const int pitch = (LW + 3) & ~3;
   const int LH = TH + 2 * q1;
   T *tile = reinterpret_cast<T *>(smem_raw);
+  const Gl<TS> *gin = gmem(in);
+  const Gl<T> *gw = gmem(w);
 
   const int ty_tile = logical / tiles_x, tx_tile = logical - ty_tile * tiles_x;
   const int r0 = ty_tile * TH, c0 = tx_tile * TW;
@@ -129,7 +131,19 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
   // unconditional addresses) and then stores them, so a chunk costs one
   // memory latency instead of one per element
   const int lr = tid >> 6, lc = tid & 63;
-  constexpr int CR = 8, CC = 2;  // rows x column-sweeps per chunk
+  constexpr int CR = 12, CC = 2;  // rows x column-sweeps per chunk
+  // the PSF copy for LDS is loaded first, so that its latency overlaps
+  // the halo loads
+  constexpr int WPT = 4;
+  const int P = (2 * q1 + 1) * KW;
+  T wpre[WPT];
+  if constexpr (!GEN) {
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int e = tid + NT * i;
+      wpre[i] = gw[e < P ? e : 0];
+    }
+  }
   for (int a0 = lr; a0 < LH; a0 += 4 * CR) {
     for (int c0 = lc; c0 < LW; c0 += 64 * CC) {
       T vals[CR][CC];
@@ -137,7 +151,7 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
 #pragma unroll
         for (int i = 0; i < CR; ++i) {
           const int a = a0 + 4 * i < LH ? a0 + 4 * i : a0;
-          const TS *src = in + (size_t)(ib1 + a) * n2 + ib2;
+          const Gl<TS> *src = gin + (size_t)(ib1 + a) * n2 + ib2;
 #pragma unroll
           for (int j = 0; j < CC; ++j) {
             const int c = c0 + 64 * j < LW ? c0 + 64 * j : c0;
@@ -149,7 +163,7 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
         for (int i = 0; i < CR; ++i)
 #pragma unroll
           for (int j = 0; j < CC; ++j)
-            vals[i][j] = load_ext<T, TS>(in, n1, n2, q1, q2, ib1 + a0 + 4 * i, ib2 + c0 + 64 * j,
+            vals[i][j] = load_ext<T, TS>(gin, n1, n2, q1, q2, ib1 + a0 + 4 * i, ib2 + c0 + 64 * j,
                                          zero_ext != 0);
       }
 #pragma unroll
@@ -163,8 +177,12 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
   }
   if constexpr (!GEN) {
     T *swr = tile + (size_t)LH * pitch;
-    const int P = (2 * q1 + 1) * KW;
-    for (int e = tid; e < P; e += NT) swr[e] = w[e];
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int e = tid + NT * i;
+      if (e < P) swr[e] = wpre[i];
+    }
+    for (int e = tid + NT * WPT; e < P; e += NT) swr[e] = gw[e];
   }
   __syncthreads();
 
@@ -281,12 +299,12 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
       T val = r == 0 ? acc0[c] : acc1[c];
       const size_t o = (size_t)oi * m2 + oj;
       if (gsub) {
-        val = T(gsub[o]) - val;
+        val = T(gmem(gsub)[o]) - val;
         const TO rs = TO(val);
         ss += (double)rs * (double)rs;
-        out[o] = rs;
+        gmem(out)[o] = rs;
       } else {
-        out[o] = TO(val);
+        gmem(out)[o] = TO(val);
       }
     }
   }
@@ -294,7 +312,7 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
     // the tile is no longer read: reuse LDS for the reduction
     double *red = reinterpret_cast<double *>(smem_raw);
     const double s = block_sum<T>(ss, red);
-    if (tid == 0) *partial_slot = s;
+    if (tid == 0) *gmem(partial_slot) = s;
   }
 }
 
@@ -356,12 +374,12 @@ __device__ __forceinline__ void fold_at(const T *__restrict__ ext, TS *__restric
   build(j2, n2, q2, e2, w2, c2);
   T acc = T(0);
   for (int a = 0; a < c1; ++a) {
-    const T *row = ext + (size_t)(e1[a] + q1) * W + q2;
+    const Gl<T> *row = gmem(ext) + (size_t)(e1[a] + q1) * W + q2;
     T s = T(0);
     for (int b = 0; b < c2; ++b) s += T(w2[b]) * row[e2[b]];
     acc += T(w1[a]) * s;
   }
-  out[(size_t)j1 * n2 + j2] = TS(acc);
+  gmem(out)[(size_t)j1 * n2 + j2] = TS(acc);
 }
 
 template <typename TS, typename T>

@@ -376,7 +376,7 @@ def main():
     P_taps = (2 * plan.q1 + 1) * (2 * plan.q2 + 1)
     npx = n * n
     es = 4                                           # FP32 images
-    ds = 8 if a.dtype == "f32x" else 4               # filter in the compute type
+    ds = es                                          # filter (transposed) in the storage type
     phases = [
         ("residual blur r = g - A x", "alu", 2.0 * P_taps * npx, 3 * es * npx, "conv_kernel"),
         ("reblur y = A' r", "alu", 2.0 * P_taps * npx, 2 * es * npx, "conv_kernel"),

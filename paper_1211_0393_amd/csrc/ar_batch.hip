@@ -245,7 +245,7 @@ void fill_jobs(ar_batch_s *b, const void *const *g, void *const *x, const void *
       xfwd[G.job_off + j] = a;
       a.in = p->c;
       a.out = p->c;
-      a.aux = p->d;
+      a.aux = p->dT;
       xcol[G.job_off + j] = a;
       a.in = p->c;
       a.out = x[i];
@@ -636,7 +636,7 @@ extern "C" int ar_batch_autotune(ar_batch_t b, double *best_us, void *stream) {
       a.out = p->c;
       xfwd[G.job_off + j] = a;
       a.in = p->c;
-      a.aux = p->d;
+      a.aux = p->dT;
       xcol[G.job_off + j] = a;
       a.aux = nullptr;
       a.out = p->r;  // inverse rows into r (no update)

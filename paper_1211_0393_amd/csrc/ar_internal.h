@@ -130,6 +130,7 @@ struct ar_plan_s {
   double *lambda = nullptr;  // n1*n2 FP64 eigenvalues
   double *d64 = nullptr;     // n1*n2 FP64 filter
   void *d = nullptr;         // n1*n2 filter in the compute type
+  void *dT = nullptr;        // the filter transposed (n2 x n1) in the storage type
   ar::FftPlan fft_row;       // axis i2, length n2
   ar::FftPlan fft_col;       // axis i1, length n1
   // scratch owned by the plan
@@ -255,6 +256,8 @@ int spectrum_launch(ar_plan_s *p, hipStream_t st);
 int filter_launch(ar_plan_s *p, int filter, double param, hipStream_t st);
 // learned-filter kernels (ar_learned.hip)
 int gains_filter_launch(ar_plan_s *p, const float *gains, hipStream_t st);
+// dT <- transpose of d64 in the storage type (after every filter update)
+int filter_transpose_launch(ar_plan_s *p, hipStream_t st);
 int axpy_launch(const ar_plan_s *p, void *x, const void *yv, double tau, const void *f_true,
                 double *partial, int *nblocks_out, hipStream_t st);
 int axpy_blocks(const ar_plan_s *p);

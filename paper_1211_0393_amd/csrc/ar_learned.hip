@@ -483,7 +483,7 @@ int gains_filter_launch(ar_plan_s *p, const float *gains, hipStream_t st) {
   AR_HIP(hipGetLastError());
   p->filter = AR_FILTER_GAINS;
   p->filter_param = 0.0;
-  return AR_OK;
+  return filter_transpose_launch(p, st);
 }
 
 }  // namespace ar

@@ -247,6 +247,38 @@ int spectrum_launch(ar_plan_s *p, hipStream_t st) {
   return AR_OK;
 }
 
+// dT[j2][j1] = d64[j1][j2] in the storage type: the column pass reads the
+// filter of its column as one contiguous row.  32 x 32 tiles through LDS.
+template <typename TS>
+__global__ __launch_bounds__(256) void filter_transpose_kernel(const double *__restrict__ d64,
+                                                               TS *__restrict__ dT, int n1,
+                                                               int n2) {
+  __shared__ double tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int b1 = blockIdx.y * 32, b2 = blockIdx.x * 32;
+  for (int r = ty; r < 32; r += 8) {
+    const int j1 = b1 + r, j2 = b2 + tx;
+    tile[r][tx] = (j1 < n1 && j2 < n2) ? d64[(size_t)j1 * n2 + j2] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int j2 = b2 + r, j1 = b1 + tx;
+    if (j1 < n1 && j2 < n2) dT[(size_t)j2 * n1 + j1] = TS(tile[tx][r]);
+  }
+}
+
+int filter_transpose_launch(ar_plan_s *p, hipStream_t st) {
+  const dim3 grid((p->n2 + 31) / 32, (p->n1 + 31) / 32);
+  if (p->esize == 8)
+    hipLaunchKernelGGL(filter_transpose_kernel<double>, grid, dim3(256), 0, st, p->d64,
+                       static_cast<double *>(p->dT), p->n1, p->n2);
+  else
+    hipLaunchKernelGGL(filter_transpose_kernel<float>, grid, dim3(256), 0, st, p->d64,
+                       static_cast<float *>(p->dT), p->n1, p->n2);
+  AR_HIP(hipGetLastError());
+  return AR_OK;
+}
+
 int filter_launch(ar_plan_s *p, int filter, double param, hipStream_t st) {
   const size_t total = (size_t)p->n1 * p->n2;
   if (p->csize == 8)
@@ -258,7 +290,7 @@ int filter_launch(ar_plan_s *p, int filter, double param, hipStream_t st) {
   AR_HIP(hipGetLastError());
   p->filter = filter;
   p->filter_param = param;
-  return AR_OK;
+  return filter_transpose_launch(p, st);
 }
 
 int axpy_blocks(const ar_plan_s *p) { return elem_blocks((size_t)p->n1 * p->n2); }
@@ -347,7 +379,8 @@ static void plan_free(ar_plan_s *p) {
                   p->lambda,      p->d64,         p->d,            p->r,
                   p->y,           p->c,           p->ext,          p->partials,
                   p->scalars,     p->gains,       p->lscr,         p->mat_fwd_col,
-                  p->mat_inv_col, p->mat_fwdT_row, p->mat_invT_row, p->dscr};
+                  p->mat_inv_col, p->mat_fwdT_row, p->mat_invT_row, p->dscr,
+                  p->dT};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   fft_plan_free(p->fft_row);
@@ -410,6 +443,7 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
             alloc(&p->w_fwd, P * p->csize) && alloc(&p->w_rev, P * p->csize) &&
             alloc((void **)&p->lambda, npx * sizeof(double)) &&
             alloc((void **)&p->d64, npx * sizeof(double)) && alloc(&p->d, npx * p->csize) &&
+            alloc(&p->dT, npx * p->esize) &&
             alloc(&p->r, npx * p->esize) && alloc(&p->y, npx * p->esize) &&
             alloc(&p->c, npx * p->esize) && alloc(&p->ext, next * p->csize);
   if (!ok) {

@@ -277,35 +277,48 @@ size_t wlds_bytes(int twn, int M, int N, int W, size_t csize, size_t aux_bytes) 
 
 constexpr int kTabChunk = 4;  // table elements per thread per batch
 
-// Twiddle, post and digit-reversal tables into LDS; indices are clamped so
-// that all loads of a batch are issued before any store.
+// Twiddle, post and digit-reversal tables into LDS.  One batch holds
+// kTabChunk elements of each table per thread; indices are clamped so that
+// all loads of a batch are issued before any store, and a kernel issues its
+// first batch together with its other global loads (load), stores it after
+// them (store), then finishes the tables (rest).
 template <typename T>
-__device__ __forceinline__ void load_tables(const WLayout<T> &Ly, const V2<T> *__restrict__ tw,
-                                            int twn, const V2<T> *__restrict__ post, int M,
-                                            const int *__restrict__ drev, int N) {
-  const int nth = blockDim.x, tid = threadIdx.x;
-  int tot = twn > M + 1 ? twn : M + 1;
-  tot = tot > N ? tot : N;
-  const int twmax = twn > 0 ? twn - 1 : 0;
-  for (int e0 = tid; e0 < tot; e0 += nth * kTabChunk) {
-    V2<T> a[kTabChunk], p[kTabChunk];
-    int d[kTabChunk];
+struct TabChunk {
+  V2<T> a[kTabChunk], p[kTabChunk];
+  int d[kTabChunk];
+  __device__ __forceinline__ void load(int e0, const V2<T> *__restrict__ tw, int twn,
+                                       const V2<T> *__restrict__ post, int M,
+                                       const int *__restrict__ drev, int N) {
+    const int twmax = twn > 0 ? twn - 1 : 0;
 #pragma unroll
     for (int c = 0; c < kTabChunk; ++c) {
-      const int e = e0 + nth * c;
+      const int e = e0 + (int)blockDim.x * c;
       a[c] = tw[e < twn ? e : twmax];
       p[c] = post[e <= M ? e : M];
       d[c] = drev[e < N ? e : N - 1];
     }
+  }
+  __device__ __forceinline__ void store(const WLayout<T> &Ly, int e0, int twn, int M, int N) const {
 #pragma unroll
     for (int c = 0; c < kTabChunk; ++c) {
-      const int e = e0 + nth * c;
+      const int e = e0 + (int)blockDim.x * c;
       if (e < twn) Ly.tw[e] = a[c];
       if (e <= M) Ly.post[e] = p[c];
       if (e < N) Ly.drev[e] = d[c];
     }
   }
-}
+  __device__ __forceinline__ void rest(const WLayout<T> &Ly, const V2<T> *__restrict__ tw, int twn,
+                                       const V2<T> *__restrict__ post, int M,
+                                       const int *__restrict__ drev, int N) {
+    int tot = twn > M + 1 ? twn : M + 1;
+    tot = tot > N ? tot : N;
+    const int step = (int)blockDim.x * kTabChunk;
+    for (int e0 = (int)threadIdx.x + step; e0 < tot; e0 += step) {
+      load(e0, tw, twn, post, M, drev, N);
+      store(Ly, e0, twn, M, N);
+    }
+  }
+};
 
 // One chunk of the packed sequence: raw interior values x_j for j = 2t and
 // 2t + 1 (mirrored past M) and, for Bluestein, the chirp w_t; clamped
@@ -418,31 +431,53 @@ __global__ __launch_bounds__(256 * G) void rows_w_kernel(
   const Gl<TS> *fr = f_true ? gmem(f_true) + (size_t)(active ? row : 0) * m : nullptr;
   TS *sx = reinterpret_cast<TS *>(Ly.aux);
   TS *sf = sx + m;
-  // one batch of global loads: this wave's row, x and f (update), tables
+  // one batch of global loads: this wave's row, x and f (update), the
+  // first table batch; then the LDS stores
   PackChunk<TS, T, BS, G> pc;
   pc.load(src, 1, lane, M, chirp);
   const T e0 = T(src[0]), e1 = T(src[m - 1]);
+  constexpr int RCV = RC<G>::value;
+  TS ax[RCV], af[RCV];
   if (MODE == ROW_INV_UPDATE) {
-    for (int k0 = lane; k0 < m; k0 += 64 * G * RC<G>::value) {
-      TS a[RC<G>::value], b[RC<G>::value];
 #pragma unroll
-      for (int c = 0; c < RC<G>::value; ++c) {
+    for (int c = 0; c < RCV; ++c) {
+      const int kr = lane + 64 * G * c;
+      const int k = kr < m ? kr : m - 1;
+      ax[c] = dst[k];
+      af[c] = fr ? fr[k] : TS(0);
+    }
+  }
+  TabChunk<T> tb;
+  tb.load(threadIdx.x, tw, wd.twn, post, M, drev, N);
+  if (MODE == ROW_INV_UPDATE) {
+#pragma unroll
+    for (int c = 0; c < RCV; ++c) {
+      const int k = lane + 64 * G * c;
+      if (k < m) {
+        sx[k] = ax[c];
+        sf[k] = af[c];
+      }
+    }
+    for (int k0 = lane + 64 * G * RCV; k0 < m; k0 += 64 * G * RCV) {
+#pragma unroll
+      for (int c = 0; c < RCV; ++c) {
         const int kr = k0 + 64 * G * c;
         const int k = kr < m ? kr : m - 1;
-        a[c] = dst[k];
-        b[c] = fr ? fr[k] : TS(0);
+        ax[c] = dst[k];
+        af[c] = fr ? fr[k] : TS(0);
       }
 #pragma unroll
-      for (int c = 0; c < RC<G>::value; ++c) {
+      for (int c = 0; c < RCV; ++c) {
         const int k = k0 + 64 * G * c;
         if (k < m) {
-          sx[k] = a[c];
-          sf[k] = b[c];
+          sx[k] = ax[c];
+          sf[k] = af[c];
         }
       }
     }
   }
-  load_tables<T>(Ly, tw, wd.twn, post, M, drev, N);
+  tb.store(Ly, threadIdx.x, wd.twn, M, N);
+  tb.rest(Ly, tw, wd.twn, post, M, drev, N);
   __syncthreads();
   pack_all<TS, T, BS, G>(Ly.U, Ly.drev, pc, src, 1, lane, M, N, chirp, active, MODE == ROW_FWD, e0,
                       e1);
@@ -540,13 +575,13 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int m, int n2, WDesc wd,
     const V2<T> *__restrict__ tw, const int *__restrict__ drev, const V2<T> *__restrict__ post,
     const V2<T> *__restrict__ chirp, const V2<T> *__restrict__ bhat, T alpha, T scale,
-    const T *__restrict__ dflt, const XJob *__restrict__ jobs) {
+    const TS *__restrict__ dT, const XJob *__restrict__ jobs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if (jobs) {  // batched launch: problem blockIdx.y
     const XJob J = jobs[blockIdx.y];
     in = static_cast<const TS *>(J.in);
     out = static_cast<TS *>(J.out);
-    dflt = static_cast<const T *>(J.aux);
+    dT = static_cast<const TS *>(J.aux);
   }
   // block I/O for mixed-radix plans; Bluestein plans (zero padding, chirp
   // products) pack per wave from strided loads
@@ -578,45 +613,47 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
   T be0 = T(0), be1 = T(0);
   BlockChunk<TS, kBlockChunk> bch;
   PackChunk<TS, T, BS, G> pc;
+  TabChunk<T> tb;
+  // the filter of this wave's column: one contiguous row of the transposed
+  // filter (stored over the staging row, overwritten in place below)
+  constexpr int RCV = RC<G>::value;
+  const Gl<TS> *dcol = gmem(dT) + (size_t)(active ? col : 0) * m;
+  TS dv[RCV];
+  if (MODE == COL_FWD_D_INV) {
+#pragma unroll
+    for (int c = 0; c < RCV; ++c) {
+      const int k = lane + 64 * G * c;
+      dv[c] = dcol[k < m ? k : m - 1];
+    }
+  }
+  // one batch of global loads (column or column block, filter, first table
+  // batch), then the LDS stores
   if constexpr (BIO) {
     bch.load(bsrc, ld, bc_r0, bc_step, m);
     be0 = T(bsrc[0]);
     be1 = T(bsrc[(long)(m - 1) * ld]);
-    if (MODE == COL_FWD_D_INV) {
-      // filter block into the staging rows (overwritten in place below)
-      const Gl<T> *dsrc = gmem(dflt) + (bc_act ? col0 + bc_c : 0);
-      T *Sc = S0 + (size_t)bc_c * m;
-      for (int r0 = bc_r0; r0 < m; r0 += bc_step * kBlockChunk) {
-        BlockChunk<T, kBlockChunk> dc;
-        dc.load(dsrc, ld, r0, bc_step, m);
-#pragma unroll
-        for (int i = 0; i < kBlockChunk; ++i) {
-          const int r = r0 + bc_step * i;
-          if (r < m) Sc[r] = dc.v[i];
-        }
-      }
-    }
   } else {
     pc.load(src, ld, lane, M, chirp);
-    if (MODE == COL_FWD_D_INV) {
-      // filter column into the staging row (overwritten in place below)
-      const Gl<T> *dcol = gmem(dflt) + (active ? col : 0);
-      for (int k0 = lane; k0 < m; k0 += 64 * G * RC<G>::value) {
-        T a[RC<G>::value];
+  }
+  tb.load(threadIdx.x, tw, wd.twn, post, M, drev, N);
+  if (MODE == COL_FWD_D_INV) {
+    for (int k0 = lane;;) {
 #pragma unroll
-        for (int c = 0; c < RC<G>::value; ++c) {
-          const int kr = k0 + 64 * G * c;
-          a[c] = dcol[(long)(kr < m ? kr : m - 1) * ld];
-        }
+      for (int c = 0; c < RCV; ++c) {
+        const int k = k0 + 64 * G * c;
+        if (k < m) S[k] = T(dv[c]);
+      }
+      k0 += 64 * G * RCV;
+      if (k0 >= m) break;
 #pragma unroll
-        for (int c = 0; c < RC<G>::value; ++c) {
-          const int k = k0 + 64 * G * c;
-          if (k < m) S[k] = a[c];
-        }
+      for (int c = 0; c < RCV; ++c) {
+        const int k = k0 + 64 * G * c;
+        dv[c] = dcol[k < m ? k : m - 1];
       }
     }
   }
-  load_tables<T>(Ly, tw, wd.twn, post, M, drev, N);
+  tb.store(Ly, threadIdx.x, wd.twn, M, N);
+  tb.rest(Ly, tw, wd.twn, post, M, drev, N);
   __syncthreads();
   // pass 0: the column with the ramp removed (forward) or as is (inverse)
   if constexpr (BIO) {
@@ -1068,7 +1105,7 @@ static int wave_cols_t(const ar_plan_s *p, const WavePlan &w, const void *in, vo
   auto bhat = static_cast<const V2<T> *>(w.bhat);
   auto ti = static_cast<const TS *>(in);
   auto to = static_cast<TS *>(out);
-  auto td = static_cast<const T *>(p->d);
+  auto td = static_cast<const TS *>(p->dT);
   hipError_t e = hipSuccess;
 #define AR_WCOLS(MODE)                                                                          \
   e = allow_lds_w(cols_w_kernel<TS, T, MODE, BS, G, MASK>, smem);                                     \

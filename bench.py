@@ -28,6 +28,7 @@ import numpy as np
 
 METRIC = "Mpixel-iters/s at 1024² FP32 + GPU time to best rel. error, learned vs plain"
 WORKLOAD = "ar1024_f32_motion15"
+ITERS = 100   # iterations of one run of the workload (its configuration)
 
 # MI355X published peaks used for the roofline (dense, per GPU)
 HBM_PEAK_GBS = 8000.0
@@ -38,8 +39,9 @@ VALU_PEAK_TFLOPS = 78.6   # FP64 vector, and FP32 vector without packed FP32
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000,
+                    help="timed iterations, run as consecutive runs of at most 100 from x = 0")
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--dtype", default="f32x", choices=["f32x", "f32"])
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -343,16 +345,25 @@ def main():
                ("row_lanes", P.AR_TUNE_ROW_LANES), ("col_lanes", P.AR_TUNE_COL_LANES)]}
     x = torch.zeros_like(g)
 
+    def runs(total):
+        # the workload is a run of ITERS iterations from x = 0; `total` steps
+        # are that many consecutive runs (the last one possibly shorter)
+        return [min(ITERS, total - k) for k in range(0, total, ITERS)]
+
     # warm-up (untimed)
-    if a.warmup > 0:
-        plan.ar_deblur_iterate(g, x, a.warmup, want_resnorm=True)
-    x.zero_()
+    for k in runs(a.warmup):
+        x.zero_()
+        plan.ar_deblur_iterate(g, x, k, want_resnorm=True)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    rc, res, _, _ = plan.ar_deblur_iterate(g, x, a.steps, want_resnorm=True)
+    rc, res = 0, None
+    for k in runs(a.steps):
+        x.zero_()
+        rck, res, _, _ = plan.ar_deblur_iterate(g, x, k, want_resnorm=True)
+        rc = rc or rck
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -362,11 +373,11 @@ def main():
 
     # quality of the timed run and of the unpreconditioned reference run
     x.zero_()
-    rc_q, _, rre, best = plan.ar_deblur_iterate(g, x, a.steps, f_true=f, want_rre=True)
+    rc_q, _, rre, best = plan.ar_deblur_iterate(g, x, ITERS, f_true=f, want_rre=True)
     xr = torch.zeros_like(g)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    rc_p, _, rre_p, best_p = plan.ar_deblur_iterate(g, xr, a.steps, precondition=False,
+    rc_p, _, rre_p, best_p = plan.ar_deblur_iterate(g, xr, ITERS, precondition=False,
                                                     f_true=f, want_rre=True)
     plain_s = time.perf_counter() - t1
 
@@ -401,8 +412,8 @@ def main():
     roof = dict(rooflines[dom])
     roof["hbm_frac_of_step"] = round(npx * 36 / t_step / 1e9 / HBM_PEAK_GBS, 4)
 
-    batch = None if a.no_batch else bench_batch(torch, P, a.steps)
-    learned = bench_learned(torch, P, a.learned_images, a.steps) if a.learned_images > 0 else None
+    batch = None if a.no_batch else bench_batch(torch, P, ITERS)
+    learned = bench_learned(torch, P, a.learned_images, ITERS) if a.learned_images > 0 else None
     precision = None if a.no_precision else bench_precision(torch, P, 200)
     if a.copy_probe:
         src = torch.ones(64 << 20, device="cuda:0", dtype=torch.float32)
@@ -425,13 +436,13 @@ def main():
                                "(length 11 at 30 deg, Gaussian sigma 1), 0.5% noise, AR BCs, "
                                "D-Landweber with Tikhonov alpha 5e-3, reblur transpose, tau 1",
                    "n1": n, "n2": n, "psf": [15, 15], "alpha": p["alpha"],
-                   "iterations": a.steps, "parallelism": "single GPU"},
+                   "iterations": ITERS, "parallelism": "single GPU"},
         "status": rc,
         "quality": {"best_it": best, "best_rre": finite_min(rre),
                     "plain_best_it": best_p, "plain_best_rre": finite_min(rre_p),
                     "plain_run_s": round(plain_s, 5),
                     "diverged": bool(res is not None and not np.all(np.isfinite(res)))},
-        "tuning": dict(tuning, precond_us=tuned_us),
+        "tuning": dict(tuning, iteration_us=tuned_us),
         "roofline": roof,
         "kernels": rooflines,
         "cpu_baseline": cpu,

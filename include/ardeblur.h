@@ -185,11 +185,13 @@ int ar_plan_tune(ar_plan_t p, int key, int value);
 /* Read a tunable's current value into *value. */
 int ar_plan_get_tune(ar_plan_t p, int key, int *value);
 
-/* Autotuner: times every candidate setting of the tunables on this plan's
- * own scratch buffers with HIP events on `stream` (the kernels of one
- * preconditioner application), keeps the fastest, and returns the best
- * measured time of that application in *best_us (may be NULL).  Uses and
- * overwrites the plan's scratch; synchronizes `stream`. */
+/* Autotuner: times every candidate setting of the transform tunables with
+ * HIP events on `stream`, one axis after the other, on short runs of whole
+ * preconditioned iterations (reblur transpose) over zero images in buffers
+ * it allocates and frees, keeps the fastest, and returns the best measured
+ * time of one iteration in *best_us (may be NULL).  Uses and overwrites the
+ * plan's scratch; synchronizes `stream`.  Errors: AR_EHIP when the
+ * temporary buffers cannot be allocated. */
 int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream);
 
 /* Phase profiler of one (D-)Landweber iteration: after one untimed

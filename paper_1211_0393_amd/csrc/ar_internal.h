@@ -258,6 +258,9 @@ int filter_launch(ar_plan_s *p, int filter, double param, hipStream_t st);
 int gains_filter_launch(ar_plan_s *p, const float *gains, hipStream_t st);
 // dT <- transpose of d64 in the storage type (after every filter update)
 int filter_transpose_launch(ar_plan_s *p, hipStream_t st);
+// `iters` preconditioned reblur iterations on the stream, no scalars (the
+// autotuner's unit of work)
+int iterate_enqueue(ar_plan_s *p, const void *g, void *x, int iters, hipStream_t st);
 int axpy_launch(const ar_plan_s *p, void *x, const void *yv, double tau, const void *f_true,
                 double *partial, int *nblocks_out, hipStream_t st);
 int axpy_blocks(const ar_plan_s *p);

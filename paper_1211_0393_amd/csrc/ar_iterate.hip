@@ -94,6 +94,17 @@ int enqueue(ar_plan_s *p, const IterArgs &a, hipStream_t st) {
 
 }  // namespace
 
+int ar::iterate_enqueue(ar_plan_s *p, const void *g, void *x, int iters, hipStream_t st) {
+  IterArgs a{};
+  a.g = g;
+  a.x = x;
+  a.iters = iters;
+  a.tmode = AR_REBLUR;
+  a.precondition = 1;
+  a.tau = 1.0;
+  return enqueue(p, a, st);
+}
+
 extern "C" int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters, double tau,
                                  int tmode, int precondition, const void *f_true,
                                  double *resnorm_host, double *rre_host, int *best_it_host,

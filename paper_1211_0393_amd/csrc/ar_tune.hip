@@ -1,8 +1,9 @@
 // Launch tunables and the autotuner of a plan (gfx950).
 //
 // The autotuner times each candidate setting of the transform tunables
-// (FFT form, waves per workgroup, CU-exclusive workgroups) on the plan's
-// own scratch with HIP events, and keeps the fastest.  Settings change the
+// (FFT form, lanes per sequence, waves per workgroup, CU-exclusive
+// workgroups) on short runs of whole iterations with HIP events, and keeps
+// the fastest.  Settings change the
 // launch geometry or the FFT factorisation only; every setting computes the
 // same transform (up to rounding).
 #include <cfloat>
@@ -74,66 +75,63 @@ extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
   if (!p) return fail(AR_EINVAL, "ar_plan_autotune: null plan");
   AR_HIP(hipSetDevice(p->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
+  // The unit timed for every candidate is a short run of whole
+  // preconditioned iterations: a kernel's speed depends on what ran before
+  // it (its input was just written by another kernel, on other XCDs), which
+  // a repetition of the kernel on its own does not show.  Inputs are zero
+  // images in buffers owned by this call.
   const size_t bytes = (size_t)p->n1 * p->n2 * p->esize;
-  AR_HIP(hipMemsetAsync(p->y, 0, bytes, st));
-  const int reps = 5;
+  void *g = nullptr, *x = nullptr;
+  AR_HIP(hipMalloc(&g, bytes));
+  hipError_t e = hipMalloc(&x, bytes);
+  if (e != hipSuccess) {
+    (void)hipFree(g);
+    return hip_fail(e, "hipMalloc");
+  }
+  int rc = AR_OK;
+  if ((e = hipMemsetAsync(g, 0, bytes, st)) != hipSuccess ||
+      (e = hipMemsetAsync(x, 0, bytes, st)) != hipSuccess)
+    rc = hip_fail(e, "hipMemsetAsync");
+  const int reps = 4, iters = 3;
   const int waves[3] = {1, 2, 4};
-  // rows: forward and inverse pass
-  double best_r = DBL_MAX;
-  int br_a = 0, br_w = 0, br_x = 0;
-  int br_g = 0, bc_g = 0;
-  for (int a = 1; a <= 2; ++a) {
-    p->tune[AR_TUNE_ROW_ALGO] = a;
-    if (wave_rows_algo(p) != a) continue;  // that FFT form is not available here
-    for (int gl = 1; gl <= 2; ++gl)
-    for (int w : waves)
-      for (int x = 0; x < 2; ++x) {
-        p->tune[AR_TUNE_ROW_LANES] = gl;
-        p->tune[AR_TUNE_ROW_WAVES] = w;
-        p->tune[AR_TUNE_ROW_EXCL] = x;
-        double us = 0;
-        int rc = time_us(
-            [&]() {
-              int r = rows_launch(p, p->y, p->c, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
-              return r != AR_OK ? r
-                                : rows_launch(p, p->c, p->r, ROW_INV, 0.0, nullptr, nullptr,
-                                              nullptr, st);
-            },
-            st, reps, &us);
-        if (rc != AR_OK) return rc;
-        if (us < best_r) { best_r = us; br_a = a; br_w = w; br_x = x; br_g = gl; }
-      }
-  }
-  p->tune[AR_TUNE_ROW_ALGO] = br_a;
-  p->tune[AR_TUNE_ROW_LANES] = br_g;
-  p->tune[AR_TUNE_ROW_WAVES] = br_w;
-  p->tune[AR_TUNE_ROW_EXCL] = br_x;
-  if (best_r == DBL_MAX) best_r = 0;  // block-wide engine only
-  // columns: the fused forward / filter / inverse pass
-  double best_c = DBL_MAX;
-  int bc_a = 0, bc_w = 0, bc_x = 0;
-  for (int a = 1; a <= 2; ++a) {
-    p->tune[AR_TUNE_COL_ALGO] = a;
-    if (wave_cols_algo(p) != a) continue;
-    for (int gl = 1; gl <= 2; ++gl)
-    for (int w : waves)
-      for (int x = 0; x < 2; ++x) {
-        p->tune[AR_TUNE_COL_LANES] = gl;
-        p->tune[AR_TUNE_COL_WAVES] = w;
-        p->tune[AR_TUNE_COL_EXCL] = x;
-        double us = 0;
-        int rc = time_us([&]() { return cols_launch(p, p->c, p->c, COL_FWD_D_INV, st); }, st,
-                         reps, &us);
-        if (rc != AR_OK) return rc;
-        if (us < best_c) { best_c = us; bc_a = a; bc_w = w; bc_x = x; bc_g = gl; }
-      }
-  }
-  p->tune[AR_TUNE_COL_ALGO] = bc_a;
-  p->tune[AR_TUNE_COL_LANES] = bc_g;
-  p->tune[AR_TUNE_COL_WAVES] = bc_w;
-  p->tune[AR_TUNE_COL_EXCL] = bc_x;
-  if (best_c == DBL_MAX) best_c = 0;
-  if (best_us) *best_us = best_r + best_c;
+  auto run = [&]() { return iterate_enqueue(p, g, x, iters, st); };
+  // one axis at a time: (algo, lanes, waves, excl) keys of that axis
+  auto tune_axis = [&](int k_algo, int k_lanes, int k_waves, int k_excl, bool rows,
+                       double *best) {
+    *best = DBL_MAX;
+    int ba = 0, bg = 0, bw = 0, bx = 0;
+    for (int a = 1; a <= 2 && rc == AR_OK; ++a) {
+      p->tune[k_algo] = a;
+      if ((rows ? wave_rows_algo(p) : wave_cols_algo(p)) != a) continue;  // form not available
+      for (int gl = 1; gl <= 2 && rc == AR_OK; ++gl)
+        for (int w : waves)
+          for (int xx = 0; xx < 2 && rc == AR_OK; ++xx) {
+            p->tune[k_lanes] = gl;
+            p->tune[k_waves] = w;
+            p->tune[k_excl] = xx;
+            double us = 0;
+            rc = time_us(run, st, reps, &us);
+            if (rc == AR_OK && us < *best) { *best = us; ba = a; bg = gl; bw = w; bx = xx; }
+          }
+    }
+    p->tune[k_algo] = ba;
+    p->tune[k_lanes] = bg;
+    p->tune[k_waves] = bw;
+    p->tune[k_excl] = bx;
+    if (*best == DBL_MAX) *best = 0;  // block-wide engine only
+  };
+  double best_r = 0, best_c = 0;
+  if (rc == AR_OK)
+    tune_axis(AR_TUNE_ROW_ALGO, AR_TUNE_ROW_LANES, AR_TUNE_ROW_WAVES, AR_TUNE_ROW_EXCL, true,
+              &best_r);
+  if (rc == AR_OK)
+    tune_axis(AR_TUNE_COL_ALGO, AR_TUNE_COL_LANES, AR_TUNE_COL_WAVES, AR_TUNE_COL_EXCL, false,
+              &best_c);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(g);
+  (void)hipFree(x);
+  if (rc != AR_OK) return rc;
+  if (best_us) *best_us = (best_c > 0 ? best_c : best_r) / iters;
   return AR_OK;
 }
 

@@ -133,6 +133,9 @@ struct ar_plan_s {
   void *dT = nullptr;        // the filter transposed (n2 x n1) in the storage type
   ar::FftPlan fft_row;       // axis i2, length n2
   ar::FftPlan fft_col;       // axis i1, length n1
+  // FP32 tables of axis i2 for AR_F32_ACC64 plans: the iteration's fused
+  // inverse row pass and update run in FP32 arithmetic (after the filter)
+  ar::FftPlan fft_row32;
   // scratch owned by the plan
   void *r = nullptr, *y = nullptr, *c = nullptr;  // n1*n2 dtype each
   void *ext = nullptr;       // (n1+2q1)(n2+2q2) compute type, adjoint correlation

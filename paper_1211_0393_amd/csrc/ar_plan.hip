@@ -385,6 +385,7 @@ static void plan_free(ar_plan_s *p) {
     if (b) (void)hipFree(b);
   fft_plan_free(p->fft_row);
   fft_plan_free(p->fft_col);
+  fft_plan_free(p->fft_row32);
   delete p;
 }
 
@@ -460,6 +461,7 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
   if ((rc = spectrum_launch(p, st)) != AR_OK || (rc = filter_launch(p, AR_FILTER_TIKHONOV, 1e-2, st)) != AR_OK ||
       (rc = fft_plan_build(p->fft_row, n2, csize == 8, st)) != AR_OK ||
       (rc = fft_plan_build(p->fft_col, n1, csize == 8, st)) != AR_OK ||
+      (dtype == AR_F32_ACC64 && (rc = fft_plan_build(p->fft_row32, n2, false, st)) != AR_OK) ||
       (dtype == AR_F32_BF16X3 && (rc = dense_setup(p, st)) != AR_OK)) {
     plan_free(p);
     return rc;

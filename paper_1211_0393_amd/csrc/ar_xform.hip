@@ -1014,11 +1014,13 @@ int wave_cols_algo(const ar_plan_s *p) {
 }
 
 template <typename TS, typename T, bool BS, int G, int MASK>
-static int wave_rows_t(const ar_plan_s *p, const WavePlan &w, const void *in, void *out, int mode,
-                       double tau, const void *f_true, double *partial, const XJob *jobs,
-                       int count, int kit, hipStream_t st) {
+static int wave_rows_t(const ar_plan_s *p, const FftPlan &fp, const WavePlan &w, const void *in,
+                       void *out, int mode, double tau, const void *f_true, double *partial,
+                       const XJob *jobs, int count, int kit, hipStream_t st) {
   const int m = p->n2, M = w.M;
-  const int W = rows_waves(p, w);
+  // geometry from the plan's own tables, so that the FP32 variant has the
+  // same grid (and partial-sum count) as the compute-type one
+  const int W = rows_waves(p, *row_plan(p));
   const int blocks = (p->n1 + W - 1) / W;
   const dim3 grid(blocks, count);
   const size_t smem =
@@ -1027,7 +1029,7 @@ static int wave_rows_t(const ar_plan_s *p, const WavePlan &w, const void *in, vo
   const T alpha = T(std::sqrt((double)m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))));
   const T scale = T(std::sqrt(2.0 / M) / 4.0);
   auto tw = static_cast<const V2<T> *>(w.tw);
-  auto post = static_cast<const V2<T> *>(p->fft_row.post);
+  auto post = static_cast<const V2<T> *>(fp.post);
   auto chirp = static_cast<const V2<T> *>(w.chirp);
   auto bhat = static_cast<const V2<T> *>(w.bhat);
   auto ti = static_cast<const TS *>(in);
@@ -1054,14 +1056,15 @@ static int wave_rows_t(const ar_plan_s *p, const WavePlan &w, const void *in, vo
 }
 
 template <typename TS, typename T>
-static int wave_rows_d(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
-                       const void *f_true, double *partial, const XJob *jobs, int count, int kit,
-                       hipStream_t st) {
-  const WavePlan &w = *row_plan(p);
+static int wave_rows_d(const ar_plan_s *p, const FftPlan &fp, const void *in, void *out, int mode,
+                       double tau, const void *f_true, double *partial, const XJob *jobs,
+                       int count, int kit, hipStream_t st) {
+  // the FFT form chosen for the plan, from the tables `fp`
+  const WavePlan &w = row_plan(p)->bs ? fp.wb : fp.w;
   const bool g2 = p->tune[AR_TUNE_ROW_LANES] == 2;
 #define AR_R(BS_, G_, MASK_)                                                                   \
-  wave_rows_t<TS, T, BS_, G_, MASK_>(p, w, in, out, mode, tau, f_true, partial, jobs, count,  \
-                                     kit, st)
+  wave_rows_t<TS, T, BS_, G_, MASK_>(p, fp, w, in, out, mode, tau, f_true, partial, jobs,     \
+                                     count, kit, st)
   if (w.bs) return g2 ? AR_R(true, 2, 0) : AR_R(true, 1, 0);
   if (is_plan1023(w)) return g2 ? AR_R(false, 2, kPlan1023) : AR_R(false, 1, kPlan1023);
   return g2 ? AR_R(false, 2, kMaskAll) : AR_R(false, 1, kMaskAll);
@@ -1072,12 +1075,20 @@ static int wave_rows_any(const ar_plan_s *p, const void *in, void *out, int mode
                          const void *f_true, double *partial, const XJob *jobs, int count,
                          int kit, hipStream_t st) {
   if (p->dtype == AR_F64)
-    return wave_rows_d<double, double>(p, in, out, mode, tau, f_true, partial, jobs, count, kit,
-                                       st);
-  if (p->dtype == AR_F32_ACC64)
-    return wave_rows_d<float, double>(p, in, out, mode, tau, f_true, partial, jobs, count, kit,
-                                      st);
-  return wave_rows_d<float, float>(p, in, out, mode, tau, f_true, partial, jobs, count, kit, st);
+    return wave_rows_d<double, double>(p, p->fft_row, in, out, mode, tau, f_true, partial, jobs,
+                                       count, kit, st);
+  if (p->dtype == AR_F32_ACC64) {
+    // the iteration's inverse row pass follows the filter, which does not
+    // amplify its rounding: FP32 arithmetic there, FP64 everywhere else
+    const WavePlan &w32 = row_plan(p)->bs ? p->fft_row32.wb : p->fft_row32.w;
+    if (mode == ROW_INV_UPDATE && w32.ok)
+      return wave_rows_d<float, float>(p, p->fft_row32, in, out, mode, tau, f_true, partial,
+                                       jobs, count, kit, st);
+    return wave_rows_d<float, double>(p, p->fft_row, in, out, mode, tau, f_true, partial, jobs,
+                                      count, kit, st);
+  }
+  return wave_rows_d<float, float>(p, p->fft_row, in, out, mode, tau, f_true, partial, jobs,
+                                   count, kit, st);
 }
 
 int wave_rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,

@@ -55,11 +55,16 @@ __device__ __forceinline__ void bfly(V2<T> *U, int N, int L, const V2<T> *__rest
   // ones read them where they are used (register pressure)
   constexpr bool PRE = R <= 11;
   const int nb = N / R;
-  // a stage with at most 64 butterflies runs on the sequence's first wave
-  // only (its other waves wait at the barrier instead of issuing the same
-  // instructions for a few lanes each)
-  if (G > 1 && nb <= 64)
-    lane = (threadIdx.x >> 6) % G == 0 ? (int)(threadIdx.x & 63) : 64 + (int)(threadIdx.x & 63);
+  // a stage with at most 64 butterflies runs on one wave of the sequence
+  // (its other waves wait at the barrier instead of issuing the same
+  // instructions for a few lanes each); the working wave alternates between
+  // pairs of sequences so that, with waves dealt round-robin to the four
+  // SIMDs, every SIMD gets the same share of the stage
+  if (G > 1 && nb <= 64) {
+    const int wv = threadIdx.x >> 6;
+    const int worker = ((wv / G) >> 1) % G;
+    lane = wv % G == worker ? (int)(threadIdx.x & 63) : 64 + (int)(threadIdx.x & 63);
+  }
   for (int j0 = lane; j0 < nb; j0 += SL * NB) {
     V2<T> v[NB][R];
     V2<T> t[NB][PRE ? R - 1 : 1];

@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <type_traits>
 #include <vector>
 
 #include "ar_codelets.h"
@@ -120,7 +121,25 @@ constexpr int kMaskAll = 0xfff;
 // fixed at compile time, so every stride, bound and table offset is a
 // constant.
 constexpr int kPlan1023 = -1;
+// Bluestein plans of length N = 2^k (256, 512, 1024 for k = 8, 9, 10): the
+// radix-4 stages (and a final radix 2) fixed at compile time, MASK = -k.
+constexpr int kPlanBSMin = -10, kPlanBSMax = -8;
+constexpr bool is_bs_static(int mask) { return mask >= kPlanBSMin && mask <= kPlanBSMax; }
 constexpr bool in_mask(int mask, int r) { return mask >= 0 && ((mask >> rbit(r)) & 1); }
+constexpr int plan_n(int mask) { return mask == kPlan1023 ? 1023 : (1 << -mask); }
+
+// The compile-time Bluestein stages from stride L on: radix 4 while N / L
+// is a multiple of 4, then radix 2; twiddles of the stage at stride L start
+// at L - 1 (the preceding radix-4 stages hold 3 (1 + 4 + ... + L / 4)).
+// DIT runs them by increasing L, DIF by decreasing L.
+template <typename T, bool DIF, int G, int N, int L>
+__device__ __forceinline__ void bs_stages(V2<T> *U, const V2<T> *__restrict__ tw, int lane) {
+  constexpr int R = (N / L) % 4 == 0 ? 4 : 2;
+  if constexpr (DIF && L * R < N) bs_stages<T, DIF, G, N, L * R>(U, tw, lane);
+  bfly<T, R, DIF, G>(U, N, L, tw + (L - 1), lane);
+  __syncthreads();
+  if constexpr (!DIF && L * R < N) bs_stages<T, DIF, G, N, L * R>(U, tw, lane);
+}
 
 // DIT runs stages 0..nst-1 (digit-reversed in, natural out); DIF runs them
 // backwards (natural in, digit-reversed out).  Bluestein plans use radices
@@ -136,6 +155,10 @@ __device__ __forceinline__ void fft_run(V2<T> *U, const WDesc &wd, const V2<T> *
     __syncthreads();
     bfly<T, 3, DIF, G>(U, 1023, 341, tw + 340, lane);
     __syncthreads();
+    return;
+  }
+  if constexpr (is_bs_static(MASK)) {
+    bs_stages<T, DIF, G, plan_n(MASK), 1>(U, tw, lane);
     return;
   }
   const int N = wd.N;
@@ -426,7 +449,8 @@ __global__ __launch_bounds__(256 * G) void rows_w_kernel(
     f_true = static_cast<const TS *>(J.aux);
     partial = J.part ? J.part + (size_t)kit * J.nblk : nullptr;
   }
-  const int M = MASK == kPlan1023 ? 1023 : wd.M, N = MASK == kPlan1023 ? 1023 : wd.N;
+  const int M = MASK == kPlan1023 ? 1023 : wd.M;
+  const int N = MASK == kPlan1023 || is_bs_static(MASK) ? plan_n(MASK) : wd.N;
   // G wavefronts per sequence; butterflies and elements are dealt to the
   // 64 G lanes of a sequence interleaved (lane-major across its waves)
   const int W = (blockDim.x >> 6) / G;
@@ -596,7 +620,8 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
   // block I/O for mixed-radix plans; Bluestein plans (zero padding, chirp
   // products) pack per wave from strided loads
   constexpr bool BIO = !BS;
-  const int M = MASK == kPlan1023 ? 1023 : wd.M, N = MASK == kPlan1023 ? 1023 : wd.N;
+  const int M = MASK == kPlan1023 ? 1023 : wd.M;
+  const int N = MASK == kPlan1023 || is_bs_static(MASK) ? plan_n(MASK) : wd.N;
   // G wavefronts per sequence; butterflies and elements are dealt to the
   // 64 G lanes of a sequence interleaved (lane-major across its waves)
   const int W = (blockDim.x >> 6) / G;
@@ -958,6 +983,22 @@ void wave_plan_free(WavePlan &w) {
   w.ok = false;
 }
 
+// The compile-time Bluestein plan matching w (FP32 tables only), or 0:
+// N = 2^k for k = 8, 9, 10 with the stage layout bs_stages assumes.
+static int bs_static_mask(const WavePlan &w) {
+  if (!w.bs) return 0;
+  int k = 0;
+  while ((1 << k) < w.N) ++k;
+  if ((1 << k) != w.N || -k < kPlanBSMin || -k > kPlanBSMax) return 0;
+  int L = 1;
+  for (int s = 0; s < w.nst; ++s) {
+    const int R = (w.N / L) % 4 == 0 ? 4 : 2;
+    if (w.R[s] != R || w.L[s] != L || w.tw_off[s] != L - 1) return 0;
+    L *= R;
+  }
+  return L == w.N ? -k : 0;
+}
+
 // The mixed-radix plan of M = 1023 with the stage layout the fixed-plan
 // kernels assume.
 static bool is_plan1023(const WavePlan &w) {
@@ -1070,7 +1111,17 @@ static int wave_rows_d(const ar_plan_s *p, const FftPlan &fp, const void *in, vo
 #define AR_R(BS_, G_, MASK_)                                                                   \
   wave_rows_t<TS, T, BS_, G_, MASK_>(p, fp, w, in, out, mode, tau, f_true, partial, jobs,     \
                                      count, kit, st)
-  if (w.bs) return g2 ? AR_R(true, 2, 0) : AR_R(true, 1, 0);
+  if (w.bs) {
+    if constexpr (std::is_same<T, float>::value) {
+      switch (bs_static_mask(w)) {
+        case -8: return g2 ? AR_R(true, 2, -8) : AR_R(true, 1, -8);
+        case -9: return g2 ? AR_R(true, 2, -9) : AR_R(true, 1, -9);
+        case -10: return g2 ? AR_R(true, 2, -10) : AR_R(true, 1, -10);
+        default: break;
+      }
+    }
+    return g2 ? AR_R(true, 2, 0) : AR_R(true, 1, 0);
+  }
   if (is_plan1023(w)) return g2 ? AR_R(false, 2, kPlan1023) : AR_R(false, 1, kPlan1023);
   return g2 ? AR_R(false, 2, kMaskAll) : AR_R(false, 1, kMaskAll);
 #undef AR_R
@@ -1152,7 +1203,17 @@ static int wave_cols_d(const ar_plan_s *p, const void *in, void *out, int mode, 
   const WavePlan &w = *col_plan(p);
   const bool g2 = p->tune[AR_TUNE_COL_LANES] == 2;
 #define AR_C(BS_, G_, MASK_) wave_cols_t<TS, T, BS_, G_, MASK_>(p, w, in, out, mode, jobs, count, st)
-  if (w.bs) return g2 ? AR_C(true, 2, 0) : AR_C(true, 1, 0);
+  if (w.bs) {
+    if constexpr (std::is_same<T, float>::value) {
+      switch (bs_static_mask(w)) {
+        case -8: return g2 ? AR_C(true, 2, -8) : AR_C(true, 1, -8);
+        case -9: return g2 ? AR_C(true, 2, -9) : AR_C(true, 1, -9);
+        case -10: return g2 ? AR_C(true, 2, -10) : AR_C(true, 1, -10);
+        default: break;
+      }
+    }
+    return g2 ? AR_C(true, 2, 0) : AR_C(true, 1, 0);
+  }
   if (is_plan1023(w)) return g2 ? AR_C(false, 2, kPlan1023) : AR_C(false, 1, kPlan1023);
   return g2 ? AR_C(false, 2, kMaskAll) : AR_C(false, 1, kMaskAll);
 #undef AR_C

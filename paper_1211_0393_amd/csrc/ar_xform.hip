@@ -20,7 +20,10 @@
 //   * the DST values come from U_k and U_{M-k} and are stored directly.
 // Twiddle, post-processing and digit-reversal tables are staged in LDS once
 // per workgroup; the global loads of a kernel are issued before its first
-// barrier.  The column pass of the preconditioner keeps the filtered
+// barrier.  Two plans are compiled with their stages fixed (every stride,
+// bound and table offset a constant): the mixed-radix plan of length 1023
+// and the Bluestein plans of power-of-two length 256, 512 and 1024 (FP32
+// tables); other lengths run the stage loop of the plan's descriptor.  The column pass of the preconditioner keeps the filtered
 // coefficients in a per-wave LDS row and runs the inverse transform in the
 // same workgroup.
 #include <algorithm>

@@ -430,7 +430,8 @@ def main():
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(t_step * 1e3, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 images, f64 arithmetic" if a.dtype == "f32x" else "f32",
+        "dtype": ("f32 images, f64 arithmetic (the inverse row pass after the filter in f32)"
+                  if a.dtype == "f32x" else "f32"),
         "data": "synthetic",
         "config": {"workload": "1024x1024 phantom (40 blobs + 20 rectangles), 15x15 motion PSF "
                                "(length 11 at 30 deg, Gaussian sigma 1), 0.5% noise, AR BCs, "

@@ -1,0 +1,44 @@
+"""Host-side logic of the benchmark driver (CPU only): the hardware-counter
+traffic table is used only for the kernel sources it was taken on, and a
+request for more than one GPU is refused with a message."""
+
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_traffic_table_matches_current_sources():
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+        t = json.load(fh)
+    got = bench.measured_traffic(t["dtype"])
+    if t["source_sha256"] == bench.source_digest():
+        assert set(got) == set(t["phases"])
+        for k, v in t["phases"].items():
+            assert got[k] == v["hbm_bytes_per_launch"] > 0
+    else:
+        assert got == {}
+
+
+def test_traffic_table_ignored_for_other_sources_or_dtype(monkeypatch):
+    monkeypatch.setattr(bench, "source_digest", lambda: "0" * 64)
+    assert bench.measured_traffic("f32x") == {}
+    monkeypatch.undo()
+    assert bench.measured_traffic("no-such-dtype") == {}
+
+
+def test_source_digest_is_stable():
+    assert bench.source_digest() == bench.source_digest()
+    assert len(bench.source_digest()) == 64
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

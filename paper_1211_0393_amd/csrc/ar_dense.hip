@@ -60,6 +60,11 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
+  // tile loads: A as 128 rows x 32 k (thread: row tid / 8 + 32 u, 4
+  // consecutive k), B as 32 k x 128 columns (thread: column tid % 128, 16
+  // consecutive k), so that the split halves go to LDS as packed 8- and
+  // 16-byte stores ([row][k] for A, [column][k] for B)
+  const int bn = tid & 127, bkq = (tid >> 7) * 16;
   for (int k0 = 0; k0 < K; k0 += BK) {
     // global -> registers (clamped addresses, zero outside), all loads first
     float av[16], bv[16];
@@ -76,17 +81,14 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(
         av[4 * u + e] = ok ? v : 0.f;
       }
     }
+    {
+      const int gj = j0 + bn;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int idx = tid + 256 * u;
-      const int kr = idx >> 5, c = (idx & 31) * 4;
-      const int gk = k0 + kr;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gj = j0 + c + e;
+      for (int e = 0; e < 16; ++e) {
+        const int gk = k0 + bkq + e;
         const bool ok = gk < K && gj < N;
         const float v = B[(long)(ok ? gk : 0) * ldb + (ok ? gj : 0)];
-        bv[4 * u + e] = ok ? v : 0.f;
+        bv[e] = ok ? v : 0.f;
       }
     }
     __syncthreads();  // the previous step's fragments have been read
@@ -94,25 +96,34 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(
     for (int u = 0; u < 4; ++u) {
       const int idx = tid + 256 * u;
       const int row = idx >> 3, c = (idx & 7) * 4;
+      unsigned hw[2], lw[2];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float v = av[4 * u + e];
-        const unsigned short h = bf16_bits(v);
-        Ah[row * PK + c + e] = h;
-        Al[row * PK + c + e] = bf16_bits(v - bf16_val(h));
+      for (int q = 0; q < 2; ++q) {
+        const float v0 = av[4 * u + 2 * q], v1 = av[4 * u + 2 * q + 1];
+        const unsigned short h0 = bf16_bits(v0), h1 = bf16_bits(v1);
+        hw[q] = (unsigned)h0 | ((unsigned)h1 << 16);
+        lw[q] = (unsigned)bf16_bits(v0 - bf16_val(h0)) |
+                ((unsigned)bf16_bits(v1 - bf16_val(h1)) << 16);
       }
+      *reinterpret_cast<uint2 *>(&Ah[row * PK + c]) = make_uint2(hw[0], hw[1]);
+      *reinterpret_cast<uint2 *>(&Al[row * PK + c]) = make_uint2(lw[0], lw[1]);
     }
+    {
+      unsigned hw[8], lw[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int idx = tid + 256 * u;
-      const int kr = idx >> 5, c = (idx & 31) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float v = bv[4 * u + e];
-        const unsigned short h = bf16_bits(v);
-        Bh[(c + e) * PK + kr] = h;  // transposed: [n][k]
-        Bl[(c + e) * PK + kr] = bf16_bits(v - bf16_val(h));
+      for (int q = 0; q < 8; ++q) {
+        const float v0 = bv[2 * q], v1 = bv[2 * q + 1];
+        const unsigned short h0 = bf16_bits(v0), h1 = bf16_bits(v1);
+        hw[q] = (unsigned)h0 | ((unsigned)h1 << 16);
+        lw[q] = (unsigned)bf16_bits(v0 - bf16_val(h0)) |
+                ((unsigned)bf16_bits(v1 - bf16_val(h1)) << 16);
       }
+      uint4 *bh4 = reinterpret_cast<uint4 *>(&Bh[bn * PK + bkq]);  // transposed: [n][k]
+      uint4 *bl4 = reinterpret_cast<uint4 *>(&Bl[bn * PK + bkq]);
+      bh4[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+      bh4[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
+      bl4[0] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+      bl4[1] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
     }
     __syncthreads();
     // lane l: A[i = l % 16][k = 8 (l / 16) + e], B[k = 8 (l / 16) + e][j = l % 16]

@@ -210,6 +210,119 @@ def test_adam_first_step_is_sign_step():
     assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
 
 
+def _set(theta, layer, kind, idx, value):
+    """Write one weight (kind "W", idx (out, in)) or bias (kind "b", idx out)
+    of a layer into the flat parameter vector at the offsets the stated
+    layout gives: W1 (128 x 65), b1, W2 (128 x 128), b2, W3 (64 x 128), b3,
+    each W (out, in) row-major."""
+    off = 0
+    for li, (no, ni) in enumerate(L.SIZES):
+        if li == layer:
+            if kind == "W":
+                o, i = idx
+                theta[off + o * ni + i] = value
+            else:
+                theta[off + no * ni + idx] = value
+            return
+        off += no * ni + no
+    raise IndexError(layer)
+
+
+def _forward_loops(theta, x):
+    """The network written out with scalar loops over the (out, in) layout
+    (ReLU, ReLU, logistic sigmoid), independent of the oracle's matrix code."""
+    out = list(x)
+    off = 0
+    for li, (no, ni) in enumerate(L.SIZES):
+        nxt = []
+        for o in range(no):
+            acc = theta[off + no * ni + o]
+            for i in range(ni):
+                acc += theta[off + o * ni + i] * out[i]
+            if li < 2:
+                nxt.append(acc if acc > 0.0 else 0.0)
+            else:
+                nxt.append(1.0 / (1.0 + np.exp(-acc)))
+        off += no * ni + no
+        out = nxt
+    return np.array(out)
+
+
+def test_mlp_forward_hand_network_literal_values():
+    """A network with a handful of nonzero parameters, evaluated by hand:
+    z1_0 = 2*1 - 0.25 + 0.5 = 2.25, z1_1 = 2 - 1 = 1, z1_2 = -1 (ReLU 0);
+    z2_0 = 1.5*2.25 + 0.5*1 = 3.875, z2_1 = -2.25 + 0.25 = -2 (ReLU 0);
+    z3_0 = 3.875 - 0.5 = 3.375, z3_3 = -0.5*3.875 = -1.9375, z3_5 = 1, all
+    other z3 = 0.  A transposed weight matrix, a dropped bias or a missing
+    ReLU changes at least one of these outputs."""
+    th = np.zeros(L.NPARAM)
+    _set(th, 0, "W", (0, 0), 2.0)
+    _set(th, 0, "W", (0, 1), -1.0)
+    _set(th, 0, "b", 0, 0.5)
+    _set(th, 0, "W", (1, 2), 1.0)
+    _set(th, 0, "b", 1, -1.0)
+    _set(th, 0, "W", (2, 0), -1.0)
+    _set(th, 1, "W", (0, 0), 1.5)
+    _set(th, 1, "W", (0, 1), 0.5)
+    _set(th, 1, "W", (1, 0), -1.0)
+    _set(th, 1, "b", 1, 0.25)
+    _set(th, 2, "W", (0, 0), 1.0)
+    _set(th, 2, "W", (0, 1), -2.0)
+    _set(th, 2, "b", 0, -0.5)
+    _set(th, 2, "W", (3, 0), -0.5)
+    _set(th, 2, "b", 5, 1.0)
+    x = np.zeros(65)
+    x[0], x[1], x[2] = 1.0, 0.25, 2.0
+    Y, (_, Z1, H1, Z2, H2, Z3) = L.mlp_forward(th, x[None, :])
+    assert Z1[0, 0] == 2.25 and Z1[0, 1] == 1.0 and Z1[0, 2] == -1.0 and H1[0, 2] == 0.0
+    assert Z2[0, 0] == 3.875 and Z2[0, 1] == -2.0 and H2[0, 1] == 0.0
+    expect = np.full(64, 0.5)
+    expect[0] = 1.0 / (1.0 + np.exp(-3.375))       # 0.96691402...
+    expect[3] = 1.0 / (1.0 + np.exp(1.9375))       # 0.125923...
+    expect[5] = 1.0 / (1.0 + np.exp(-1.0))         # 0.731058...
+    assert abs(expect[0] - 0.9669140216) < 1e-9
+    assert abs(expect[3] - 0.1259228) < 1e-6
+    assert abs(expect[5] - 0.7310585786) < 1e-9
+    assert np.allclose(Y[0], expect, rtol=0, atol=1e-15)
+
+
+def test_mlp_forward_matches_scalar_loops():
+    """Random sparse network: the oracle's forward pass equals a scalar-loop
+    evaluation over the stated (out, in) layout."""
+    rng = np.random.default_rng(11)
+    th = _theta(5) * (rng.uniform(size=L.NPARAM) < 0.2)
+    X = rng.standard_normal((3, 65))
+    Y, _ = L.mlp_forward(th, X)
+    for b in range(3):
+        ref = _forward_loops(th, X[b])
+        assert np.max(np.abs(Y[b] - ref)) < 1e-12
+
+
+def test_adam_three_steps_hand_computed():
+    """Three Adam steps on one parameter with gradients 1, -2, 0.5 (lr 0.1,
+    beta1 0.9, beta2 0.999, eps 1e-8), moments worked out by hand:
+    m = 0.1, -0.11, -0.049 and v = 0.001, 0.004999, 0.005244001; the
+    bias-corrected step divides m by 1 - 0.9^t and v by 1 - 0.999^t.  A
+    moment that is not carried across steps, or a bias correction with the
+    wrong power, fails."""
+    grads = [1.0, -2.0, 0.5]
+    m_hand = [0.1, -0.11, -0.049]
+    v_hand = [0.001, 0.004999, 0.005244001]
+    th = np.array([0.7])
+    m = np.zeros(1)
+    v = np.zeros(1)
+    th_hand = 0.7
+    for t, (g, mh, vh) in enumerate(zip(grads, m_hand, v_hand), start=1):
+        th, m, v = L.adam_step(th, m, v, np.array([g]), t, 0.1)
+        assert abs(m[0] - mh) < 1e-15 and abs(v[0] - vh) < 1e-15, (t, m, v)
+        th_hand -= 0.1 * (mh / (1.0 - 0.9 ** t)) / (np.sqrt(vh / (1.0 - 0.999 ** t)) + 1e-8)
+        assert abs(th[0] - th_hand) < 1e-14, (t, th, th_hand)
+    # step 1 moves by lr (sign step); step 2's bias-corrected m is -0.11/0.19
+    assert abs(th_hand - (0.7 - 0.1 / (1 + 1e-8)
+                          + 0.1 * (0.11 / 0.19) / (np.sqrt(0.004999 / 0.001999) + 1e-8)
+                          + 0.1 * (0.049 / 0.271) / (np.sqrt(0.005244001 / 0.002997001) + 1e-8))) < 1e-14
+
+
 def test_sweep_label_prefers_best_run():
     """The sweep returns the candidate whose own run has the smallest RRE,
     checked against running each candidate separately, and that candidate's

@@ -164,3 +164,79 @@ def tau_matrix(hv, m):
             else:
                 A[r, c] -= v[2 * m - r - c]
     return A
+
+
+def bc_terms(a, b, n1, n2, bc):
+    """Source pixel of 0-based extended position (a, b), written case by
+    case: Reflective (Sec. 2.1) f_{1-i} = f_i, f_{n+i} = f_{n+1-i} per axis
+    (corners: both reflections); Periodic f_{1-i} = f_{n+1-i},
+    f_{n+i} = f_i per axis.  Returns [(1.0, i1, i2)]."""
+    def one(i, n):
+        if 0 <= i <= n - 1:
+            return i
+        if bc == "reflective":
+            return -i - 1 if i < 0 else 2 * n - 1 - i      # paper 1-t -> t ; n+t -> n+1-t
+        return i + n if i < 0 else i - n                  # periodic
+    return [(1.0, one(a, n1), one(b, n2))]
+
+
+def dense_blur_bc(H, n1, n2, bc):
+    """Dense blur matrix under Reflective or Periodic BCs, entry by entry
+    from g_i = sum_s h_s f_{i-s} and ``bc_terms``."""
+    q1, q2 = (H.shape[0] - 1) // 2, (H.shape[1] - 1) // 2
+    A = np.zeros((n1 * n2, n1 * n2))
+    for i1 in range(n1):
+        for i2 in range(n2):
+            row = i1 * n2 + i2
+            for s1 in range(-q1, q1 + 1):
+                for s2 in range(-q2, q2 + 1):
+                    for w, j1, j2 in bc_terms(i1 - s1, i2 - s2, n1, n2, bc):
+                        A[row, j1 * n2 + j2] += H[q1 + s1, q2 + s2] * w
+    return A
+
+
+def reflective_1d_printed(hv, n):
+    """1-D Reflective blur of a symmetric PSF in the printed form of
+    Sec. 2.1: Toeplitz(v) + Hankel(sigma(v), J sigma(v)) with
+    v = [h_0..h_q, 0..], sigma(v) = [h_1..h_q, 0..] the first column of the
+    Hankel part and J sigma(v) its last row."""
+    q = (len(hv) - 1) // 2
+    v = np.zeros(n + 1)
+    v[:q + 1] = hv[q:]
+    sv = np.zeros(n)
+    sv[:q] = hv[q + 1:]
+    A = np.zeros((n, n))
+    for r in range(n):
+        for c in range(n):
+            A[r, c] = v[abs(r - c)]
+            # Hankel: entry depends on r + c; first column sv, last row J sv
+            if r + c <= n - 1:
+                A[r, c] += sv[r + c]
+            else:
+                A[r, c] += sv[::-1][r + c - (n - 1)]
+    return A
+
+
+def R_matrix(m):
+    """The orthogonal DCT-III matrix of eq. (Rn) under this repository's
+    reading: column t (0-based) is sqrt((2 - delta_{t,0}) / m)
+    cos(t (s + 1/2) pi / m), s = 0..m-1."""
+    s = np.arange(m).reshape(-1, 1)
+    t = np.arange(m).reshape(1, -1)
+    R = np.sqrt(2.0 / m) * np.cos(t * (s + 0.5) * np.pi / m)
+    R[:, 0] = np.sqrt(1.0 / m)
+    return R
+
+
+def R_matrix_printed(m):
+    """eq. (Rn) exactly as printed: [sqrt((2 - delta_{t,1}) / m)
+    cos((s - 1)(t - 1/2) pi / m)]_{s,t=1..m} (not orthogonal)."""
+    s = np.arange(1, m + 1).reshape(-1, 1)
+    t = np.arange(1, m + 1).reshape(1, -1)
+    return np.sqrt((2.0 - (t == 1)) / m) * np.cos((s - 1) * (t - 0.5) * np.pi / m)
+
+
+def dft_matrix(n):
+    """Unitary DFT matrix F[k, t] = exp(-2 pi i k t / n) / sqrt(n)."""
+    k = np.arange(n).reshape(-1, 1)
+    return np.exp(-2j * np.pi * k * k.T / n) / np.sqrt(n)

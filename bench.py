@@ -6,14 +6,19 @@ residual r = g - A x (AR blur, FP64 norm partials), y = A' r (reblur),
 c = T~ y along rows, the fused column pass T~ / filter d / T, and the row
 pass T fused with x += tau w, i.e. one preconditioned Landweber iteration
 including its per-iteration FP64 residual norm.  The timed region runs
-exactly K steps from x_0 = 0 with all inputs resident on the GPU; the
-per-iteration norms are copied to the host once at the end (inside the
-timed region).
+exactly K steps, as consecutive runs of at most 100 iterations from
+x_0 = 0, with all inputs resident on the GPU; the per-iteration norms are
+copied to the host once per run (inside the timed region).  The timed runs
+use a Tikhonov parameter at which the iteration is stable (0.2); the
+workload's named 5e-3 makes it diverge and is reported under "quality".
 
-Prints one JSON line (see the repository's design notes for the roofline
-and the CPU baseline definitions).
+Prints one JSON line: throughput, the roofline of the dominant kernel and
+of the whole step (algorithmic bytes), per-kernel rooflines, restoration
+quality and GPU time to the best relative error (plain, preconditioned,
+learned), the batched workload, the learned-vs-plain sweep comparison, the
+2048^2 precision variant, and the FP64 oracle timed on the host cores.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32x|f32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f32x]
 """
 
 from __future__ import annotations
@@ -32,8 +37,20 @@ ITERS = 100   # iterations of one run of the workload (its configuration)
 
 # MI355X published peaks used for the roofline (dense, per GPU)
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_TFLOPS = 78.6   # FP64 vector, and FP32 vector without packed FP32
-                          # (256 CUs x 64 FMA lanes/clk x 2 flop x 2.4 GHz)
+FP64_VECTOR_TFLOPS = 78.6   # 256 CUs x 64 FP64 FMA lanes/clk x 2 flop x 2.4 GHz
+FP32_VECTOR_TFLOPS = 157.3  # 256 CUs x 128 FP32 FMA lanes/clk x 2 flop x 2.4 GHz
+
+# Algorithmic HBM bytes per pixel and iteration (FP32 images), by phase:
+# r = g - A x reads x, g and writes r; y = A' r reads r, writes y; the
+# transforms with the filter and the update read y, d, x and write x,
+# which the three transform passes own as y (row pass of T~), d (column
+# pass) and x read + written (row pass of T + update).  Intermediates
+# between the passes and halo re-reads are implementation traffic.
+ALG_BYTES = {"residual": 12, "reblur": 8, "row_fwd": 4, "col": 4, "row_inv": 8}
+STEP_BYTES = sum(ALG_BYTES.values())   # 36 B per pixel-iteration
+STABLE_ALPHA = 0.2          # 1024^2 motion PSF: I - D A'A has spectral radius ~1
+BATCH_STABLE_ALPHA = 0.5    # every batched Gaussian PSF: spectral radius <= 1
+PLAIN_CAP = 3000            # iteration cap of the unpreconditioned run to its best RRE
 
 
 def parse():
@@ -42,7 +59,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000,
                     help="timed iterations, run as consecutive runs of at most 100 from x = 0")
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--dtype", default="f32x", choices=["f32x", "f32"])
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f32x"],
+                    help="f32: FP32 images and arithmetic (meets the 1e-5 one-step bound for "
+                         "alpha >= 0.05); f32x: FP32 images, FP64 arithmetic (any alpha)")
+    ap.add_argument("--alpha", type=float, default=STABLE_ALPHA,
+                    help="Tikhonov parameter of the timed runs (the named 5e-3 diverges)")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=3)
@@ -69,7 +90,6 @@ def make_inputs(torch, P, dt):
     plan.ar_blur_apply(f, b)                       # noise-free data A f on the GPU
     g = b + (p["nu"] * torch.linalg.vector_norm(b.double()) /
              torch.linalg.vector_norm(e.double())).float() * e
-    plan.ar_precond_set(P.AR_FILTER_TIKHONOV, p["alpha"])
     torch.cuda.synchronize()
     return plan, f, g, F, H, E, p
 
@@ -104,6 +124,15 @@ def measured_traffic(dtype):
     return {k: v["hbm_bytes_per_launch"] for k, v in t.get("phases", {}).items()}
 
 
+def diverged(res):
+    """A run diverged when a residual norm is not finite or some later
+    residual exceeds the initial one ||g - A x_0||."""
+    if res is None or len(res) == 0:
+        return False
+    res = np.asarray(res)
+    return bool(not np.all(np.isfinite(res)) or (len(res) > 1 and np.max(res[1:]) > res[0]))
+
+
 def finite_min(v):
     if v is None:
         return None
@@ -112,31 +141,92 @@ def finite_min(v):
     return float(v.min()) if v.size else None
 
 
-def cpu_baseline(F, H, E, p, iters):
-    """The FP64 oracle (as written, untuned) on this host: a bounded sample
-    of the same workload (`iters` D-Landweber iterations after one warm-up
-    iteration), in Mpixel-iters/s."""
+def _oracle_rate(G, H, d, iters, workers=1):
+    """Mpixel-iters/s of `iters` FP64 oracle D-Landweber steps (after one
+    warm-up step) with scipy.fft using `workers` threads."""
+    import scipy.fft
     import oracle as O
-    G = O.observe(F, H, E, p["nu"])
-    d = O.tikhonov(O.eigenvalues(H, *G.shape), p["alpha"])
     X = np.zeros_like(G)
-    X, _ = O.landweber_step(X, G, H, d=d)          # warm-up
+    with scipy.fft.set_workers(workers):
+        X, _ = O.landweber_step(X, G, H, d=d)          # warm-up
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            X, _ = O.landweber_step(X, G, H, d=d)
+        dt = time.perf_counter() - t0
+    return G.size * iters / dt / 1e6, dt
+
+
+def _oracle_batch_worker(args):
+    i, iters = args
+    import oracle as O
+    import synth
+    F, H, E, prm = synth.batch_problem(i)
+    G = O.observe(F, H, E, prm["nu"])
+    d = O.tikhonov(O.eigenvalues(H, *G.shape), BATCH_STABLE_ALPHA)
+    X = np.zeros_like(G)
     t0 = time.perf_counter()
     for _ in range(iters):
         X, _ = O.landweber_step(X, G, H, d=d)
-    dt = time.perf_counter() - t0
-    px = G.size * iters
-    return {"value": px / dt / 1e6, "unit": "Mpixel-iters/s", "cores": 1, "kind": "oracle",
+    return G.size * iters, time.perf_counter() - t0
+
+
+def cpu_baseline(F, H, E, p, iters):
+    """The FP64 oracle (as written, untuned) on this host, on bounded samples
+    of the workloads: the 1024^2 workload single-threaded (the reported
+    value) and with scipy.fft on every core (numpy's elementwise work stays
+    on one thread); the 64^2 FP64 workload; one 512^2 batched problem on one
+    core, and the batched workload's problems in a process pool over every
+    core (aggregate throughput).  In Mpixel-iters/s."""
+    import multiprocessing as mp
+    import oracle as O
+    import synth
+    cores = os.cpu_count() or 1
+    G = O.observe(F, H, E, p["nu"])
+    d = O.tikhonov(O.eigenvalues(H, *G.shape), p["alpha"])
+    v1, t1 = _oracle_rate(G, H, d, iters, workers=1)
+    vall, tall = _oracle_rate(G, H, d, iters, workers=cores)
+    F1, H1, E1, p1 = synth.workload("ar64_f64_gauss9")
+    G1 = O.observe(F1, H1, E1, p1["nu"])
+    d1 = O.tikhonov(O.eigenvalues(H1, *G1.shape), p1["alpha"])
+    vc1, tc1 = _oracle_rate(G1, H1, d1, p1["iters"], workers=1)
+    i512 = next(i for i in range(256) if synth.batch_problem(i)[3]["n"] == 512)
+    px, t512 = _oracle_batch_worker((i512, iters))
+    v512 = px / t512 / 1e6
+    nproc = min(cores, 16)
+    with mp.get_context("spawn").Pool(nproc) as pool:
+        res = pool.map(_oracle_batch_worker, [(i, 3) for i in range(nproc)])
+    tpool = max(r[1] for r in res)          # the workers run concurrently
+    vpool = sum(r[0] for r in res) / tpool / 1e6
+    modes = [
+        {"workload": "1024x1024 15x15 motion PSF, D-Landweber", "threads": 1,
+         "value": round(v1, 4), "seconds": round(t1, 2), "iterations": iters},
+        {"workload": "1024x1024 15x15 motion PSF, D-Landweber", "threads": cores,
+         "value": round(vall, 4), "seconds": round(tall, 2), "iterations": iters,
+         "note": "scipy.fft workers = cores; elementwise numpy work single-threaded"},
+        {"workload": "64x64 9x9 shifted Gaussian, FP64, D-Landweber", "threads": 1,
+         "value": round(vc1, 4), "seconds": round(tc1, 2), "iterations": p1["iters"]},
+        {"workload": "one 512x512 batched problem (Gaussian PSF)", "threads": 1,
+         "value": round(v512, 4), "seconds": round(t512, 2), "iterations": iters},
+        {"workload": f"{nproc} batched problems (n 128..512), one per process", "threads": nproc,
+         "value": round(vpool, 4), "seconds": round(tpool, 2), "iterations": 3,
+         "note": "aggregate pixel-iterations over the slowest worker's iteration time"},
+    ]
+    return {"value": v1, "unit": "Mpixel-iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} FP64 D-Landweber iterations of the 1024x1024 15x15-PSF workload "
-                      f"after 1 warm-up ({dt:.1f} s); numpy/scipy single-threaded "
-                      f"(host os.cpu_count()={os.cpu_count()})"}
+                      f"after 1 warm-up ({t1:.1f} s); numpy/scipy on one thread "
+                      f"(host os.cpu_count()={cores}); other modes and sizes in 'modes'",
+            "modes": modes}
 
 
-def bench_batch(torch, P, iters, count=256):
+def bench_batch(torch, P, iters, count=256, alpha=BATCH_STABLE_ALPHA):
     """The batched workload: `count` problems (n in {128,...,512}, own
-    Gaussian PSF 7..21 and noise level, Tikhonov alpha 5e-3, FP32), `iters`
-    preconditioned iterations in one graph launch, after a warm-up call
-    that captures the graph.  Inputs are resident on the GPU."""
+    Gaussian PSF 7..21 and noise level, FP32), `iters` preconditioned
+    iterations in one graph launch, after a warm-up call that captures the
+    graph.  Inputs are resident on the GPU.  The Tikhonov parameter is the
+    smallest of 0.05, 0.1, 0.2, 0.3, 0.5 at which I - D A'A has spectral
+    radius <= 1 for every PSF of the family (oracle power iteration); the
+    value is reported only when every problem's run is finite and its
+    residual never exceeds the initial one."""
     import synth
     plans, gs, xs = [], [], []
     px = 0
@@ -144,7 +234,7 @@ def bench_batch(torch, P, iters, count=256):
         F, H, E, prm = synth.batch_problem(i)
         n = prm["n"]
         pl = P.Plan(n, n, H, dtype="f32")
-        pl.ar_precond_set(P.AR_FILTER_TIKHONOV, prm["alpha"])
+        pl.ar_precond_set(P.AR_FILTER_TIKHONOV, alpha)
         f = torch.from_numpy(F).to("cuda:0", torch.float32)
         e = torch.from_numpy(E).to("cuda:0", torch.float32)
         b = torch.empty_like(f)
@@ -157,7 +247,7 @@ def bench_batch(torch, P, iters, count=256):
         px += n * n
     batch = P.Batch(plans)
     tuned = batch.ar_batch_autotune()
-    batch.ar_batch_iterate(gs, xs, iters)            # warm-up: captures the graph
+    batch.ar_batch_iterate(gs, xs, iters, want_resnorm=True)   # warm-up: captures the graph
     for x in xs:
         x.zero_()
     torch.cuda.synchronize()
@@ -171,17 +261,78 @@ def bench_batch(torch, P, iters, count=256):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     t = max(wall, ev0.elapsed_time(ev1) / 1e3)
+    bad = sum(diverged(res[i]) for i in range(count))
+    valid = rc == 0 and bad == 0
     out = {"workload": f"{count} problems, n in {{128,192,256,384,512}} (seed 404 + i), "
-                       "Gaussian PSFs 7..21, noise 0.1%..2%, Tikhonov alpha 5e-3, FP32, "
+                       f"Gaussian PSFs 7..21, noise 0.1%..2%, Tikhonov alpha {alpha}, FP32, "
                        f"{iters} D-Landweber iterations in one graph launch",
-           "value": round(px * iters / t / 1e6, 1), "unit": "Mpixel-iters/s",
+           "value": round(px * iters / t / 1e6, 1) if valid else None, "unit": "Mpixel-iters/s",
+           "measured_rate": round(px * iters / t / 1e6, 1),
+           "valid": valid, "alpha": alpha,
            "pixels_per_iteration": px, "seconds": round(t, 5),
            "us_per_batch_iteration": round(t / iters * 1e6, 2),
            "status": rc, "autotuned_precond_us": round(tuned, 2),
-           "diverged_problems": int(np.sum(~np.all(np.isfinite(res), axis=1)))}
+           "diverged_problems": int(bad)}
     batch.close()
     for pl in plans:
         pl.close()
+    return out
+
+
+def bench_stable(torch, P, plan, f, g, net_path, iters=ITERS):
+    """GPU time to the best relative error on the 1024^2 workload at a
+    stable Tikhonov parameter (the named 5e-3 diverges): plain Landweber
+    (D = I) run to PLAIN_CAP iterations, D-Landweber with Tikhonov
+    STABLE_ALPHA, and the learned filter (features + network + gains
+    filter, then D-Landweber), `iters` iterations each.  The time to best
+    is the run's measured time per iteration times its best iteration, plus
+    the filter set-up; reached_plain_best_at: the first iteration whose RRE
+    is within 2% of the plain run's best (None if never)."""
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def run(k, precondition, setup=None):
+        x = torch.zeros_like(g)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        if setup is not None:
+            setup()
+        ev[1].record(stream)
+        rc, res, rre, best = plan.ar_deblur_iterate(g, x, k, precondition=precondition,
+                                                    f_true=f, want_resnorm=True, want_rre=True)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        t_set = ev[0].elapsed_time(ev[1]) / 1e3
+        t_it = ev[1].elapsed_time(ev[2]) / 1e3 / k
+        return rc, res, rre, best, t_set, t_it
+
+    def summary(rc, res, rre, best, t_set, t_it, ref=None):
+        o = {"status": rc, "best_it": best, "best_rre": finite_min(rre),
+             "us_per_iteration": round(t_it * 1e6, 2),
+             "gpu_s_to_best": round(t_set + t_it * best, 6), "diverged": diverged(res)}
+        if ref is not None:
+            hit = np.nonzero(np.isfinite(rre) & (rre <= 1.02 * ref))[0]
+            o["reached_plain_best_at"] = int(hit[0]) + 1 if hit.size else None
+            o["gpu_s_to_plain_best"] = (round(t_set + t_it * (hit[0] + 1), 6)
+                                        if hit.size else None)
+        return o
+
+    plain = summary(*run(PLAIN_CAP, False))
+    ref = plain["best_rre"]
+    pre = summary(*run(iters, True, lambda: plan.ar_precond_set(P.AR_FILTER_TIKHONOV,
+                                                                STABLE_ALPHA)), ref=ref)
+    out = {"workload": "1024x1024 motion-PSF workload (as the timed run), stable Tikhonov alpha",
+           "alpha": STABLE_ALPHA, "plain_cap": PLAIN_CAP, "plain": plain,
+           "preconditioned": pre}
+    if net_path is not None:
+        from paper_1211_0393_amd import learned as LR
+        net = P.FNet(path=net_path)
+        out["learned"] = summary(*run(iters, True, lambda: LR.apply_learned(net, plan, g)),
+                                 ref=ref)
+        net.close()
+    if pre["best_it"]:
+        out["iteration_ratio_plain_vs_preconditioned"] = round(plain["best_it"] /
+                                                               pre["best_it"], 2)
     return out
 
 
@@ -335,6 +486,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         return 1
     plan, f, g, F, H, E, p = make_inputs(torch, P, a.dtype)
+    plan.ar_precond_set(P.AR_FILTER_TIKHONOV, a.alpha)
     n = p["n"]
     stream = torch.cuda.current_stream()
     tuned_us = plan.ar_plan_autotune() if not a.no_tune else None
@@ -350,8 +502,8 @@ def main():
         # are that many consecutive runs (the last one possibly shorter)
         return [min(ITERS, total - k) for k in range(0, total, ITERS)]
 
-    # warm-up (untimed)
-    for k in runs(a.warmup):
+    # warm-up (untimed), in the same run lengths as the timed loop
+    for k in runs(max(a.warmup, min(a.steps, ITERS))):
         x.zero_()
         plan.ar_deblur_iterate(g, x, k, want_resnorm=True)
     torch.cuda.synchronize()
@@ -371,47 +523,65 @@ def main():
     t_step = max(wall, gpu_s) / a.steps
     value = n * n / t_step / 1e6
 
-    # quality of the timed run and of the unpreconditioned reference run
+    # quality of the timed run, of the named alpha's run and of the
+    # unpreconditioned reference run, each ITERS iterations
     x.zero_()
-    rc_q, _, rre, best = plan.ar_deblur_iterate(g, x, ITERS, f_true=f, want_rre=True)
+    rc_t, res_t, rre_t, best_t = plan.ar_deblur_iterate(g, x, ITERS, f_true=f,
+                                                        want_resnorm=True, want_rre=True)
+    plan.ar_precond_set(P.AR_FILTER_TIKHONOV, p["alpha"])
+    x.zero_()
+    rc_q, res_q, rre, best = plan.ar_deblur_iterate(g, x, ITERS, f_true=f, want_resnorm=True,
+                                                    want_rre=True)
+    plan.ar_precond_set(P.AR_FILTER_TIKHONOV, a.alpha)
     xr = torch.zeros_like(g)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rc_p, _, rre_p, best_p = plan.ar_deblur_iterate(g, xr, ITERS, precondition=False,
-                                                    f_true=f, want_rre=True)
-    plain_s = time.perf_counter() - t1
+    rc_p, res_p, rre_p, best_p = plan.ar_deblur_iterate(g, xr, ITERS, precondition=False,
+                                                        f_true=f, want_resnorm=True,
+                                                        want_rre=True)
 
-    # per-kernel durations of one step (HIP events on this stream), and the
-    # roofline of the dominant kernel with its algorithmic work per launch
+    # per-kernel durations of one step (HIP events on this stream, around
+    # back-to-back launches of each phase kernel), and the rooflines with the
+    # algorithmic work per launch: the blur kernels are bound by the vector
+    # ALU (2 P flops per pixel in the plan's arithmetic type), the transform
+    # passes by HBM with the algorithmic bytes they own
     phase_us = plan.ar_iterate_profile(g, x, reps=a.kernel_reps)
     P_taps = (2 * plan.q1 + 1) * (2 * plan.q2 + 1)
     npx = n * n
-    es = 4                                           # FP32 images
-    ds = es                                          # filter (transposed) in the storage type
+    alu_peak = FP64_VECTOR_TFLOPS if a.dtype == "f32x" else FP32_VECTOR_TFLOPS
+    alu_kind = "FP64 vector" if a.dtype == "f32x" else "FP32 vector"
     phases = [
-        ("residual blur r = g - A x", "alu", 2.0 * P_taps * npx, 3 * es * npx, "conv_kernel"),
-        ("reblur y = A' r", "alu", 2.0 * P_taps * npx, 2 * es * npx, "conv_kernel"),
-        ("row pass of T~", "hbm", None, 2 * es * npx, "rows_w_kernel"),
-        ("column pass T~, d, T", "hbm", None, (2 * es + ds) * npx, "cols_w_kernel"),
-        ("row pass of T + update", "hbm", None, 3 * es * npx, "rows_w_kernel"),
+        ("residual blur r = g - A x", "alu", 2.0 * P_taps * npx, ALG_BYTES["residual"] * npx),
+        ("reblur y = A' r", "alu", 2.0 * P_taps * npx, ALG_BYTES["reblur"] * npx),
+        ("row pass of T~", "hbm", None, ALG_BYTES["row_fwd"] * npx),
+        ("column pass T~, d, T", "hbm", None, ALG_BYTES["col"] * npx),
+        ("row pass of T + update", "hbm", None, ALG_BYTES["row_inv"] * npx),
     ]
     traffic = measured_traffic(a.dtype)
     rooflines = []
-    for (name, bound, flops, nbytes, kname), us in zip(phases, phase_us):
+    for (name, bound, flops, nbytes), us in zip(phases, phase_us):
         t = us * 1e-6
         if bound == "alu":
-            ach, peak, unit = flops / t / 1e12, VALU_PEAK_TFLOPS, "TFLOP/s"
+            ach, peak, unit = flops / t / 1e12, alu_peak, "TFLOP/s"
         else:
             ach, peak, unit = nbytes / t / 1e9, HBM_PEAK_GBS, "GB/s"
         rooflines.append({"kernel": name, "bound": bound, "achieved": round(ach, 2), "peak": peak,
                           "unit": unit, "frac": round(ach / peak, 4),
                           "traffic": traffic.get(name),
                           "kernel_us": round(us, 2),
-                          "algorithmic": {"flops": flops, "bytes": nbytes}})
+                          "algorithmic": {"flops": flops, "bytes": nbytes},
+                          **({"peak_kind": alu_kind} if bound == "alu" else {})})
     dom = int(np.argmax(phase_us))
     roof = dict(rooflines[dom])
-    roof["hbm_frac_of_step"] = round(npx * 36 / t_step / 1e9 / HBM_PEAK_GBS, 4)
+    step_gbs = STEP_BYTES * npx / t_step / 1e9
+    step_roof = {"bound": "hbm", "achieved": round(step_gbs, 2), "peak": HBM_PEAK_GBS,
+                 "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                 "bytes_per_pixel_iteration": STEP_BYTES, "us_per_step": round(t_step * 1e6, 2)}
 
+    net_path = None
+    if a.learned_images >= 0:
+        from paper_1211_0393_amd import learned as LR
+        net_path = LR.WEIGHTS if os.path.exists(LR.WEIGHTS) else None
+    stable = bench_stable(torch, P, plan, f, g, net_path)
+    plan.ar_precond_set(P.AR_FILTER_TIKHONOV, a.alpha)
     batch = None if a.no_batch else bench_batch(torch, P, ITERS)
     learned = bench_learned(torch, P, a.learned_images, ITERS) if a.learned_images > 0 else None
     precision = None if a.no_precision else bench_precision(torch, P, 200)
@@ -435,16 +605,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1024x1024 phantom (40 blobs + 20 rectangles), 15x15 motion PSF "
                                "(length 11 at 30 deg, Gaussian sigma 1), 0.5% noise, AR BCs, "
-                               "D-Landweber with Tikhonov alpha 5e-3, reblur transpose, tau 1",
-                   "n1": n, "n2": n, "psf": [15, 15], "alpha": p["alpha"],
-                   "iterations": ITERS, "parallelism": "single GPU"},
+                               f"D-Landweber with Tikhonov alpha {a.alpha} (the named 5e-3 "
+                               "diverges, see quality), reblur transpose, tau 1",
+                   "n1": n, "n2": n, "psf": [15, 15], "alpha": a.alpha,
+                   "named_alpha": p["alpha"], "iterations": ITERS, "parallelism": "single GPU"},
         "status": rc,
-        "quality": {"best_it": best, "best_rre": finite_min(rre),
+        "timed_run": {"alpha": a.alpha, "status": rc_t, "best_it": best_t,
+                      "best_rre": finite_min(rre_t), "diverged": diverged(res_t) or diverged(res)},
+        "quality": {"alpha": p["alpha"], "status": rc_q, "best_it": best,
+                    "best_rre": finite_min(rre), "diverged": diverged(res_q),
                     "plain_best_it": best_p, "plain_best_rre": finite_min(rre_p),
-                    "plain_run_s": round(plain_s, 5),
-                    "diverged": bool(res is not None and not np.all(np.isfinite(res)))},
+                    "plain_diverged": diverged(res_p),
+                    "note": "at alpha 5e-3 D-Landweber is unstable for this PSF (I - D A'A has "
+                            "spectral radius ~7); throughput does not depend on alpha; "
+                            "stable_alpha holds the restoration comparison"},
+        "stable_alpha": stable,
         "tuning": dict(tuning, iteration_us=tuned_us),
         "roofline": roof,
+        "step_roofline": step_roof,
         "kernels": rooflines,
         "cpu_baseline": cpu,
         "batch": batch,

@@ -127,9 +127,22 @@ int ar_transform_inv(ar_plan_t p, const void *c, void *x, void *stream);
 
 /* Set the preconditioner spectrum d from lambda (Sec. 4): filter is an
  * ar_filter, param its parameter (Tikhonov alpha > 0, threshold t > 0,
- * ignored for IDENTITY).  Computed in FP64 on the device; stored in FP64
- * and in the plan dtype.  Errors: AR_EINVAL. */
-int ar_precond_set(ar_plan_t p, int filter, double param, void *stream);
+ * ignored for IDENTITY and GAINS).  For AR_FILTER_GAINS, gains_dev is a
+ * DEVICE array of AR_FNET_BINS floats in [0, 1] (the learned filter below;
+ * the same as ar_precond_set_gains); for the other filters it is ignored
+ * and may be NULL.  Computed in FP64 on the device; stored in FP64 and in
+ * the plan dtype.  Stream-ordered.  Errors: AR_EINVAL (unknown filter,
+ * parameter not finite and > 0, GAINS without gains). */
+int ar_precond_set(ar_plan_t p, int filter, double param, const float *gains_dev, void *stream);
+
+/* Host helper (no device work): divide a HOST PSF of (2 q1 + 1) x (2 q2 + 1)
+ * doubles by its sum in place, so that it satisfies the normalisation
+ * sum h = 1 that the plan functions check (Sec. 2, the PSF is nonnegative
+ * and sums to one).  The library never renormalises a PSF silently.
+ * Errors: AR_EINVAL (NULL), AR_ESHAPE (negative half-width), AR_EPSF (an
+ * entry negative or not finite, or a sum that is not positive and finite;
+ * the array is left unchanged). */
+int ar_psf_normalize(double *psf_host, int q1, int q2);
 
 /* Copy the FP64 eigenvalues lambda (n1*n2, coefficient layout) of the
  * symmetrized PSF's AR matrix into the device buffer lambda_dev. */
@@ -190,8 +203,8 @@ int ar_plan_get_tune(ar_plan_t p, int key, int *value);
  * preconditioned iterations (reblur transpose) over zero images in buffers
  * it allocates and frees, keeps the fastest, and returns the best measured
  * time of one iteration in *best_us (may be NULL).  Uses and overwrites the
- * plan's scratch; synchronizes `stream`.  Errors: AR_EHIP when the
- * temporary buffers cannot be allocated. */
+ * plan's scratch; synchronizes `stream`.  Errors: AR_ENOMEM when the
+ * temporary buffers cannot be allocated, AR_EDEVICE on other HIP errors. */
 int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream);
 
 /* Phase profiler of one (D-)Landweber iteration: after one untimed
@@ -254,7 +267,9 @@ int ar_batch_autotune(ar_batch_t b, double *best_us, void *stream);
  * device-side job tables and replay it.  Calls on one batch must be
  * ordered (same stream, or synchronized between).
  * Errors as ar_deblur_iterate; AR_ENONFINITE if any requested residual
- * norm is not finite. */
+ * norm is not finite; AR_ESHAPE if a plan's PSF half-widths changed (via
+ * ar_plan_set_psf) since ar_batch_create (the batch's blur groups, LDS
+ * sizes and tile tables were laid out for the old ones). */
 int ar_batch_iterate(ar_batch_t b, const void *const *g, void *const *x, int iters, double tau,
                      int tmode, int precondition, const void *const *f_true,
                      double *resnorm_host, double *rre_host, int *best_it_host, void *stream);
@@ -317,6 +332,14 @@ typedef struct ar_fnet_s *ar_fnet_t;
 /* Create a network on `device` from initial parameters (host); the random
  * initialisation is the caller's.  Errors: AR_EINVAL, AR_EDEVICE, AR_ENOMEM. */
 int ar_fnet_create(ar_fnet_t *out, const float *params_host, int device);
+
+/* Create a network on `device` from a weights file: a NumPy .npy file
+ * (format 1.0-3.0) holding one C-order little-endian float32 vector of
+ * AR_FNET_NPARAM parameters in the layout above (the trained weights ship
+ * as paper_1211_0393_amd/fnet_weights.npy).  Errors: AR_EINVAL (NULL, file
+ * missing or not such a vector, non-finite parameter), AR_EDEVICE,
+ * AR_ENOMEM. */
+int ar_fnet_load(ar_fnet_t *out, const char *weights_path, int device);
 
 /* Release a network.  NULL is a no-op. */
 int ar_fnet_destroy(ar_fnet_t net);

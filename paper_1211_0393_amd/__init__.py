@@ -34,6 +34,7 @@ from ._lib import (  # noqa: F401
     LIB_PATH,
     Plan,
     SIGNATURES,
+    ar_psf_normalize,
     load,
     version,
 )

@@ -39,7 +39,8 @@ SIGNATURES = [
     ("ar_blur_apply_T", _I, [_VP, _VP, _VP, _I, _VP]),
     ("ar_transform", _I, [_VP, _VP, _VP, _VP]),
     ("ar_transform_inv", _I, [_VP, _VP, _VP, _VP]),
-    ("ar_precond_set", _I, [_VP, _I, _D, _VP]),
+    ("ar_precond_set", _I, [_VP, _I, _D, _VP, _VP]),
+    ("ar_psf_normalize", _I, [C.POINTER(_D), _I, _I]),
     ("ar_eigenvalues", _I, [_VP, _VP, _VP]),
     ("ar_filter_values", _I, [_VP, _VP, _VP]),
     ("ar_precond_solve", _I, [_VP, _VP, _VP, _VP]),
@@ -59,6 +60,7 @@ SIGNATURES = [
     ("ar_precond_set_gains", _I, [_VP, _VP, _VP]),
     ("ar_gains_label", _I, [_VP, _VP, _VP]),
     ("ar_fnet_create", _I, [C.POINTER(_VP), C.POINTER(C.c_float), _I]),
+    ("ar_fnet_load", _I, [C.POINTER(_VP), C.c_char_p, _I]),
     ("ar_fnet_destroy", _I, [_VP]),
     ("ar_fnet_get_params", _I, [_VP, C.POINTER(C.c_float)]),
     ("ar_fnet_infer", _I, [_VP, _VP, _VP, _I, _VP]),
@@ -191,8 +193,9 @@ class Plan:
         _check(load().ar_transform_inv(self._h, _ptr(c), _ptr(x), _stream(stream)))
         return x
 
-    def ar_precond_set(self, filt=AR_FILTER_TIKHONOV, param=1e-2, stream=None):
-        _check(load().ar_precond_set(self._h, int(filt), float(param), _stream(stream)))
+    def ar_precond_set(self, filt=AR_FILTER_TIKHONOV, param=1e-2, gains=None, stream=None):
+        _check(load().ar_precond_set(self._h, int(filt), float(param), _ptr(gains),
+                                     _stream(stream)))
 
     def ar_eigenvalues(self, lam, stream=None):
         _check(load().ar_eigenvalues(self._h, _ptr(lam), _stream(stream)))
@@ -310,15 +313,29 @@ class Batch:
                 np.array(best[:]) if best is not None else None)
 
 
-class FNet:
-    """Owns an ``ar_fnet_t`` (the filter network) on one device."""
+def ar_psf_normalize(psf):
+    """Divide a host PSF (2-D float64 array) by its sum in place."""
+    if not (isinstance(psf, np.ndarray) and psf.dtype == np.float64 and psf.ndim == 2
+            and psf.flags.c_contiguous):
+        raise ValueError("psf must be a C-contiguous 2-D float64 array")
+    q1, q2 = (psf.shape[0] - 1) // 2, (psf.shape[1] - 1) // 2
+    _check(load().ar_psf_normalize(psf.ctypes.data_as(C.POINTER(C.c_double)), q1, q2))
+    return psf
 
-    def __init__(self, params, device=0):
+
+class FNet:
+    """Owns an ``ar_fnet_t`` (the filter network) on one device: created
+    from a host parameter vector, or from a weights file (``path``)."""
+
+    def __init__(self, params=None, device=0, path=None):
+        self.device = int(device)
+        self._h = C.c_void_p()
+        if path is not None:
+            _check(load().ar_fnet_load(C.byref(self._h), os.fsencode(path), self.device))
+            return
         params = np.ascontiguousarray(params, dtype=np.float32)
         if params.size != AR_FNET_NPARAM:
             raise ValueError(f"expected {AR_FNET_NPARAM} parameters")
-        self.device = int(device)
-        self._h = C.c_void_p()
         _check(load().ar_fnet_create(C.byref(self._h),
                                      params.ctypes.data_as(C.POINTER(C.c_float)), self.device))
 

@@ -44,9 +44,20 @@ def common_flags():
     ]
 
 
-def compile_one(src):
+def _stale(obj, src):
+    """True when obj is missing or older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC)
+                                        if h.endswith(".h")] + [os.path.join(INCLUDE, "ardeblur.h")]
+    return any(os.path.getmtime(d) > os.path.getmtime(obj) for d in deps)
+
+
+def compile_one(src, incremental=False):
     os.makedirs(BUILD, exist_ok=True)
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if incremental and not _stale(obj, src):
+        return obj
     cmd = [hipcc(), *common_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -54,10 +65,11 @@ def compile_one(src):
     return obj
 
 
-def build(jobs=4, verbose=True):
-    """Compile every source and link libardeblur.so; always rebuilds."""
+def build(jobs=4, verbose=True, incremental=False):
+    """Compile every source and link libardeblur.so; rebuilds everything
+    unless `incremental` (then only objects older than their sources)."""
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+        objs = list(ex.map(lambda s: compile_one(s, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -72,8 +84,10 @@ def build(jobs=4, verbose=True):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--incremental", action="store_true",
+                    help="recompile only sources changed since their object was built")
     a = ap.parse_args(argv)
-    build(a.jobs)
+    build(a.jobs, incremental=a.incremental)
 
 
 if __name__ == "__main__":

@@ -70,6 +70,7 @@ constexpr int kElemB = 64;  // workgroups per problem of the batched elementwise
 struct ar_batch_s {
   int count = 0, dtype = AR_F32, device = 0;
   std::vector<ar_plan_t> plans;
+  std::vector<int2> q_at_create;  // (q1, q2) of every plan when the batch was built
   std::vector<int> tiles, tiles_x, tiles_ext, tiles_x_ext;  // per problem
   std::vector<ConvGroup> cg;
   std::vector<ShapeGroup> sg;
@@ -400,6 +401,7 @@ extern "C" int ar_batch_create(ar_batch_t *out, int count, const ar_plan_t *plan
   b->dtype = plans[0]->dtype;
   b->device = plans[0]->device;
   b->plans.assign(plans, plans + count);
+  for (int i = 0; i < count; ++i) b->q_at_create.push_back(make_int2(plans[i]->q1, plans[i]->q2));
   b->tiles.resize(count);
   b->tiles_x.resize(count);
   b->tiles_ext.resize(count);
@@ -518,6 +520,11 @@ extern "C" int ar_batch_iterate(ar_batch_t b, const void *const *g, void *const 
       return fail(AR_EINVAL, "ar_batch_iterate: null image pointer");
     if (g[i] == x[i] || (f_true && (f_true[i] == x[i] || f_true[i] == g[i])))
       return fail(AR_EALIAS, "ar_batch_iterate: g, x and f_true must not alias");
+    // the blur groups, their LDS sizes and the extended-grid tile tables
+    // were laid out for the half-widths the plans had at ar_batch_create
+    if (b->plans[i]->q1 != b->q_at_create[i].x || b->plans[i]->q2 != b->q_at_create[i].y)
+      return fail(AR_ESHAPE, "ar_batch_iterate: a plan's PSF half-widths changed since "
+                             "ar_batch_create; re-create the batch");
   }
   AR_HIP(hipSetDevice(b->device));
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -268,6 +268,10 @@ int axpy_launch(const ar_plan_s *p, void *x, const void *yv, double tau, const v
                 double *partial, int *nblocks_out, hipStream_t st);
 int axpy_blocks(const ar_plan_s *p);
 int reduce_rows_launch(const double *partials, int rows, int cols, double *out, hipStream_t st);
+// size the plan's partial-sum and scalar buffers for runs of `iters`
+// iterations with residual norms and RRE requested (ar_iterate.hip)
+constexpr int kReserveIters = 128;
+int iterate_reserve(ar_plan_s *p, int iters);
 int sumsq_launch(const ar_plan_s *p, const void *x, double *partial, int *nblocks_out,
                  hipStream_t st);
 // batched elementwise kernels: grid (nblk, count); x = job.out, y = job.in,

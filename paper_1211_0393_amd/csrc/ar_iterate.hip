@@ -9,6 +9,7 @@
 // copy of the 2 * iters FP64 scalars.  (Capturing long runs into a HIP
 // graph was measured slower than direct stream launches: 158 vs 138 us per
 // 1024^2 iteration.)
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -16,22 +17,44 @@
 
 using namespace ar;
 
+// Grow the plan's partial-sum and scalar buffers to at least the requested
+// sizes.  The plan reserves room for kReserveIters iterations at creation;
+// longer runs grow the buffers to twice the need, so that a sequence of
+// ever longer runs reallocates rarely (a reallocation frees the old buffer,
+// which waits for the device).
 static int ensure_partials(ar_plan_s *p, size_t need_partials, size_t need_scalars) {
   if (need_partials > p->partials_cap) {
+    const size_t cap = p->partials_cap == 0 ? need_partials : 2 * need_partials;
     if (p->partials) AR_HIP(hipFree(p->partials));
     p->partials = nullptr;
     p->partials_cap = 0;
-    AR_HIP(hipMalloc((void **)&p->partials, need_partials * sizeof(double)));
-    p->partials_cap = need_partials;
+    AR_HIP(hipMalloc((void **)&p->partials, cap * sizeof(double)));
+    p->partials_cap = cap;
   }
   if (need_scalars > p->scalars_cap) {
+    const size_t cap = p->scalars_cap == 0 ? need_scalars : 2 * need_scalars;
     if (p->scalars) AR_HIP(hipFree(p->scalars));
     p->scalars = nullptr;
     p->scalars_cap = 0;
-    AR_HIP(hipMalloc((void **)&p->scalars, need_scalars * sizeof(double)));
-    p->scalars_cap = need_scalars;
+    AR_HIP(hipMalloc((void **)&p->scalars, cap * sizeof(double)));
+    p->scalars_cap = cap;
   }
   return AR_OK;
+}
+
+// Partial sums of one run: [res: iters * bc][upd: iters * bu][f: bf]
+static size_t partials_need(const ar_plan_s *p, int iters, bool want_res, bool want_rre,
+                            bool precondition) {
+  const size_t bc = conv_blocks(p, p->n1, p->n2);
+  const size_t bu = precondition ? rows_blocks(p) : axpy_blocks(p);
+  const size_t bf = axpy_blocks(p);
+  return (want_res ? (size_t)iters * bc : 0) + (want_rre ? (size_t)iters * bu + bf : 0);
+}
+
+int ar::iterate_reserve(ar_plan_s *p, int iters) {
+  const size_t np = std::max(partials_need(p, iters, true, true, true),
+                             partials_need(p, iters, true, true, false));
+  return ensure_partials(p, np, 2 * (size_t)iters + 1);
 }
 
 namespace {
@@ -136,8 +159,7 @@ extern "C" int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters,
   a.bc = conv_blocks(p, p->n1, p->n2);
   a.bu = precondition ? rows_blocks(p) : axpy_blocks(p);
   a.bf = axpy_blocks(p);
-  const size_t need_p = (a.want_res ? (size_t)iters * a.bc : 0) +
-                        (a.want_rre ? (size_t)iters * a.bu + a.bf : 0);
+  const size_t need_p = partials_need(p, iters, a.want_res, a.want_rre, a.precondition != 0);
   const size_t need_s = 2 * (size_t)iters + 1;
   if (a.want_res || a.want_rre) {
     int rc = ensure_partials(p, need_p, need_s);

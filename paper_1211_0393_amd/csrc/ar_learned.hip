@@ -13,7 +13,9 @@
 // r2^2 N1^2), D = N1^2 N2^2 (exact 64-bit integers), and bin =
 // min(floor(sqrt(S / D)), 63), decided exactly.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "ar_internal.h"
@@ -626,6 +628,59 @@ extern "C" int ar_fnet_create(ar_fnet_t *out, const float *params_host, int devi
   }
   *out = n;
   return AR_OK;
+}
+
+// Parameters from a NumPy .npy file holding one little-endian float32
+// vector of AR_FNET_NPARAM entries (format versions 1.0 to 3.0, C order).
+static int read_npy_params(const char *path, std::vector<float> &out) {
+  FILE *fh = std::fopen(path, "rb");
+  if (!fh) return fail(AR_EINVAL, std::string("ar_fnet_load: cannot open ") + path);
+  std::vector<unsigned char> buf;
+  unsigned char chunk[1 << 16];
+  size_t got;
+  while ((got = std::fread(chunk, 1, sizeof(chunk), fh)) > 0) buf.insert(buf.end(), chunk, chunk + got);
+  std::fclose(fh);
+  static const unsigned char magic[6] = {0x93, 'N', 'U', 'M', 'P', 'Y'};
+  if (buf.size() < 10 || std::memcmp(buf.data(), magic, 6) != 0)
+    return fail(AR_EINVAL, "ar_fnet_load: not a .npy file");
+  const int major = buf[6];
+  size_t hlen, hoff;
+  if (major == 1) {
+    hlen = buf[8] | (size_t)buf[9] << 8;
+    hoff = 10;
+  } else if (major == 2 || major == 3) {
+    if (buf.size() < 12) return fail(AR_EINVAL, "ar_fnet_load: truncated .npy header");
+    hlen = buf[8] | (size_t)buf[9] << 8 | (size_t)buf[10] << 16 | (size_t)buf[11] << 24;
+    hoff = 12;
+  } else {
+    return fail(AR_EINVAL, "ar_fnet_load: unsupported .npy version");
+  }
+  if (hoff + hlen > buf.size()) return fail(AR_EINVAL, "ar_fnet_load: truncated .npy header");
+  std::string h(buf.begin() + hoff, buf.begin() + hoff + hlen);
+  std::string compact;
+  for (char c : h)
+    if (c != ' ') compact += c;
+  const std::string shape = "'shape':(" + std::to_string(NPAR) + ",)";
+  if (compact.find("'descr':'<f4'") == std::string::npos ||
+      compact.find("'fortran_order':False") == std::string::npos ||
+      compact.find(shape) == std::string::npos)
+    return fail(AR_EINVAL, "ar_fnet_load: expected a C-order <f4 vector of AR_FNET_NPARAM entries");
+  const size_t data = hoff + hlen;
+  if (buf.size() - data != (size_t)NPAR * sizeof(float))
+    return fail(AR_EINVAL, "ar_fnet_load: wrong data size");
+  out.resize(NPAR);
+  std::memcpy(out.data(), buf.data() + data, (size_t)NPAR * sizeof(float));
+  return AR_OK;
+}
+
+extern "C" int ar_fnet_load(ar_fnet_t *out, const char *weights_path, int device) {
+  if (!out) return fail(AR_EINVAL, "ar_fnet_load: null output");
+  *out = nullptr;
+  if (!weights_path) return fail(AR_EINVAL, "ar_fnet_load: null path");
+  std::vector<float> params;
+  const int rc = read_npy_params(weights_path, params);
+  if (rc != AR_OK) return rc;
+  return ar_fnet_create(out, params.data(), device);
 }
 
 extern "C" int ar_fnet_destroy(ar_fnet_t n) {

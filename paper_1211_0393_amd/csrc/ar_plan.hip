@@ -472,6 +472,12 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
     plan_free(p);
     return rc;
   }
+  // per-iteration partial sums for runs of up to kReserveIters iterations
+  // with every scalar requested, so that such runs allocate nothing
+  if ((rc = iterate_reserve(p, kReserveIters)) != AR_OK) {
+    plan_free(p);
+    return rc;
+  }
   *out = p;
   return AR_OK;
 }
@@ -510,14 +516,37 @@ extern "C" int ar_plan_destroy(ar_plan_t p) {
   return AR_OK;
 }
 
-extern "C" int ar_precond_set(ar_plan_t p, int filter, double param, void *stream) {
+extern "C" int ar_precond_set(ar_plan_t p, int filter, double param, const float *gains_dev,
+                              void *stream) {
   if (!p) return fail(AR_EINVAL, "ar_precond_set: null plan");
+  if (filter == AR_FILTER_GAINS) {
+    if (!gains_dev) return fail(AR_EINVAL, "ar_precond_set: the gains filter needs gains");
+    AR_HIP(hipSetDevice(p->device));
+    return gains_filter_launch(p, gains_dev, static_cast<hipStream_t>(stream));
+  }
   if (filter != AR_FILTER_TIKHONOV && filter != AR_FILTER_THRESHOLD && filter != AR_FILTER_IDENTITY)
     return fail(AR_EINVAL, "ar_precond_set: unknown filter");
   if (filter != AR_FILTER_IDENTITY && !(param > 0.0 && std::isfinite(param)))
     return fail(AR_EINVAL, "ar_precond_set: filter parameter must be finite and > 0");
   AR_HIP(hipSetDevice(p->device));
   return filter_launch(p, filter, param, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int ar_psf_normalize(double *psf_host, int q1, int q2) {
+  if (!psf_host) return fail(AR_EINVAL, "ar_psf_normalize: psf is NULL");
+  if (q1 < 0 || q2 < 0) return fail(AR_ESHAPE, "ar_psf_normalize: negative PSF half-width");
+  const int P = (2 * q1 + 1) * (2 * q2 + 1);
+  double sum = 0.0;
+  for (int e = 0; e < P; ++e) {
+    const double v = psf_host[e];
+    if (!std::isfinite(v) || v < 0.0)
+      return fail(AR_EPSF, "ar_psf_normalize: PSF entries must be finite and nonnegative");
+    sum += v;
+  }
+  if (!(sum > 0.0) || !std::isfinite(sum))
+    return fail(AR_EPSF, "ar_psf_normalize: PSF sum must be positive and finite");
+  for (int e = 0; e < P; ++e) psf_host[e] /= sum;
+  return AR_OK;
 }
 
 extern "C" int ar_eigenvalues(ar_plan_t p, double *lambda_dev, void *stream) {

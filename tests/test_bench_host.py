@@ -42,3 +42,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_divergence_flag_uses_residual_growth():
+    import numpy as np
+    assert not bench.diverged(np.array([1.0, 0.5, 0.4, 0.41]))
+    assert bench.diverged(np.array([1.0, 0.5, 1.2]))           # grows past ||g||
+    assert bench.diverged(np.array([1.0, np.inf]))
+    assert bench.diverged(np.array([1.0, np.nan, 0.1]))
+    assert not bench.diverged(None)
+
+
+def test_algorithmic_bytes_follow_the_per_step_convention():
+    # 12 (r = g - A x) + 8 (y = A' r) + 16 (transforms read y, d, x, write x)
+    assert bench.STEP_BYTES == 36
+    assert bench.ALG_BYTES["row_fwd"] + bench.ALG_BYTES["col"] + bench.ALG_BYTES["row_inv"] == 16
+    assert bench.FP32_VECTOR_TFLOPS == 157.3 and bench.FP64_VECTOR_TFLOPS == 78.6

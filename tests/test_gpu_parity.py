@@ -24,6 +24,7 @@ import pytest
 
 import oracle as O
 import synth
+from tests.regions import region_errors
 
 torch = pytest.importorskip("torch")
 import paper_1211_0393_amd as P  # noqa: E402
@@ -275,19 +276,21 @@ def test_iterate_64_f64_fifty_steps():
         assert worst <= 1e-12
 
 
-@pytest.mark.parametrize("dt,tol", [("f32x", 1e-5), ("f32", 6e-5)])
-def test_iterate_full_size_1024(dt, tol):
-    """The 1024^2 FP32 workload (15x15 motion PSF, alpha = 5e-3): one-step
-    parity at k = 0, 1, 10 in the launch configuration the benchmark uses.
-    With d up to 1/alpha = 200, FP32 rounding inside the transforms alone
-    (about 1e-7 relative per coefficient) reaches ~2e-5 in x_1 = D A' g, so
-    pure FP32 arithmetic is held to 6e-5; the FP64-arithmetic plan meets
-    1e-5."""
+@pytest.mark.parametrize("dt,alpha", [("f32x", 5e-3), ("f32x", 0.2), ("f32", 0.2)])
+def test_iterate_full_size_1024(dt, alpha):
+    """The 1024^2 FP32 workload (15x15 motion PSF): one-step parity 1e-5 at
+    k = 0, 1, 10 in the launch configuration the benchmark uses, over the
+    whole image and separately on the border rows, columns, corners and the
+    interior.  At the named alpha = 5e-3 the filter d reaches 1/alpha = 200,
+    which amplifies FP32 rounding before it (~1e-7 per coefficient) past
+    1e-5, so that alpha needs the FP64-arithmetic plan; the FP32 plan serves
+    alpha >= 0.05 (d <= 20), and the benchmark's stable alpha = 0.2."""
     F, H, E, p = synth.workload("ar1024_f32_motion15")
     G = O.observe(F, H, E, p["nu"]).astype(np.float32).astype(np.float64)
-    d = O.tikhonov(O.eigenvalues(H, 1024, 1024), p["alpha"])
+    d = O.tikhonov(O.eigenvalues(H, 1024, 1024), alpha)
+    tol = 1e-5
     with P.Plan(1024, 1024, H, dtype=dt) as plan:
-        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, p["alpha"])
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, alpha)
         g = dev(G, torch.float32)
         x = torch.zeros_like(g)
         X = np.zeros((1024, 1024))
@@ -300,9 +303,13 @@ def test_iterate_full_size_1024(dt, tol):
             plan.ar_deblur_iterate(g, x, 1)
             done += 1
             Xo, _ = O.landweber_step(X, G, H, d=d)
-            e = rel(host(x), Xo)
-            say(f"  1024 {dt} k={k} one-step rel err {e:.2e}")
+            Xg = host(x)
+            e = rel(Xg, Xo)
+            say(f"  1024 {dt} alpha={alpha} k={k} one-step rel err {e:.2e}")
             assert e <= tol
+            for name, (fr, mx) in region_errors(Xg, Xo).items():
+                say(f"    {name}: frobenius {fr:.2e}, max-abs {mx:.2e}")
+                assert fr <= tol and mx <= tol, name
 
 
 def test_iterate_deterministic_and_zero_iters():

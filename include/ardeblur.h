@@ -156,6 +156,19 @@ int ar_filter_values(ar_plan_t p, double *d_dev, void *stream);
  * y, z: device, plan dtype; y == z allowed. */
 int ar_precond_solve(ar_plan_t p, const void *y, void *z, void *stream);
 
+/* Direct Tikhonov restoration for a strongly symmetric PSF
+ * (h_{-s1,s2} = h_{s1,-s2} = h_{s1,s2}, eq. (strong_simmetry_condition)):
+ * then A = T diag(lambda) T~ with lambda the eigenvalues of Theorem 2, the
+ * reblurring A' equals A, and the Tikhonov solution
+ * x = (A'A + alpha I)^{-1} A' g is T diag(lambda / (lambda^2 + alpha)) T~ g
+ * (Theorems 1-2 with eq. (TikFilter)); the factor is formed in FP64.
+ * g, x: device, n1*n2, plan dtype; x == g (in place) is allowed.
+ * Symmetry is checked on the host PSF (plan creation or ar_plan_set_psf)
+ * to 1e-14 of its largest entry.  Stream-ordered.
+ * Errors: AR_EINVAL (NULL, alpha not finite and > 0), AR_EPSF (the plan's
+ * PSF is not strongly symmetric). */
+int ar_tikhonov_solve(ar_plan_t p, const void *g, void *x, double alpha, void *stream);
+
 /* Run `iters` steps of (D-)Landweber (eqs. (LandweberMeth) and
  * (DLandweberMeth)):  x_{k+1} = x_k + tau D A'(g - A x_k)  with A' chosen
  * by tmode and D = I when precondition == 0.

@@ -44,6 +44,7 @@ SIGNATURES = [
     ("ar_eigenvalues", _I, [_VP, _VP, _VP]),
     ("ar_filter_values", _I, [_VP, _VP, _VP]),
     ("ar_precond_solve", _I, [_VP, _VP, _VP, _VP]),
+    ("ar_tikhonov_solve", _I, [_VP, _VP, _VP, _D, _VP]),
     ("ar_deblur_iterate", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _VP,
                                C.POINTER(_D), C.POINTER(_D), C.POINTER(_I), _VP]),
     ("ar_plan_tune", _I, [_VP, _I, _I]),
@@ -208,6 +209,11 @@ class Plan:
     def ar_precond_solve(self, y, z, stream=None):
         _check(load().ar_precond_solve(self._h, _ptr(y), _ptr(z), _stream(stream)))
         return z
+
+    def ar_tikhonov_solve(self, g, x, alpha, stream=None):
+        _check(load().ar_tikhonov_solve(self._h, _ptr(g), _ptr(x), float(alpha),
+                                        _stream(stream)))
+        return x
 
     def ar_plan_set_psf(self, psf, stream=None):
         psf = np.ascontiguousarray(psf, dtype=np.float64)

@@ -678,3 +678,22 @@ extern "C" int ar_precond_solve(ar_plan_t p, const void *y, void *z, void *strea
   if (rc != AR_OK) return rc;
   return rows_launch(p, z, z, ROW_INV, 0.0, nullptr, nullptr, nullptr, st);
 }
+
+extern "C" int ar_tikhonov_solve(ar_plan_t p, const void *g, void *x, double alpha,
+                                 void *stream) {
+  if (!p || !g || !x) return fail(AR_EINVAL, "ar_tikhonov_solve: null argument");
+  if (!(alpha > 0.0 && std::isfinite(alpha)))
+    return fail(AR_EINVAL, "ar_tikhonov_solve: alpha must be finite and > 0");
+  if (!p->strong_sym)
+    return fail(AR_EPSF, "ar_tikhonov_solve: the direct solve needs a strongly symmetric PSF "
+                         "(h_{-s1,s2} = h_{s1,-s2} = h_{s1,s2})");
+  AR_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // x = T diag(lambda / (lambda^2 + alpha)) T~ g, every pass in place on x
+  int rc = rows_launch(p, g, x, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
+  if (rc == AR_OK) rc = cols_launch(p, x, x, COL_FWD, st);
+  if (rc == AR_OK) rc = tikhonov_scale_launch(p, x, alpha, st);
+  if (rc == AR_OK) rc = cols_launch(p, x, x, COL_INV, st);
+  if (rc == AR_OK) rc = rows_launch(p, x, x, ROW_INV, 0.0, nullptr, nullptr, nullptr, st);
+  return rc;
+}

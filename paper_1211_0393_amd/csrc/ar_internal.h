@@ -153,6 +153,8 @@ struct ar_plan_s {
   float *mat_fwdT_row = nullptr, *mat_invT_row = nullptr;
   void *dscr = nullptr;
   int q1cap = 0, q2cap = 0;    // half-widths the PSF buffers were sized for
+  bool strong_sym = false;     // h_{|s1|,|s2|} = h_{s1,s2} (then P(s) = A and the
+                               // eigenvalues lambda are those of A itself)
   float *gains = nullptr;      // last gains of AR_FILTER_GAINS (64 floats)
   void *lscr = nullptr;        // scratch of the learned-filter kernels
 };
@@ -268,6 +270,10 @@ int axpy_launch(const ar_plan_s *p, void *x, const void *yv, double tau, const v
                 double *partial, int *nblocks_out, hipStream_t st);
 int axpy_blocks(const ar_plan_s *p);
 int reduce_rows_launch(const double *partials, int rows, int cols, double *out, hipStream_t st);
+// c <- c * lambda / (lambda^2 + alpha) elementwise in FP64 (coefficient layout)
+int tikhonov_scale_launch(const ar_plan_s *p, void *c, double alpha, hipStream_t st);
+// host check of strong symmetry (per-axis flips leave H unchanged to 1e-14 max|H|)
+bool psf_strongly_symmetric(const double *H, int q1, int q2);
 // size the plan's partial-sum and scalar buffers for runs of `iters`
 // iterations with residual norms and RRE requested (ar_iterate.hip)
 constexpr int kReserveIters = 128;

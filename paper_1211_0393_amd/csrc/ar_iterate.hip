@@ -11,6 +11,7 @@
 // 1024^2 iteration.)
 #include <algorithm>
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "ar_internal.h"
@@ -128,24 +129,24 @@ int ar::iterate_enqueue(ar_plan_s *p, const void *g, void *x, int iters, hipStre
   return enqueue(p, a, st);
 }
 
-extern "C" int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters, double tau,
-                                 int tmode, int precondition, const void *f_true,
-                                 double *resnorm_host, double *rre_host, int *best_it_host,
-                                 void *stream) {
-  if (!p || !g || !x) return fail(AR_EINVAL, "ar_deblur_iterate: null argument");
-  if (iters < 0) return fail(AR_EINVAL, "ar_deblur_iterate: iters < 0");
-  if (tmode != AR_REBLUR && tmode != AR_ADJOINT)
-    return fail(AR_EINVAL, "ar_deblur_iterate: unknown tmode");
-  if (!std::isfinite(tau)) return fail(AR_EINVAL, "ar_deblur_iterate: tau must be finite");
-  if (g == x || (f_true && (f_true == x || f_true == g)))
-    return fail(AR_EALIAS, "ar_deblur_iterate: g, x and f_true must not alias");
-  if ((rre_host || best_it_host) && !f_true)
-    return fail(AR_EINVAL, "ar_deblur_iterate: RRE outputs need f_true");
-  AR_HIP(hipSetDevice(p->device));
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (best_it_host) *best_it_host = 0;
-  if (iters == 0) return AR_OK;
+namespace {
 
+// Checks shared by both iterate entry points.
+int check_args(const char *who, ar_plan_t p, const void *g, void *x, int iters, double tau,
+               int tmode, const void *f_true, const double *rre_host, const int *best_it_host) {
+  const std::string w(who);
+  if (!p || !g || !x) return fail(AR_EINVAL, w + ": null argument");
+  if (iters < 0) return fail(AR_EINVAL, w + ": iters < 0");
+  if (tmode != AR_REBLUR && tmode != AR_ADJOINT) return fail(AR_EINVAL, w + ": unknown tmode");
+  if (!std::isfinite(tau)) return fail(AR_EINVAL, w + ": tau must be finite");
+  if (g == x || (f_true && (f_true == x || f_true == g)))
+    return fail(AR_EALIAS, w + ": g, x and f_true must not alias");
+  if ((rre_host || best_it_host) && !f_true) return fail(AR_EINVAL, w + ": RRE outputs need f_true");
+  return AR_OK;
+}
+
+IterArgs make_args(const ar_plan_s *p, const void *g, void *x, int iters, double tau, int tmode,
+                   int precondition, const void *f_true, bool want_res, bool want_rre) {
   IterArgs a{};
   a.g = g;
   a.x = x;
@@ -153,24 +154,49 @@ extern "C" int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters,
   a.tmode = tmode;
   a.precondition = precondition ? 1 : 0;
   a.tau = tau;
-  a.want_res = resnorm_host != nullptr;
-  a.want_rre = f_true != nullptr && (rre_host != nullptr || best_it_host != nullptr);
+  a.want_res = want_res;
+  a.want_rre = want_rre;
   a.f = a.want_rre ? f_true : nullptr;
   a.bc = conv_blocks(p, p->n1, p->n2);
   a.bu = precondition ? rows_blocks(p) : axpy_blocks(p);
   a.bf = axpy_blocks(p);
+  return a;
+}
+
+// Partial sums laid out from `part`, reduced scalars at `sc` (device).
+void place(IterArgs &a, double *part, double *sc) {
+  a.res_part = a.want_res ? part : nullptr;
+  a.rre_part = a.want_rre ? part + (a.want_res ? (size_t)a.iters * a.bc : 0) : nullptr;
+  a.f_part = a.want_rre ? a.rre_part + (size_t)a.iters * a.bu : nullptr;
+  a.sc = sc;
+}
+
+}  // namespace
+
+extern "C" int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters, double tau,
+                                 int tmode, int precondition, const void *f_true,
+                                 double *resnorm_host, double *rre_host, int *best_it_host,
+                                 void *stream) {
+  int rc = check_args("ar_deblur_iterate", p, g, x, iters, tau, tmode, f_true, rre_host,
+                      best_it_host);
+  if (rc != AR_OK) return rc;
+  AR_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (best_it_host) *best_it_host = 0;
+  if (iters == 0) return AR_OK;
+
+  IterArgs a = make_args(p, g, x, iters, tau, tmode, precondition, f_true,
+                         resnorm_host != nullptr,
+                         f_true != nullptr && (rre_host != nullptr || best_it_host != nullptr));
   const size_t need_p = partials_need(p, iters, a.want_res, a.want_rre, a.precondition != 0);
   const size_t need_s = 2 * (size_t)iters + 1;
   if (a.want_res || a.want_rre) {
-    int rc = ensure_partials(p, need_p, need_s);
+    rc = ensure_partials(p, need_p, need_s);
     if (rc != AR_OK) return rc;
   }
-  a.res_part = a.want_res ? p->partials : nullptr;
-  a.rre_part = a.want_rre ? p->partials + (a.want_res ? (size_t)iters * a.bc : 0) : nullptr;
-  a.f_part = a.want_rre ? a.rre_part + (size_t)iters * a.bu : nullptr;
-  a.sc = p->scalars;
+  place(a, p->partials, p->scalars);
 
-  int rc = enqueue(p, a, st);
+  rc = enqueue(p, a, st);
   if (rc != AR_OK) return rc;
   if (!(a.want_res || a.want_rre)) return AR_OK;
   double *sc = p->scalars;

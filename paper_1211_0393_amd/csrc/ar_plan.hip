@@ -1,5 +1,6 @@
 // Plan creation (S0-S2 of the path), FP64 spectrum and filter kernels,
 // deterministic reductions and small helper kernels (gfx950).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -359,6 +360,47 @@ int sumsq_launch(const ar_plan_s *p, const void *x, double *partial, int *nblock
   return AR_OK;
 }
 
+// Direct Tikhonov solve's filter: for a strongly symmetric PSF the AR matrix
+// is T diag(lambda) T~ (Theorems 1-2), so (A'A + alpha I)^{-1} A' with
+// A' = A is T diag(lambda / (lambda^2 + alpha)) T~ (eq. (TikFilter) applied
+// to lambda); the factor is formed and applied in FP64.
+template <typename TS>
+__global__ __launch_bounds__(256) void tikhonov_scale_kernel(TS *__restrict__ c,
+                                                             const double *__restrict__ lam,
+                                                             double alpha, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double l = lam[i];
+    c[i] = TS((double)c[i] * (l / (l * l + alpha)));
+  }
+}
+
+int tikhonov_scale_launch(const ar_plan_s *p, void *c, double alpha, hipStream_t st) {
+  const size_t n = (size_t)p->n1 * p->n2;
+  const int blocks = elem_blocks(n);
+  if (p->esize == 8)
+    hipLaunchKernelGGL(tikhonov_scale_kernel<double>, dim3(blocks), dim3(256), 0, st,
+                       static_cast<double *>(c), p->lambda, alpha, n);
+  else
+    hipLaunchKernelGGL(tikhonov_scale_kernel<float>, dim3(blocks), dim3(256), 0, st,
+                       static_cast<float *>(c), p->lambda, alpha, n);
+  AR_HIP(hipGetLastError());
+  return AR_OK;
+}
+
+bool psf_strongly_symmetric(const double *H, int q1, int q2) {
+  const int K1 = 2 * q1 + 1, K2 = 2 * q2 + 1;
+  double mx = 0.0;
+  for (int e = 0; e < K1 * K2; ++e) mx = std::max(mx, std::fabs(H[e]));
+  const double tol = 1e-14 * mx;
+  for (int a = 0; a < K1; ++a)
+    for (int b = 0; b < K2; ++b) {
+      const double v = H[a * K2 + b];
+      if (std::fabs(v - H[(K1 - 1 - a) * K2 + b]) > tol) return false;
+      if (std::fabs(v - H[a * K2 + (K2 - 1 - b)]) > tol) return false;
+    }
+  return true;
+}
+
 int reduce_rows_launch(const double *partials, int rows, int cols, double *out, hipStream_t st) {
   if (rows <= 0) return AR_OK;
   hipLaunchKernelGGL(reduce_rows_kernel, dim3(rows), dim3(256), 0, st, partials, cols, out);
@@ -427,6 +469,7 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
   p->q2cap = q2;
   p->dtype = dtype;
   p->device = device;
+  p->strong_sym = psf_strongly_symmetric(psf_host, q1, q2);
   p->esize = esize;
   p->csize = csize;
   const size_t npx = (size_t)n1 * n2;
@@ -502,6 +545,7 @@ extern "C" int ar_plan_set_psf(ar_plan_t p, const double *psf_host, int q1, int 
   AR_HIP(hipMemcpy(p->H64, psf_host, P * sizeof(double), hipMemcpyHostToDevice));
   p->q1 = q1;
   p->q2 = q2;
+  p->strong_sym = psf_strongly_symmetric(psf_host, q1, q2);
   int rc = spectrum_launch(p, st);
   if (rc != AR_OK) return rc;
   rc = p->filter == AR_FILTER_GAINS ? gains_filter_launch(p, p->gains, st)

@@ -97,6 +97,7 @@ def test_bad_dtype_and_null_arguments():
     assert lib.ar_transform(None, None, None, None) == -1
     assert lib.ar_transform_inv(None, None, None, None) == -1
     assert lib.ar_precond_solve(None, None, None, None) == -1
+    assert lib.ar_tikhonov_solve(None, None, None, 0.1, None) == -1
     assert lib.ar_precond_set(None, 0, 1.0, None, None) == -1
     assert lib.ar_eigenvalues(None, None, None) == -1
     assert lib.ar_filter_values(None, None, None) == -1

@@ -135,8 +135,13 @@ def test_dense_one_step_2048_tail31():
             Xg = host(x)
             errs[dt] = rel(Xg, X1o)
         say(f"  2048 one-step rel err at k=0, {dt}: {errs[dt]:.2e}")
+        # per region: Frobenius within the bound; the largest single-pixel
+        # error (over max |x|) within four times it (over 4 * 10^6 pixels the
+        # maximum of the rounding field sits ~3x above its Frobenius mean,
+        # measured); an error confined to the border would show as a border
+        # region above the interior
         for name, (fr, mx) in region_errors(Xg, X1o).items():
             say(f"    {name}: frobenius {fr:.2e}, max-abs {mx:.2e}")
-            assert fr <= tol[dt] and mx <= tol[dt], (dt, name)
+            assert fr <= tol[dt] and mx <= 4 * tol[dt], (dt, name)
     for dt, t in tol.items():
         assert errs[dt] <= t, dt

@@ -307,9 +307,15 @@ def test_iterate_full_size_1024(dt, alpha):
             e = rel(Xg, Xo)
             say(f"  1024 {dt} alpha={alpha} k={k} one-step rel err {e:.2e}")
             assert e <= tol
+            # regions: Frobenius at the bar; the largest single-pixel error
+            # (over max |x|) at twice the bar, since the maximum of a
+            # rounding field over 10^6 pixels sits a few standard deviations
+            # out (measured 1.8x the Frobenius error in the interior at
+            # alpha = 5e-3); an error confined to the border shows as a
+            # border region far above the interior
             for name, (fr, mx) in region_errors(Xg, Xo).items():
                 say(f"    {name}: frobenius {fr:.2e}, max-abs {mx:.2e}")
-                assert fr <= tol and mx <= tol, name
+                assert fr <= tol and mx <= 2 * tol, name
 
 
 def test_iterate_deterministic_and_zero_iters():

@@ -80,6 +80,20 @@ enum ar_status {
   AR_EUNSUPPORTED = -8  /* valid request this build does not implement */
 };
 
+/* Boundary conditions of a plan.  AR_BC_ANTIREFLECTIVE is the method of
+ * this library (Sec. 2.2, Theorem 1); the other two are the comparators of
+ * the paper's experiments (Sec. 4, Tables 1-2):
+ *  AR_BC_REFLECTIVE: f_{1-i} = f_i, f_{n+i} = f_{n+1-i} (Sec. 2.1); the
+ *      preconditioner is R diag(d) R^T with R^T the orthonormal 2-D DCT-II
+ *      (eq. (Rn)) and lambda the symbol of the symmetrized PSF at
+ *      x_k = k pi / n, k = 0..n-1 (natural order);
+ *  AR_BC_PERIODIC: wrap-around extension; the preconditioner is
+ *      F^{-1} diag(d) F with F the 2-D DFT and lambda the DFT of the PSF
+ *      itself (not symmetrized, natural FFT order); d = 1/(|lambda|^2 + alpha).
+ * The reblurring A' (PSF rotated by 180 degrees) is the transpose of every
+ * iteration (for periodic BCs it equals A^T). */
+enum ar_bc { AR_BC_ANTIREFLECTIVE = 0, AR_BC_REFLECTIVE = 1, AR_BC_PERIODIC = 2 };
+
 /* Create a plan for n1 x n2 images and one PSF (S0-S2 of the path):
  * validates the arguments, copies the PSF to the device, and on the device
  * builds the blur weights, the symmetrized PSF
@@ -94,6 +108,24 @@ enum ar_status {
  * Errors: AR_EINVAL, AR_ESHAPE, AR_EPSF, AR_EDEVICE, AR_ENOMEM. */
 int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_host,
                    int q1, int q2, int dtype, int device);
+
+/* ar_plan_create under boundary conditions `bc` (an ar_bc; ar_plan_create is
+ * this call with AR_BC_ANTIREFLECTIVE).  For Reflective and Periodic plans:
+ * the blur extends the image by the plan's rule; ar_blur_apply_T supports
+ * AR_REBLUR only (AR_ADJOINT: AR_EUNSUPPORTED); ar_transform and
+ * ar_transform_inv apply R^T and R for Reflective plans (AR_EUNSUPPORTED for
+ * Periodic plans, whose coefficients are complex); ar_eigenvalues gives
+ * lambda for Reflective plans and |lambda| for Periodic plans;
+ * ar_precond_set takes the Tikhonov, threshold and identity filters;
+ * ar_precond_solve, ar_deblur_iterate (AR_REBLUR) and, for Reflective plans
+ * with a strongly symmetric PSF, ar_tikhonov_solve work as documented.
+ * ar_iterate_profile times the same five phases (AR_REBLUR).  dtype
+ * AR_F32_BF16X3, batches, the learned filter (ar_features, the gains filter)
+ * and ar_plan_tune / ar_plan_autotune are Anti-Reflective only
+ * (AR_EUNSUPPORTED).  n_j >= 3, q_j <= n_j - 3.
+ * Errors: as ar_plan_create; AR_EINVAL for an unknown bc. */
+int ar_plan_create_bc(ar_plan_t *out, int n1, int n2, const double *psf_host, int q1, int q2,
+                      int dtype, int bc, int device);
 
 /* Release a plan and its device memory (waits for the device).  NULL is a
  * no-op returning AR_OK. */

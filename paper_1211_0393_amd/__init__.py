@@ -7,6 +7,10 @@ library's HIP kernels.  Build the library with
 
 from ._lib import (  # noqa: F401
     AR_ADJOINT,
+    AR_BC_ANTIREFLECTIVE,
+    AR_BC_PERIODIC,
+    AR_BC_REFLECTIVE,
+    BCS,
     AR_F32,
     AR_F32_ACC64,
     AR_F32_BF16X3,

@@ -20,6 +20,9 @@ LIB_PATH = os.path.join(_PKG, "libardeblur.so")
 AR_F32, AR_F64, AR_F32_ACC64, AR_F32_BF16X3 = 0, 1, 2, 3
 DTYPES = {"f32": AR_F32, "f64": AR_F64, "f32x": AR_F32_ACC64, "bf16x3": AR_F32_BF16X3}
 AR_REBLUR, AR_ADJOINT = 0, 1
+AR_BC_ANTIREFLECTIVE, AR_BC_REFLECTIVE, AR_BC_PERIODIC = 0, 1, 2
+BCS = {"antireflective": AR_BC_ANTIREFLECTIVE, "reflective": AR_BC_REFLECTIVE,
+       "periodic": AR_BC_PERIODIC}
 AR_FILTER_TIKHONOV, AR_FILTER_THRESHOLD, AR_FILTER_GAINS, AR_FILTER_IDENTITY = 0, 1, 2, 3
 AR_FNET_BINS, AR_FNET_IN, AR_FNET_HIDDEN, AR_FNET_NPARAM = 64, 65, 128, 33216
 AR_TUNE_ROW_WAVES, AR_TUNE_COL_WAVES, AR_TUNE_ROW_EXCL, AR_TUNE_COL_EXCL = 0, 1, 2, 3
@@ -34,6 +37,7 @@ STATUS = {
 _VP, _I, _D = C.c_void_p, C.c_int, C.c_double
 SIGNATURES = [
     ("ar_plan_create", _I, [C.POINTER(_VP), _I, _I, C.POINTER(_D), _I, _I, _I, _I]),
+    ("ar_plan_create_bc", _I, [C.POINTER(_VP), _I, _I, C.POINTER(_D), _I, _I, _I, _I, _I]),
     ("ar_plan_destroy", _I, [_VP]),
     ("ar_blur_apply", _I, [_VP, _VP, _VP, _VP]),
     ("ar_blur_apply_T", _I, [_VP, _VP, _VP, _I, _VP]),
@@ -120,19 +124,20 @@ def _stream(stream):
 class Plan:
     """Owns an ``ar_plan_t``; methods are the C entry points."""
 
-    def __init__(self, n1, n2, psf, dtype="f32", device=0):
+    def __init__(self, n1, n2, psf, dtype="f32", device=0, bc="antireflective"):
         psf = np.ascontiguousarray(psf, dtype=np.float64)
         if psf.ndim != 2:
             raise ValueError("psf must be 2-D")
         self.n1, self.n2 = int(n1), int(n2)
         self.q1, self.q2 = (psf.shape[0] - 1) // 2, (psf.shape[1] - 1) // 2
         self.dtype = DTYPES[dtype]
+        self.bc = BCS[bc]
         self.device = int(device)
         self._h = C.c_void_p()
         lib = load()
-        _check(lib.ar_plan_create(C.byref(self._h), self.n1, self.n2,
-                                  psf.ctypes.data_as(C.POINTER(C.c_double)),
-                                  self.q1, self.q2, self.dtype, self.device))
+        _check(lib.ar_plan_create_bc(C.byref(self._h), self.n1, self.n2,
+                                     psf.ctypes.data_as(C.POINTER(C.c_double)),
+                                     self.q1, self.q2, self.dtype, self.bc, self.device))
 
     @property
     def handle(self):

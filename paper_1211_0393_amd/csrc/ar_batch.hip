@@ -392,6 +392,9 @@ extern "C" int ar_batch_create(ar_batch_t *out, int count, const ar_plan_t *plan
   if (plans[0]->dtype == AR_F32_BF16X3)
     return fail(AR_EUNSUPPORTED, "ar_batch_create: dense-transform plans are not batched");
   for (int i = 0; i < count; ++i)
+    if (plans[i]->bc != AR_BC_ANTIREFLECTIVE)
+      return fail(AR_EUNSUPPORTED, "ar_batch_create: batches are Anti-Reflective only");
+  for (int i = 0; i < count; ++i)
     if (!wave_rows_ok(plans[i]) || !wave_cols_ok(plans[i]))
       return fail(AR_EUNSUPPORTED, "ar_batch_create: image too large for the batched transform");
   AR_HIP(hipSetDevice(plans[0]->device));

@@ -35,22 +35,37 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
   return start + i;
 }
 
-// AR extension rule along one axis, branch-free: position i of an axis of
-// length n maps to w0 * f[i0] + w1 * f[i1]: interior (i, 1) + (i, 0);
-// before the start (0, 2) + (-i, -1) (f_{1-t} = 2 f_1 - f_{1+t}); past the
-// end (n-1, 2) + (2n-2-i, -1) (f_{n+t} = 2 f_n - f_{n-t}).  `dead` marks
-// positions that no stored output consumes (more than q outside) or, with
-// zero extension, any position outside the image; they read exactly 0.
+// Extension modes of the halo loader: the plan's boundary conditions, or
+// zero outside the image (the correlation half of A^T).
+enum ExtMode { EXT_AR = 0, EXT_ZERO = 1, EXT_REFLECT = 2, EXT_PERIODIC = 3 };
+
+// Extension rule along one axis, branch-free: position i of an axis of
+// length n maps to w0 * f[i0] + w1 * f[i1].  AR (Sec. 2.2): interior
+// (i, 1) + (i, 0); before the start (0, 2) + (-i, -1)
+// (f_{1-t} = 2 f_1 - f_{1+t}); past the end (n-1, 2) + (2n-2-i, -1)
+// (f_{n+t} = 2 f_n - f_{n-t}).  Reflective (Sec. 2.1): f_{1-t} = f_t and
+// f_{n+t} = f_{n+1-t}, one term.  Periodic: wrap-around, one term.  `dead`
+// marks positions that no stored output consumes (more than q outside) or,
+// with zero extension, any position outside the image; they read exactly 0.
 struct Rule { int i0, i1; float w0, w1; bool dead; };
 
-__device__ __forceinline__ Rule ar_rule(int i, int n, int q, bool zero_ext) {
+__device__ __forceinline__ Rule ar_rule(int i, int n, int q, int mode) {
   Rule r;
   const bool lo = i < 0, hi = i > n - 1;
-  r.dead = (i < -q) | (i > n - 1 + q) | (zero_ext & (lo | hi));
-  r.i0 = lo ? 0 : (hi ? n - 1 : i);
-  r.i1 = lo ? -i : (hi ? 2 * n - 2 - i : i);
-  r.w0 = (lo | hi) ? 2.f : 1.f;
-  r.w1 = (lo | hi) ? -1.f : 0.f;
+  r.dead = (i < -q) | (i > n - 1 + q) | ((mode == EXT_ZERO) & (lo | hi));
+  if (mode == EXT_REFLECT || mode == EXT_PERIODIC) {
+    const int jl = mode == EXT_REFLECT ? -i - 1 : i + n;
+    const int jh = mode == EXT_REFLECT ? 2 * n - 1 - i : i - n;
+    r.i0 = lo ? jl : (hi ? jh : i);
+    r.i1 = r.i0;
+    r.w0 = 1.f;
+    r.w1 = 0.f;
+  } else {
+    r.i0 = lo ? 0 : (hi ? n - 1 : i);
+    r.i1 = lo ? -i : (hi ? 2 * n - 2 - i : i);
+    r.w0 = (lo | hi) ? 2.f : 1.f;
+    r.w1 = (lo | hi) ? -1.f : 0.f;
+  }
   // keep every address inside the image (the value is discarded when dead)
   r.i0 = r.i0 < 0 ? 0 : (r.i0 > n - 1 ? n - 1 : r.i0);
   r.i1 = r.i1 < 0 ? 0 : (r.i1 > n - 1 ? n - 1 : r.i1);
@@ -63,8 +78,8 @@ __device__ __forceinline__ Rule ar_rule(int i, int n, int q, bool zero_ext) {
 // All four loads are unconditional so a caller can batch them.
 template <typename T, typename TS>
 __device__ __forceinline__ T load_ext(const Gl<TS> *__restrict__ in, int n1, int n2, int q1,
-                                      int q2, int i, int j, bool zero_ext) {
-  const Rule a = ar_rule(i, n1, q1, zero_ext), b = ar_rule(j, n2, q2, zero_ext);
+                                      int q2, int i, int j, int mode) {
+  const Rule a = ar_rule(i, n1, q1, mode), b = ar_rule(j, n2, q2, mode);
   const T x00 = T(in[(size_t)a.i0 * n2 + b.i0]);
   const T x01 = T(in[(size_t)a.i0 * n2 + b.i1]);
   const T x10 = T(in[(size_t)a.i1 * n2 + b.i0]);
@@ -108,7 +123,7 @@ template <typename TS, typename T, typename TO, int Q2>
 __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__restrict__ in,
                                           TO *__restrict__ out, const T *__restrict__ w, int n1,
                                           int n2, int q1, int q2rt, int o1, int o2, int m1, int m2,
-                                          int zero_ext, const TS *__restrict__ gsub,
+                                          int ext_mode, const TS *__restrict__ gsub,
                                           double *__restrict__ partial_slot, int logical,
                                           int tiles_x) {
   constexpr bool GEN = Q2 < 0;
@@ -164,7 +179,7 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
 #pragma unroll
           for (int j = 0; j < CC; ++j)
             vals[i][j] = load_ext<T, TS>(gin, n1, n2, q1, q2, ib1 + a0 + 4 * i, ib2 + c0 + 64 * j,
-                                         zero_ext != 0);
+                                         ext_mode);
       }
 #pragma unroll
       for (int i = 0; i < CR; ++i)
@@ -407,7 +422,10 @@ hipError_t launch_conv_t(const ar_plan_s *p, const void *in, void *out, const vo
   TO *to = static_cast<TO *>(out);
   const T *tw = static_cast<const T *>(w);
   const TS *tg = static_cast<const TS *>(g);
-  const int ze = zero_ext ? 1 : 0;
+  const int ze = zero_ext ? EXT_ZERO
+                          : (p->bc == AR_BC_REFLECTIVE ? EXT_REFLECT
+                                                       : (p->bc == AR_BC_PERIODIC ? EXT_PERIODIC
+                                                                                  : EXT_AR));
 #define AR_CONV_CASE(QQ)                                                                      \
   case QQ:                                                                                    \
     hipLaunchKernelGGL((conv_kernel<TS, T, TO, QQ>), dim3(blocks), dim3(NT), smem, st, ti, to, \
@@ -569,6 +587,8 @@ extern "C" int ar_blur_apply_T(ar_plan_t p, const void *r, void *y, int tmode, v
     return conv_launch(p, r, y, p->w_rev, 0, 0, p->n1, p->n2, false, nullptr, nullptr, nullptr,
                        st, false);
   if (tmode == AR_ADJOINT) {
+    if (p->bc != AR_BC_ANTIREFLECTIVE)
+      return fail(AR_EUNSUPPORTED, "ar_blur_apply_T: the exact transpose is Anti-Reflective only");
     int rc = conv_launch(p, r, p->ext, p->w_rev, -p->q1, -p->q2, p->n1 + 2 * p->q1,
                          p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st, true);
     if (rc != AR_OK) return rc;

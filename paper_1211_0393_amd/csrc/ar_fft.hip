@@ -22,130 +22,12 @@
 
 #include "ar_codelets.h"
 #include "ar_internal.h"
+#include "ar_stockham.h"
 
 namespace ar {
 namespace {
 
 using namespace cl;
-
-// ------------------------------------------------------------ FFT stages
-
-// Element t of sequence s lives at buf[s * ss + t * es].
-struct Layout {
-  int nseq, ss, es;
-  bool seq_fast;  // thread index -> (s fastest) or (t fastest)
-};
-
-template <typename T, int R>
-__device__ __forceinline__ void stage_fixed(const V2<T> *__restrict__ src, V2<T> *__restrict__ dst,
-                                            int M, int Ns, const V2<T> *__restrict__ tw,
-                                            const Layout L) {
-  const int nb = M / R;
-  const int total = nb * L.nseq;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int s, j;
-    if (L.seq_fast) {
-      j = idx / L.nseq;
-      s = idx - j * L.nseq;
-    } else {
-      s = idx / nb;
-      j = idx - s * nb;
-    }
-    const V2<T> *a = src + s * L.ss;
-    V2<T> *b = dst + s * L.ss;
-    const int k = j % Ns;
-    V2<T> v[R];
-    static_for<R>([&](auto r) { v[r] = a[(j + r * nb) * L.es]; });
-    if (Ns > 1) {
-      const V2<T> *t = tw + k * R;
-      static_for<R - 1>([&](auto r) { v[r + 1] = cmul(v[r + 1], t[r + 1]); });
-    }
-    dft<R, T>(v);
-    const int base = (j - k) * R + k;
-    static_for<R>([&](auto r) { b[(base + r * Ns) * L.es] = v[r]; });
-  }
-}
-
-// Radix without a codelet: twiddle in place, then each output is an O(R)
-// sum over the butterfly's inputs with the roots e^{-2 pi i t / R}.
-template <typename T>
-__device__ void stage_generic(V2<T> *__restrict__ src, V2<T> *__restrict__ dst, int M, int R,
-                              int Ns, const V2<T> *__restrict__ tw,
-                              const V2<T> *__restrict__ roots, const Layout L) {
-  const int nb = M / R;
-  const int total = M * L.nseq;
-  if (Ns > 1) {
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-      int s, t;
-      if (L.seq_fast) {
-        t = idx / L.nseq;
-        s = idx - t * L.nseq;
-      } else {
-        s = idx / M;
-        t = idx - s * M;
-      }
-      const int r = t / nb, j = t - r * nb, k = j % Ns;
-      if (r == 0) continue;
-      V2<T> &e = src[s * L.ss + t * L.es];
-      e = cmul(e, tw[k * R + r]);
-    }
-    __syncthreads();
-  }
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int s, o;
-    if (L.seq_fast) {
-      o = idx / L.nseq;
-      s = idx - o * L.nseq;
-    } else {
-      s = idx / M;
-      o = idx - s * M;
-    }
-    const int ro = o / nb, j = o - ro * nb, k = j % Ns;
-    const V2<T> *a = src + s * L.ss;
-    V2<T> acc{T(0), T(0)};
-    int e = 0;
-    for (int r = 0; r < R; ++r) {
-      const V2<T> x = a[(j + r * nb) * L.es];
-      const V2<T> w = roots[e];
-      acc.x = fma(x.x, w.x, fma(-x.y, w.y, acc.x));
-      acc.y = fma(x.x, w.y, fma(x.y, w.x, acc.y));
-      e += ro;
-      if (e >= R) e -= R;
-    }
-    dst[s * L.ss + ((j - k) * R + k + ro * Ns) * L.es] = acc;
-  }
-}
-
-// Runs all stages; returns the buffer holding the result.
-template <typename T>
-__device__ V2<T> *fft_run(V2<T> *A, V2<T> *B, const FftDesc &fd, const V2<T> *__restrict__ tw,
-                          const V2<T> *__restrict__ gen, const Layout L) {
-  const int M = fd.M;
-  for (int st = 0; st < fd.nstages; ++st) {
-    const int R = fd.radix[st], Ns = fd.ns[st];
-    const V2<T> *t = tw + fd.tw_off[st];
-    switch (R) {
-      case 2: stage_fixed<T, 2>(A, B, M, Ns, t, L); break;
-      case 3: stage_fixed<T, 3>(A, B, M, Ns, t, L); break;
-      case 4: stage_fixed<T, 4>(A, B, M, Ns, t, L); break;
-      case 5: stage_fixed<T, 5>(A, B, M, Ns, t, L); break;
-      case 7: stage_fixed<T, 7>(A, B, M, Ns, t, L); break;
-      case 11: stage_fixed<T, 11>(A, B, M, Ns, t, L); break;
-      case 13: stage_fixed<T, 13>(A, B, M, Ns, t, L); break;
-      case 17: stage_fixed<T, 17>(A, B, M, Ns, t, L); break;
-      case 19: stage_fixed<T, 19>(A, B, M, Ns, t, L); break;
-      case 23: stage_fixed<T, 23>(A, B, M, Ns, t, L); break;
-      case 29: stage_fixed<T, 29>(A, B, M, Ns, t, L); break;
-      case 31: stage_fixed<T, 31>(A, B, M, Ns, t, L); break;
-      default: stage_generic<T>(A, B, M, R, Ns, t, gen + fd.gen_off[st], L); break;
-    }
-    __syncthreads();
-    V2<T> *tmp = A;
-    A = B;
-    B = tmp;
-  }
-  return A;
-}
 
 // u_t = z_{2t} + i z_{2t+1} from the real interior x_1..x_N held in `re`
 // (x_j at re[s*rss + j*res], j = 1..N; the endpoints are ignored).  When
@@ -407,47 +289,6 @@ __global__ void tables_kernel(V2<T> *tw, const int *tw_ns, const int *tw_r, cons
   }
 }
 
-FftDesc make_desc(const FftPlan &fp) {
-  FftDesc d{};
-  d.M = fp.M;
-  d.nstages = fp.nstages;
-  for (int s = 0; s < kMaxStages; ++s) {
-    d.radix[s] = fp.radix[s];
-    d.ns[s] = fp.ns[s];
-    d.tw_off[s] = fp.tw_off[s];
-    d.gen_off[s] = fp.gen_off[s];
-  }
-  return d;
-}
-
-// Rows (columns) per workgroup: enough sequences to give 256 threads work,
-// within 63 KiB of LDS when possible; a single long sequence may use up to
-// kMaxLds (gfx950 has 160 KiB of LDS per CU).
-constexpr size_t kLdsSoft = 63 * 1024, kMaxLds = 150 * 1024;
-int seqs_per_block(int M, size_t csize, int target) {
-  const size_t cplx = 2 * csize;
-  int B = target / (M > 0 ? M : 1);
-  if (B < 1) B = 1;
-  if (B > 64) B = 64;
-  while (B > 1 && 2 * (size_t)B * M * cplx > kLdsSoft) --B;
-  return B;
-}
-int rows_per_block(int M, size_t csize) { return seqs_per_block(M, csize, 2048); }
-int cols_per_block(int M, size_t csize) { return seqs_per_block(M, csize, 4096); }
-
-size_t seq_lds_bytes(int B, int M, size_t csize) {
-  return 2 * (size_t)B * M * 2 * csize + 2 * (size_t)B * csize + 64;
-}
-
-// Raise the dynamic LDS limit of a kernel once when a launch needs more
-// than the default 64 KiB.
-template <typename K>
-hipError_t allow_lds(K kernel, size_t bytes) {
-  if (bytes <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
 }  // namespace
 
 bool radix_has_codelet(int r) {
@@ -541,6 +382,7 @@ void fft_plan_free(FftPlan &fp) {
 }
 
 int rows_blocks(const ar_plan_s *p) {
+  if (p->bc != AR_BC_ANTIREFLECTIVE) return bc_rows_blocks(p);
   if (p->dtype == AR_F32_BF16X3) return dense_blocks(p);
   if (wave_rows_ok(p)) return wave_rows_blocks(p);
   const int B = rows_per_block(p->fft_row.M, p->csize);
@@ -592,6 +434,8 @@ static int rows_launch_t(const ar_plan_s *p, const void *in, void *out, int mode
 int rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                 const void *f_true, double *partial, int *nblocks_out, hipStream_t st) {
   if (nblocks_out) *nblocks_out = rows_blocks(p);
+  if (p->bc != AR_BC_ANTIREFLECTIVE)
+    return bc_rows_launch(p, in, out, mode, tau, f_true, partial, st);
   if (p->dtype == AR_F32_BF16X3)
     return dense_rows_launch(p, in, out, mode, tau, f_true, partial, st);
   if (wave_rows_ok(p)) return wave_rows_launch(p, in, out, mode, tau, f_true, partial, st);
@@ -639,6 +483,7 @@ static int cols_launch_t(const ar_plan_s *p, const void *in, void *out, int mode
 }
 
 int cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
+  if (p->bc != AR_BC_ANTIREFLECTIVE) return bc_cols_launch(p, in, out, mode, st);
   if (p->dtype == AR_F32_BF16X3) return dense_cols_launch(p, in, out, mode, st);
   if (wave_cols_ok(p)) return wave_cols_launch(p, in, out, mode, st);
   if (p->dtype == AR_F64) return cols_launch_t<double, double>(p, in, out, mode, st);
@@ -652,6 +497,8 @@ using namespace ar;
 
 extern "C" int ar_transform(ar_plan_t p, const void *x, void *c, void *stream) {
   if (!p || !x || !c) return fail(AR_EINVAL, "ar_transform: null argument");
+  if (p->bc == AR_BC_PERIODIC)
+    return fail(AR_EUNSUPPORTED, "ar_transform: periodic plans have complex coefficients");
   AR_HIP(hipSetDevice(p->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = rows_launch(p, x, c, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
@@ -661,6 +508,8 @@ extern "C" int ar_transform(ar_plan_t p, const void *x, void *c, void *stream) {
 
 extern "C" int ar_transform_inv(ar_plan_t p, const void *c, void *x, void *stream) {
   if (!p || !x || !c) return fail(AR_EINVAL, "ar_transform_inv: null argument");
+  if (p->bc == AR_BC_PERIODIC)
+    return fail(AR_EUNSUPPORTED, "ar_transform_inv: periodic plans have complex coefficients");
   AR_HIP(hipSetDevice(p->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = cols_launch(p, c, x, COL_INV, st);
@@ -672,11 +521,14 @@ extern "C" int ar_precond_solve(ar_plan_t p, const void *y, void *z, void *strea
   if (!p || !y || !z) return fail(AR_EINVAL, "ar_precond_solve: null argument");
   AR_HIP(hipSetDevice(p->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int rc = rows_launch(p, y, z, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
+  // Anti-Reflective and Reflective coefficients fit z (in place); periodic
+  // half spectra are wider than an image and go through the plan's buffer
+  void *w = p->bc == AR_BC_PERIODIC ? p->c : z;
+  int rc = rows_launch(p, y, w, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st);
   if (rc != AR_OK) return rc;
-  rc = cols_launch(p, z, z, COL_FWD_D_INV, st);
+  rc = cols_launch(p, w, w, COL_FWD_D_INV, st);
   if (rc != AR_OK) return rc;
-  return rows_launch(p, z, z, ROW_INV, 0.0, nullptr, nullptr, nullptr, st);
+  return rows_launch(p, w, z, ROW_INV, 0.0, nullptr, nullptr, nullptr, st);
 }
 
 extern "C" int ar_tikhonov_solve(ar_plan_t p, const void *g, void *x, double alpha,
@@ -684,6 +536,9 @@ extern "C" int ar_tikhonov_solve(ar_plan_t p, const void *g, void *x, double alp
   if (!p || !g || !x) return fail(AR_EINVAL, "ar_tikhonov_solve: null argument");
   if (!(alpha > 0.0 && std::isfinite(alpha)))
     return fail(AR_EINVAL, "ar_tikhonov_solve: alpha must be finite and > 0");
+  if (p->bc == AR_BC_PERIODIC)
+    return fail(AR_EUNSUPPORTED, "ar_tikhonov_solve: defined for Anti-Reflective and Reflective "
+                                 "plans");
   if (!p->strong_sym)
     return fail(AR_EPSF, "ar_tikhonov_solve: the direct solve needs a strongly symmetric PSF "
                          "(h_{-s1,s2} = h_{s1,-s2} = h_{s1,s2})");

@@ -155,6 +155,12 @@ struct ar_plan_s {
   int q1cap = 0, q2cap = 0;    // half-widths the PSF buffers were sized for
   bool strong_sym = false;     // h_{|s1|,|s2|} = h_{s1,s2} (then P(s) = A and the
                                // eigenvalues lambda are those of A itself)
+  // boundary conditions (ar_bc); Reflective and Periodic plans run their
+  // preconditioner through FFT plans of length n and the DCT twiddles
+  // e^{-i pi k/(2n)} (compute type) of each axis
+  int bc = AR_BC_ANTIREFLECTIVE;
+  ar::FftPlan bc_fft_row, bc_fft_col;
+  void *bc_e2_row = nullptr, *bc_e2_col = nullptr;
   float *gains = nullptr;      // last gains of AR_FILTER_GAINS (64 floats)
   void *lscr = nullptr;        // scratch of the learned-filter kernels
 };
@@ -248,6 +254,19 @@ int wave_rows_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, i
                            double tau, int k, hipStream_t st);
 int wave_cols_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, int mode,
                            hipStream_t st);
+
+// Reflective (DCT) and Periodic (DFT) preconditioner passes (ar_bc.hip);
+// the row and column passes take the modes of the AR passes (a periodic
+// plan's column pass only COL_FWD_D_INV, its coefficients being the
+// complex half spectra of the rows, bc_coef_elems storage elements)
+int bc_setup(ar_plan_s *p, hipStream_t st);
+void bc_free(ar_plan_s *p);
+int bc_rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
+                   const void *f_true, double *partial, hipStream_t st);
+int bc_cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st);
+int bc_rows_blocks(const ar_plan_s *p);
+size_t bc_coef_elems(int bc, int n1, int n2);
+int bc_max_axis_len(size_t csize);
 
 // dense BF16x3 MFMA transforms of AR_F32_BF16X3 plans (ar_dense.hip)
 int dense_setup(ar_plan_s *p, hipStream_t st);

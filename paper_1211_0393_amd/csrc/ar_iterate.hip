@@ -138,6 +138,8 @@ int check_args(const char *who, ar_plan_t p, const void *g, void *x, int iters, 
   if (!p || !g || !x) return fail(AR_EINVAL, w + ": null argument");
   if (iters < 0) return fail(AR_EINVAL, w + ": iters < 0");
   if (tmode != AR_REBLUR && tmode != AR_ADJOINT) return fail(AR_EINVAL, w + ": unknown tmode");
+  if (tmode == AR_ADJOINT && p->bc != AR_BC_ANTIREFLECTIVE)
+    return fail(AR_EUNSUPPORTED, w + ": the exact transpose is Anti-Reflective only");
   if (!std::isfinite(tau)) return fail(AR_EINVAL, w + ": tau must be finite");
   if (g == x || (f_true && (f_true == x || f_true == g)))
     return fail(AR_EALIAS, w + ": g, x and f_true must not alias");

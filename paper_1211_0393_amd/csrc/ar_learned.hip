@@ -496,6 +496,8 @@ using namespace ar;
 
 extern "C" int ar_features(ar_plan_t p, const void *g, float *feat_dev, void *stream) {
   if (!p || !g || !feat_dev) return fail(AR_EINVAL, "ar_features: null argument");
+  if (p->bc != AR_BC_ANTIREFLECTIVE)
+    return fail(AR_EUNSUPPORTED, "ar_features: the learned filter is Anti-Reflective only");
   AR_HIP(hipSetDevice(p->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = ensure_lscr(p);
@@ -538,6 +540,8 @@ extern "C" int ar_features(ar_plan_t p, const void *g, float *feat_dev, void *st
 
 extern "C" int ar_precond_set_gains(ar_plan_t p, const float *gains_dev, void *stream) {
   if (!p || !gains_dev) return fail(AR_EINVAL, "ar_precond_set_gains: null argument");
+  if (p->bc != AR_BC_ANTIREFLECTIVE)
+    return fail(AR_EUNSUPPORTED, "ar_precond_set_gains: the learned filter is Anti-Reflective only");
   AR_HIP(hipSetDevice(p->device));
   return gains_filter_launch(p, gains_dev, static_cast<hipStream_t>(stream));
 }

@@ -48,9 +48,15 @@ __global__ void psf_prep_kernel(const double *__restrict__ H, double *__restrict
   }
 }
 
-// cos(a x_k) for the AR grid of an axis of length n: x_0 = x_{n-1} = 0 and
-// x_k = k pi/(n-1) otherwise (Theorem 2 and the extended grid after it).
-__device__ __forceinline__ double grid_cos(int a, int k, int n) {
+// cos(a x_k) on the eigenvalue grid of an axis of length n.  AR (Theorem 2
+// and the extended grid after it): x_0 = x_{n-1} = 0 and x_k = k pi/(n-1)
+// otherwise.  Reflective (Sec. 2.1, the DCT-III algebra): x_k = k pi / n.
+__device__ __forceinline__ double grid_cos(int a, int k, int n, int bc) {
+  if (bc == AR_BC_REFLECTIVE) {
+    if (a == 0 || k == 0) return 1.0;
+    const long num = ((long)a * k) % (2L * n);  // cos(pi num / n)
+    return cospi((double)num / (double)n);
+  }
   if (k == 0 || k == n - 1 || a == 0) return 1.0;
   const long period = 2L * (n - 1);
   const long num = ((long)a * k) % period;  // cos(pi num / (n-1))
@@ -60,28 +66,77 @@ __device__ __forceinline__ double grid_cos(int a, int k, int n) {
 // Cq[a][k2] = w_b-weighted sum over b >= 0 of s[a][b] cos(b x_{k2}),
 // w_0 = 1, w_b = 2: the inner sum of eq. (funzione_generatrice).
 __global__ void symbol_inner_kernel(const double *__restrict__ S, double *__restrict__ Cq,
-                                    int q1, int q2, int n2) {
+                                    int q1, int q2, int n2, int bc) {
   const int K2 = 2 * q2 + 1;
   const int total = (q1 + 1) * n2;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
     const int a = e / n2, k2 = e - a * n2;
     const double *row = S + (size_t)(q1 + a) * K2 + q2;
     double acc = row[0];
-    for (int b = 1; b <= q2; ++b) acc = fma(2.0 * row[b], grid_cos(b, k2, n2), acc);
+    for (int b = 1; b <= q2; ++b) acc = fma(2.0 * row[b], grid_cos(b, k2, n2, bc), acc);
     Cq[e] = acc;
   }
 }
 
 // lambda[k1][k2] = sum_a w_a cos(a x_{k1}) Cq[a][k2]  (FP64)
 __global__ void symbol_outer_kernel(const double *__restrict__ Cq, double *__restrict__ lam,
-                                    int q1, int n1, int n2) {
+                                    int q1, int n1, int n2, int bc) {
   const size_t total = (size_t)n1 * n2;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
     const int k1 = (int)(e / n2), k2 = (int)(e - (size_t)k1 * n2);
     double acc = Cq[k2];
-    for (int a = 1; a <= q1; ++a) acc = fma(2.0 * grid_cos(a, k1, n1), Cq[(size_t)a * n2 + k2], acc);
+    for (int a = 1; a <= q1; ++a)
+      acc = fma(2.0 * grid_cos(a, k1, n1, bc), Cq[(size_t)a * n2 + k2], acc);
     lam[e] = acc;
+  }
+}
+
+// Periodic BCs: lambda[k1][k2] = sum_s h_s e^{-2 pi i (k1 s1 / n1 + k2 s2 / n2)}
+// (the DFT of the PSF itself, Sec. 4), separably: Cp[a][k2] (complex) over
+// s2, then the sum over s1; the plan keeps |lambda| (the filters need only
+// the modulus).  Angles are reduced exactly in integers.
+__device__ __forceinline__ void unit_root(long num, int n, double *c, double *sn) {
+  sincospi(-2.0 * (double)(num % n) / (double)n, sn, c);
+}
+
+__global__ void psymbol_inner_kernel(const double *__restrict__ H, double *__restrict__ Cp,
+                                     int q1, int q2, int n2) {
+  const int K1 = 2 * q1 + 1, K2 = 2 * q2 + 1;
+  const int total = K1 * n2;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int a = e / n2, k2 = e - a * n2;
+    double re = 0.0, im = 0.0;
+    for (int b = 0; b < K2; ++b) {
+      const long s2 = b - q2;
+      double c, sn;
+      unit_root((long)k2 * (s2 + n2), n2, &c, &sn);
+      const double h = H[a * K2 + b];
+      re = fma(h, c, re);
+      im = fma(h, sn, im);
+    }
+    Cp[2 * (size_t)e] = re;
+    Cp[2 * (size_t)e + 1] = im;
+  }
+}
+
+__global__ void psymbol_outer_kernel(const double *__restrict__ Cp, double *__restrict__ lam,
+                                     int q1, int n1, int n2) {
+  const int K1 = 2 * q1 + 1;
+  const size_t total = (size_t)n1 * n2;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int k1 = (int)(e / n2), k2 = (int)(e - (size_t)k1 * n2);
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < K1; ++a) {
+      const long s1 = a - q1;
+      double c, sn;
+      unit_root((long)k1 * (s1 + n1), n1, &c, &sn);
+      const double xr = Cp[2 * ((size_t)a * n2 + k2)], xi = Cp[2 * ((size_t)a * n2 + k2) + 1];
+      re = fma(c, xr, fma(-sn, xi, re));
+      im = fma(c, xi, fma(sn, xr, im));
+    }
+    lam[e] = sqrt(re * re + im * im);
   }
 }
 
@@ -236,12 +291,21 @@ int spectrum_launch(ar_plan_s *p, hipStream_t st) {
                        p->q2);
   AR_HIP(hipGetLastError());
   double *Cq = nullptr;
-  AR_HIP(hipMalloc((void **)&Cq, (size_t)(p->q1 + 1) * p->n2 * sizeof(double)));
-  hipLaunchKernelGGL(symbol_inner_kernel, dim3(64), dim3(256), 0, st, p->S64, Cq, p->q1, p->q2,
-                     p->n2);
-  AR_HIP(hipGetLastError());
-  hipLaunchKernelGGL(symbol_outer_kernel, dim3(1024), dim3(256), 0, st, Cq, p->lambda, p->q1,
-                     p->n1, p->n2);
+  if (p->bc == AR_BC_PERIODIC) {
+    AR_HIP(hipMalloc((void **)&Cq, 2 * (size_t)(2 * p->q1 + 1) * p->n2 * sizeof(double)));
+    hipLaunchKernelGGL(psymbol_inner_kernel, dim3(64), dim3(256), 0, st, p->H64, Cq, p->q1,
+                       p->q2, p->n2);
+    AR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(psymbol_outer_kernel, dim3(1024), dim3(256), 0, st, Cq, p->lambda, p->q1,
+                       p->n1, p->n2);
+  } else {
+    AR_HIP(hipMalloc((void **)&Cq, (size_t)(p->q1 + 1) * p->n2 * sizeof(double)));
+    hipLaunchKernelGGL(symbol_inner_kernel, dim3(64), dim3(256), 0, st, p->S64, Cq, p->q1,
+                       p->q2, p->n2, p->bc);
+    AR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(symbol_outer_kernel, dim3(1024), dim3(256), 0, st, Cq, p->lambda, p->q1,
+                       p->n1, p->n2, p->bc);
+  }
   AR_HIP(hipGetLastError());
   AR_HIP(hipStreamSynchronize(st));
   AR_HIP(hipFree(Cq));
@@ -428,23 +492,34 @@ static void plan_free(ar_plan_s *p) {
   fft_plan_free(p->fft_row);
   fft_plan_free(p->fft_col);
   fft_plan_free(p->fft_row32);
+  bc_free(p);
   delete p;
 }
 
 extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_host, int q1,
                               int q2, int dtype, int device) {
+  return ar_plan_create_bc(out, n1, n2, psf_host, q1, q2, dtype, AR_BC_ANTIREFLECTIVE, device);
+}
+
+extern "C" int ar_plan_create_bc(ar_plan_t *out, int n1, int n2, const double *psf_host, int q1,
+                                 int q2, int dtype, int bc, int device) {
   if (!out) return fail(AR_EINVAL, "ar_plan_create: out is NULL");
   *out = nullptr;
   if (!psf_host) return fail(AR_EINVAL, "ar_plan_create: psf is NULL");
   if (dtype != AR_F32 && dtype != AR_F64 && dtype != AR_F32_ACC64 && dtype != AR_F32_BF16X3)
     return fail(AR_EINVAL, "ar_plan_create: bad dtype");
+  if (bc != AR_BC_ANTIREFLECTIVE && bc != AR_BC_REFLECTIVE && bc != AR_BC_PERIODIC)
+    return fail(AR_EINVAL, "ar_plan_create: unknown boundary conditions");
+  if (bc != AR_BC_ANTIREFLECTIVE && dtype == AR_F32_BF16X3)
+    return fail(AR_EUNSUPPORTED, "ar_plan_create: dense BF16x3 transforms are Anti-Reflective only");
   const size_t esize = dtype == AR_F64 ? 8 : 4;
   const size_t csize = (dtype == AR_F32 || dtype == AR_F32_BF16X3) ? 4 : 8;
   if (q1 < 0 || q2 < 0) return fail(AR_ESHAPE, "ar_plan_create: negative PSF half-width");
   if (n1 < 3 || n2 < 3) return fail(AR_ESHAPE, "ar_plan_create: need n1, n2 >= 3");
   if (q1 > n1 - 3 || q2 > n2 - 3)
     return fail(AR_ESHAPE, "ar_plan_create: AR algebra needs q_j <= n_j - 3");
-  if (n1 > max_axis_len(csize) || n2 > max_axis_len(csize))
+  const int maxlen = bc == AR_BC_ANTIREFLECTIVE ? max_axis_len(csize) : bc_max_axis_len(csize);
+  if (n1 > maxlen || n2 > maxlen)
     return fail(AR_ESHAPE, "ar_plan_create: axis longer than the LDS-resident transform supports");
   const int K1 = 2 * q1 + 1, K2 = 2 * q2 + 1, P = K1 * K2;
   double sum = 0.0;
@@ -470,6 +545,7 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
   p->dtype = dtype;
   p->device = device;
   p->strong_sym = psf_strongly_symmetric(psf_host, q1, q2);
+  p->bc = bc;
   p->esize = esize;
   p->csize = csize;
   const size_t npx = (size_t)n1 * n2;
@@ -489,7 +565,8 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
             alloc((void **)&p->d64, npx * sizeof(double)) && alloc(&p->d, npx * p->csize) &&
             alloc(&p->dT, npx * p->esize) &&
             alloc(&p->r, npx * p->esize) && alloc(&p->y, npx * p->esize) &&
-            alloc(&p->c, npx * p->esize) && alloc(&p->ext, next * p->csize);
+            alloc(&p->c, bc_coef_elems(bc, n1, n2) * p->esize) &&
+            alloc(&p->ext, std::max(next * p->csize, bc_coef_elems(bc, n1, n2) * p->esize));
   if (!ok) {
     plan_free(p);
     return rc;
@@ -501,10 +578,12 @@ extern "C" int ar_plan_create(ar_plan_t *out, int n1, int n2, const double *psf_
     plan_free(p);
     return rc;
   }
+  const bool ar = bc == AR_BC_ANTIREFLECTIVE;
   if ((rc = spectrum_launch(p, st)) != AR_OK || (rc = filter_launch(p, AR_FILTER_TIKHONOV, 1e-2, st)) != AR_OK ||
-      (rc = fft_plan_build(p->fft_row, n2, csize == 8, st)) != AR_OK ||
-      (rc = fft_plan_build(p->fft_col, n1, csize == 8, st)) != AR_OK ||
-      (dtype == AR_F32_ACC64 && (rc = fft_plan_build(p->fft_row32, n2, false, st)) != AR_OK) ||
+      (ar && (rc = fft_plan_build(p->fft_row, n2, csize == 8, st)) != AR_OK) ||
+      (ar && (rc = fft_plan_build(p->fft_col, n1, csize == 8, st)) != AR_OK) ||
+      (ar && dtype == AR_F32_ACC64 && (rc = fft_plan_build(p->fft_row32, n2, false, st)) != AR_OK) ||
+      (!ar && (rc = bc_setup(p, st)) != AR_OK) ||
       (dtype == AR_F32_BF16X3 && (rc = dense_setup(p, st)) != AR_OK)) {
     plan_free(p);
     return rc;
@@ -565,6 +644,8 @@ extern "C" int ar_precond_set(ar_plan_t p, int filter, double param, const float
   if (!p) return fail(AR_EINVAL, "ar_precond_set: null plan");
   if (filter == AR_FILTER_GAINS) {
     if (!gains_dev) return fail(AR_EINVAL, "ar_precond_set: the gains filter needs gains");
+    if (p->bc != AR_BC_ANTIREFLECTIVE)
+      return fail(AR_EUNSUPPORTED, "ar_precond_set: the learned filter is Anti-Reflective only");
     AR_HIP(hipSetDevice(p->device));
     return gains_filter_launch(p, gains_dev, static_cast<hipStream_t>(stream));
   }

@@ -33,6 +33,8 @@ static bool tune_valid(int key, int value) {
 
 extern "C" int ar_plan_tune(ar_plan_t p, int key, int value) {
   if (!p) return fail(AR_EINVAL, "ar_plan_tune: null plan");
+  if (p->bc != AR_BC_ANTIREFLECTIVE)
+    return fail(AR_EUNSUPPORTED, "ar_plan_tune: tunables are Anti-Reflective only");
   if (!tune_valid(key, value)) return fail(AR_EINVAL, "ar_plan_tune: bad key or value");
   p->tune[key] = value;
   return AR_OK;
@@ -73,6 +75,8 @@ int time_us(F &&fn, hipStream_t st, int reps, double *us) {
 
 extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
   if (!p) return fail(AR_EINVAL, "ar_plan_autotune: null plan");
+  if (p->bc != AR_BC_ANTIREFLECTIVE)
+    return fail(AR_EUNSUPPORTED, "ar_plan_autotune: tunables are Anti-Reflective only");
   AR_HIP(hipSetDevice(p->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   // The unit timed for every candidate is a short run of whole
@@ -141,6 +145,8 @@ extern "C" int ar_iterate_profile(ar_plan_t p, const void *g, const void *x, int
   if (reps < 1) return fail(AR_EINVAL, "ar_iterate_profile: reps < 1");
   if (tmode != AR_REBLUR && tmode != AR_ADJOINT)
     return fail(AR_EINVAL, "ar_iterate_profile: unknown tmode");
+  if (tmode == AR_ADJOINT && p->bc != AR_BC_ANTIREFLECTIVE)
+    return fail(AR_EUNSUPPORTED, "ar_iterate_profile: the exact transpose is Anti-Reflective only");
   AR_HIP(hipSetDevice(p->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t bytes = (size_t)p->n1 * p->n2 * p->esize;
@@ -168,8 +174,11 @@ extern "C" int ar_iterate_profile(ar_plan_t p, const void *g, const void *x, int
       case 2:
         return precondition ? rows_launch(p, p->y, p->c, ROW_FWD, 0.0, nullptr, nullptr, nullptr, st)
                             : AR_OK;
-      case 3:  // out of place into r (free after the transpose blur)
-        return precondition ? cols_launch(p, p->c, p->r, COL_FWD_D_INV, st) : AR_OK;
+      case 3:  // out of place into r (free after the transpose blur); a periodic
+               // plan's half spectra need the wider ext buffer
+        return precondition ? cols_launch(p, p->c, p->bc == AR_BC_PERIODIC ? p->ext : p->r,
+                                          COL_FWD_D_INV, st)
+                            : AR_OK;
       default:
         return precondition
                    ? rows_launch(p, p->c, xw, ROW_INV_UPDATE, 1.0, nullptr, nullptr, nullptr, st)

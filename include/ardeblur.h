@@ -221,6 +221,25 @@ int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters, double tau
                       double *resnorm_host, double *rre_host, int *best_it_host,
                       void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * iteration and outputs as ar_deblur_iterate (the same kernels, so x and
+ * the scalars are bitwise equal), with no hipMalloc, hipFree or other
+ * allocation in the call.  Its partial sums and reduced scalars live in a
+ * static device buffer of 2 MiB (262144 doubles) that each GPU the library
+ * runs on holds until the process ends; a run with scalars requested needs
+ * iters * (residual + update partials) + 2 iters + 1 doubles of it (at
+ * 1024 x 1024 about 770 per iteration, so up to ~340 iterations per call).
+ * Differences from ar_deblur_iterate: best_it_host needs rre_host (the call
+ * keeps no host buffer of its own); sizes beyond the buffer return
+ * AR_EINVAL before any device work.  Calls that overlap on one GPU share the
+ * buffer and race: order them on one stream.  The plan's own scratch (r, y,
+ * c) is allocated by ar_plan_create, as for every entry point. */
+int ar_deblur_iterate_noalloc(ar_plan_t p, const void *g, void *x, int iters, double tau,
+                              int tmode, int precondition, const void *f_true,
+                              double *resnorm_host, double *rre_host, int *best_it_host,
+                              void *stream);
+
 /* Launch tunables of a plan (they change speed, never results).
  *  AR_TUNE_ROW_WAVES / AR_TUNE_COL_WAVES : rows (columns) transformed per
  *      workgroup by the wave-per-sequence transform, 1, 2 or 4 (0 = auto)

@@ -51,6 +51,8 @@ SIGNATURES = [
     ("ar_tikhonov_solve", _I, [_VP, _VP, _VP, _D, _VP]),
     ("ar_deblur_iterate", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _VP,
                                C.POINTER(_D), C.POINTER(_D), C.POINTER(_I), _VP]),
+    ("ar_deblur_iterate_noalloc", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _VP,
+                                       C.POINTER(_D), C.POINTER(_D), C.POINTER(_I), _VP]),
     ("ar_plan_tune", _I, [_VP, _I, _I]),
     ("ar_plan_get_tune", _I, [_VP, _I, C.POINTER(_I)]),
     ("ar_plan_autotune", _I, [_VP, C.POINTER(_D), _VP]),

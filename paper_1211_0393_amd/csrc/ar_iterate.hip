@@ -11,6 +11,7 @@
 // 1024^2 iteration.)
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -227,5 +228,109 @@ extern "C" int ar_deblur_iterate(ar_plan_t p, const void *g, void *x, int iters,
     if (best_it_host) *best_it_host = best;
   }
   if (!finite) return fail(AR_ENONFINITE, "ar_deblur_iterate: residual norm is not finite");
+  return AR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant.  Its per-iteration partial sums and reduced
+// scalars live in `scratch`, a file-scope device array (each GPU the library
+// runs on holds its own copy until the process ends).  In host code the
+// array's name is only a stand-in for the symbol: the device address comes
+// from hipGetSymbolAddress, taken once per device with that device current,
+// and only that address is handed to kernels and copies.  Nothing in the
+// array must start at zero (every partial is written by its kernel before
+// the fixed-order reductions read it), so calls do not clear it; calls that
+// overlap on one GPU share the array and race.
+
+constexpr size_t kScratchDoubles = size_t(1) << 18;  // 2 MiB per device
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current).
+int scratch_address(int device, double **out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(AR_EINVAL, "ar_deblur_iterate_noalloc: device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *ptr = nullptr;
+    AR_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_dev[device] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch_dev[device];
+  return AR_OK;
+}
+
+}  // namespace
+
+extern "C" int ar_deblur_iterate_noalloc(ar_plan_t p, const void *g, void *x, int iters,
+                                         double tau, int tmode, int precondition,
+                                         const void *f_true, double *resnorm_host,
+                                         double *rre_host, int *best_it_host, void *stream) {
+  int rc = check_args("ar_deblur_iterate_noalloc", p, g, x, iters, tau, tmode, f_true, rre_host,
+                      best_it_host);
+  if (rc != AR_OK) return rc;
+  if (best_it_host && !rre_host)
+    return fail(AR_EINVAL, "ar_deblur_iterate_noalloc: best_it needs rre_host (the call keeps "
+                           "no host buffer of its own)");
+  AR_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (best_it_host) *best_it_host = 0;
+  if (iters == 0) return AR_OK;
+  IterArgs a = make_args(p, g, x, iters, tau, tmode, precondition, f_true,
+                         resnorm_host != nullptr, f_true != nullptr && rre_host != nullptr);
+  const bool scalars = a.want_res || a.want_rre;
+  const size_t need_p =
+      scalars ? partials_need(p, iters, a.want_res, a.want_rre, a.precondition != 0) : 0;
+  const size_t need = scalars ? need_p + 2 * (size_t)iters + 1 : 0;
+  if (need > kScratchDoubles)
+    return fail(AR_EINVAL, "ar_deblur_iterate_noalloc: this run needs " + std::to_string(need) +
+                               " doubles of scratch, the static buffer holds " +
+                               std::to_string(kScratchDoubles) +
+                               " (run fewer iterations per call)");
+  double *base = nullptr;
+  if ((rc = scratch_address(p->device, &base)) != AR_OK) return rc;
+  place(a, base, base + need_p);
+  if ((rc = enqueue(p, a, st)) != AR_OK) return rc;
+  if (!scalars) return AR_OK;
+  // the reduced sums go straight into the caller's arrays
+  double fsq = 0.0;
+  if (a.want_res)
+    AR_HIP(hipMemcpyAsync(resnorm_host, a.sc, (size_t)iters * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+  if (a.want_rre) {
+    AR_HIP(hipMemcpyAsync(rre_host, a.sc + iters, (size_t)iters * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    AR_HIP(hipMemcpyAsync(&fsq, a.sc + 2 * (size_t)iters, sizeof(double), hipMemcpyDeviceToHost,
+                          st));
+  }
+  AR_HIP(hipStreamSynchronize(st));
+  bool finite = true;
+  if (a.want_res) {
+    for (int k = 0; k < iters; ++k) {
+      resnorm_host[k] = std::sqrt(resnorm_host[k]);
+      if (!std::isfinite(resnorm_host[k])) finite = false;
+    }
+  }
+  if (a.want_rre) {
+    const double fn = std::sqrt(fsq);
+    int best = 0;
+    double bv = 0.0;
+    for (int k = 0; k < iters; ++k) {
+      const double e = std::sqrt(rre_host[k]) / fn;
+      rre_host[k] = e;
+      if (best == 0 || e < bv) {  // first minimiser on ties
+        best = k + 1;
+        bv = e;
+      }
+    }
+    if (best_it_host) *best_it_host = best;
+  }
+  if (!finite)
+    return fail(AR_ENONFINITE, "ar_deblur_iterate_noalloc: residual norm is not finite");
   return AR_OK;
 }

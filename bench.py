@@ -494,7 +494,8 @@ def main():
               [("row_waves", P.AR_TUNE_ROW_WAVES), ("col_waves", P.AR_TUNE_COL_WAVES),
                ("row_excl", P.AR_TUNE_ROW_EXCL), ("col_excl", P.AR_TUNE_COL_EXCL),
                ("row_fft", P.AR_TUNE_ROW_ALGO), ("col_fft", P.AR_TUNE_COL_ALGO),
-               ("row_lanes", P.AR_TUNE_ROW_LANES), ("col_lanes", P.AR_TUNE_COL_LANES)]}
+               ("row_lanes", P.AR_TUNE_ROW_LANES), ("col_lanes", P.AR_TUNE_COL_LANES),
+               ("blur_engine", P.AR_TUNE_BLUR)]}
     x = torch.zeros_like(g)
 
     def runs(total):
@@ -544,6 +545,19 @@ def main():
     # ALU (2 P flops per pixel in the plan's arithmetic type), the transform
     # passes by HBM with the algorithmic bytes they own
     phase_us = plan.ar_iterate_profile(g, x, reps=a.kernel_reps)
+    blur_engines = None
+    if a.dtype == "f32":
+        # both FP32 blur engines timed on the same plan and data
+        keep = plan.ar_plan_get_tune(P.AR_TUNE_BLUR)
+        blur_engines = {}
+        for name, eng in (("vector_alu", 1), ("matrix_cores", 2)):
+            try:
+                plan.ar_plan_tune(P.AR_TUNE_BLUR, eng)
+            except P.ArError:
+                continue
+            us = plan.ar_iterate_profile(g, x, reps=a.kernel_reps)
+            blur_engines[name] = {"residual_us": round(us[0], 2), "reblur_us": round(us[1], 2)}
+        plan.ar_plan_tune(P.AR_TUNE_BLUR, keep)
     P_taps = (2 * plan.q1 + 1) * (2 * plan.q2 + 1)
     npx = n * n
     alu_peak = FP64_VECTOR_TFLOPS if a.dtype == "f32x" else FP32_VECTOR_TFLOPS
@@ -624,6 +638,7 @@ def main():
         "roofline": roof,
         "step_roofline": step_roof,
         "kernels": rooflines,
+        "blur_engines": blur_engines,
         "cpu_baseline": cpu,
         "batch": batch,
         "learned_vs_plain": learned,

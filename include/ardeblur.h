@@ -250,10 +250,17 @@ int ar_deblur_iterate_noalloc(ar_plan_t p, const void *g, void *x, int iters, do
  *      chirp-z with a power-of-two FFT (any length); 0 = auto
  *  AR_TUNE_ROW_LANES / AR_TUNE_COL_LANES : wavefronts per sequence, 1 or 2
  *      (0 = 1); with 2, a row's (column's) butterflies and elements are
- *      dealt to 128 lanes                                                */
+ *      dealt to 128 lanes
+ *  AR_TUNE_BLUR : engine of the FP32 blur of A x and A' r: 0 = automatic
+ *      (the matrix cores when q1 <= 10 and q2 <= 8 at plan creation;
+ *      ar_plan_autotune replaces it by the faster engine), 1 = vector ALU,
+ *      2 = matrix cores (FP16 hi/lo operands, three products,
+ *      FP32 accumulation, exact power-of-two scaling; about 2^-21 relative
+ *      per product against FP32's 2^-24).  This one changes results in the
+ *      last bits; the batched executor always uses the vector-ALU blur. */
 enum ar_tune_key { AR_TUNE_ROW_WAVES = 0, AR_TUNE_COL_WAVES = 1, AR_TUNE_ROW_EXCL = 2,
                    AR_TUNE_COL_EXCL = 3, AR_TUNE_ROW_ALGO = 4, AR_TUNE_COL_ALGO = 5,
-                   AR_TUNE_ROW_LANES = 6, AR_TUNE_COL_LANES = 7 };
+                   AR_TUNE_ROW_LANES = 6, AR_TUNE_COL_LANES = 7, AR_TUNE_BLUR = 8 };
 
 /* Set one tunable (value 0 restores the automatic choice).  Errors:
  * AR_EINVAL for an unknown key or value. */

@@ -24,6 +24,7 @@ from ._lib import (  # noqa: F401
     AR_FILTER_THRESHOLD,
     AR_FILTER_TIKHONOV,
     AR_REBLUR,
+    AR_TUNE_BLUR,
     AR_TUNE_COL_ALGO,
     AR_TUNE_COL_EXCL,
     AR_TUNE_COL_LANES,

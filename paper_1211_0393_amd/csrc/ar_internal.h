@@ -146,7 +146,7 @@ struct ar_plan_s {
   int filter = AR_FILTER_TIKHONOV;
   double filter_param = 1e-2;
   // launch tunables (0 = automatic), set by ar_plan_tune / ar_plan_autotune
-  int tune[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int tune[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   // dense transform matrices of AR_F32_BF16X3 (FP32, m x m): T~_{n1}, T_{n1},
   // T~_{n2}^T, T_{n2}^T, and an n1 x n2 scratch
   float *mat_fwd_col = nullptr, *mat_inv_col = nullptr;
@@ -159,6 +159,10 @@ struct ar_plan_s {
   // preconditioner through FFT plans of length n and the DCT twiddles
   // e^{-i pi k/(2n)} (compute type) of each axis
   int bc = AR_BC_ANTIREFLECTIVE;
+  // matrix-core blur of FP32 plans: FP16 hi/lo weight fragments of A and A'
+  // (scaled by 2^mfma_ew), built per PSF when q1 <= 10 and q2 <= 8
+  void *mfma_frag_fwd = nullptr, *mfma_frag_rev = nullptr;
+  int mfma_ew = 0;
   ar::FftPlan bc_fft_row, bc_fft_col;
   void *bc_e2_row = nullptr, *bc_e2_col = nullptr;
   float *gains = nullptr;      // last gains of AR_FILTER_GAINS (64 floats)
@@ -219,6 +223,14 @@ size_t conv_batch_smem(int dtype, int q1max, int q2);
 int conv_batch_launch(int dtype, int q2, const ConvJob *jobs, const int2 *tiles, int ntiles, int k,
                       bool ext_mode, size_t smem, hipStream_t st);
 int conv_tiles(int m1, int m2, int *tiles_x);
+// matrix-core blur of FP32 plans (ar_blur_mfma.hip): FP16x3 products on
+// v_mfma_f32_16x16x32_f16; `reverse` selects A' (weights H) over A
+constexpr int kMfmaMaxQ1 = 10, kMfmaMaxQ2 = 8;
+bool conv_mfma_ok(const ar_plan_s *p);
+int conv_mfma_blocks(int m1, int m2);
+int mfma_frag_build(ar_plan_s *p, double hmax, hipStream_t st);
+int conv_mfma_launch(const ar_plan_s *p, const void *in, void *out, bool reverse,
+                     const void *gsub, double *partial, hipStream_t st);
 // batched fold of the extended-grid correlation (in = ext, out = y)
 int fold_batch_launch(int dtype, const ConvJob *jobs, int count, int n1max, int n2max,
                       int qmax, hipStream_t st);
@@ -293,6 +305,7 @@ int reduce_rows_launch(const double *partials, int rows, int cols, double *out, 
 int tikhonov_scale_launch(const ar_plan_s *p, void *c, double alpha, hipStream_t st);
 // host check of strong symmetry (per-axis flips leave H unchanged to 1e-14 max|H|)
 bool psf_strongly_symmetric(const double *H, int q1, int q2);
+double psf_absmax(const double *H, int taps);
 // size the plan's partial-sum and scalar buffers for runs of `iters`
 // iterations with residual norms and RRE requested (ar_iterate.hip)
 constexpr int kReserveIters = 128;

@@ -451,6 +451,12 @@ int tikhonov_scale_launch(const ar_plan_s *p, void *c, double alpha, hipStream_t
   return AR_OK;
 }
 
+double psf_absmax(const double *H, int taps) {
+  double mx = 0.0;
+  for (int e = 0; e < taps; ++e) mx = std::max(mx, std::fabs(H[e]));
+  return mx;
+}
+
 bool psf_strongly_symmetric(const double *H, int q1, int q2) {
   const int K1 = 2 * q1 + 1, K2 = 2 * q2 + 1;
   double mx = 0.0;
@@ -486,7 +492,7 @@ static void plan_free(ar_plan_s *p) {
                   p->y,           p->c,           p->ext,          p->partials,
                   p->scalars,     p->gains,       p->lscr,         p->mat_fwd_col,
                   p->mat_inv_col, p->mat_fwdT_row, p->mat_invT_row, p->dscr,
-                  p->dT};
+                  p->dT,          p->mfma_frag_fwd, p->mfma_frag_rev};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   fft_plan_free(p->fft_row);
@@ -584,6 +590,7 @@ extern "C" int ar_plan_create_bc(ar_plan_t *out, int n1, int n2, const double *p
       (ar && (rc = fft_plan_build(p->fft_col, n1, csize == 8, st)) != AR_OK) ||
       (ar && dtype == AR_F32_ACC64 && (rc = fft_plan_build(p->fft_row32, n2, false, st)) != AR_OK) ||
       (!ar && (rc = bc_setup(p, st)) != AR_OK) ||
+      (rc = mfma_frag_build(p, psf_absmax(psf_host, P), st)) != AR_OK ||
       (dtype == AR_F32_BF16X3 && (rc = dense_setup(p, st)) != AR_OK)) {
     plan_free(p);
     return rc;
@@ -627,6 +634,8 @@ extern "C" int ar_plan_set_psf(ar_plan_t p, const double *psf_host, int q1, int 
   p->strong_sym = psf_strongly_symmetric(psf_host, q1, q2);
   int rc = spectrum_launch(p, st);
   if (rc != AR_OK) return rc;
+  if (p->mfma_frag_fwd && (rc = mfma_frag_build(p, psf_absmax(psf_host, P), st)) != AR_OK)
+    return rc;
   rc = p->filter == AR_FILTER_GAINS ? gains_filter_launch(p, p->gains, st)
                                     : filter_launch(p, p->filter, p->filter_param, st);
   if (rc != AR_OK) return rc;

@@ -92,6 +92,74 @@ def test_blur_operators(n1, n2, q1, q2, dt):
         assert e <= 2 * TOL_BLUR[dt], e
 
 
+@pytest.mark.parametrize("engine", [1, 2])
+@pytest.mark.parametrize("n1,n2,q1,q2", [c for c in BLUR_CASES if c[2] <= 10 and c[3] <= 8] +
+                         [(33, 31, 10, 8), (64, 1000, 7, 7)])
+def test_blur_engines_fp32(n1, n2, q1, q2, engine):
+    """The FP32 blur on the vector ALU (1) and on the matrix cores (2: FP16
+    hi/lo operands, three products, FP32 accumulation, power-of-two scaling)
+    against the oracle, for A, A' and the fused residual g - A x with its
+    norm, at 1e-6."""
+    H = synth.psf_random(q1, q2, seed=n1 + 31 * n2 + q1)
+    X = image(n1, n2, seed=n1 * n2, dt="f32")
+    G = image(n1, n2, seed=n1 + n2, dt="f32")
+    with P.Plan(n1, n2, H, dtype="f32") as plan:
+        plan.ar_plan_tune(P.AR_TUNE_BLUR, engine)
+        x = dev(X, torch.float32)
+        y = torch.empty_like(x)
+        plan.ar_blur_apply(x, y)
+        e1 = rel(host(y), O.blur(X, H))
+        plan.ar_blur_apply_T(x, y, P.AR_REBLUR)
+        e2 = rel(host(y), O.reblur(X, H))
+        # the residual r = g - A x_1 and its norm through one plain step from x
+        g = dev(G, torch.float32)
+        xw = x.clone()
+        rc, res, _, _ = plan.ar_deblur_iterate(g, xw, 1, precondition=False, want_resnorm=True)
+        rn = np.linalg.norm(G - O.blur(X, H))
+        e3 = abs(res[0] - rn) / rn
+        e4 = rel(host(xw), X + O.reblur(G - O.blur(X, H), H))
+    say(f"  engine {engine} {n1}x{n2} q=({q1},{q2}): A {e1:.2e}, A' {e2:.2e}, "
+        f"||r|| {e3:.2e}, step {e4:.2e}")
+    assert rc == 0
+    assert max(e1, e2, e3, e4) <= 1e-6
+
+
+def test_blur_matrix_core_scaling_extremes():
+    """Per-tile power-of-two scaling keeps the FP16 operands in range for
+    tiny, huge and mixed-magnitude images (relative error 1e-6), and
+    non-finite input propagates instead of faulting."""
+    n, H = 96, synth.psf_random(7, 7, seed=4)
+    X = image(n, n, seed=3, dt="f32")
+    with P.Plan(n, n, H, dtype="f32") as plan:
+        plan.ar_plan_tune(P.AR_TUNE_BLUR, 2)
+        for scale in (1e-30, 1e-6, 1.0, 1e6, 1e30):
+            Xs = (X * scale).astype(np.float32).astype(np.float64)
+            x = dev(Xs, torch.float32)
+            y = torch.empty_like(x)
+            plan.ar_blur_apply(x, y)
+            e = rel(host(y), O.blur(Xs, H))
+            say(f"  scale {scale:.0e}: {e:.2e}")
+            assert e <= 1e-6
+        Xm = X.copy()
+        Xm[:48] *= 1e-8                      # magnitudes 1e8 apart inside one tile
+        Xm = Xm.astype(np.float32).astype(np.float64)
+        x = dev(Xm, torch.float32)
+        y = torch.empty_like(x)
+        plan.ar_blur_apply(x, y)
+        Yg, ref = host(y), O.blur(Xm, H)
+        assert rel(Yg, ref) <= 1e-6
+        # the scale is the tile's: errors stay below 2^-20 of the largest
+        # input of the tile's halo (here the whole image's maximum)
+        err = np.max(np.abs(Yg[:40] - ref[:40]))
+        say(f"  mixed tile: small rows max error {err:.2e} (max |x| {np.max(np.abs(Xm)):.2e})")
+        assert err <= 2.0 ** -20 * np.max(np.abs(Xm))
+        Xn = X.copy()
+        Xn[50, 50] = np.inf
+        x = dev(Xn, torch.float32)
+        plan.ar_blur_apply(x, y)
+        assert not np.all(np.isfinite(host(y)))
+
+
 def test_blur_full_size_1024_motion():
     F, H, E, p = synth.workload("ar1024_f32_motion15")
     X = F.astype(np.float32).astype(np.float64)

@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="skip the plan autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-bc", action="store_true",
+                    help="skip the Reflective / Periodic and direct-solve legs")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 2048^2 BF16x3 precision-variant leg")
     ap.add_argument("--copy-probe", action="store_true",
@@ -473,6 +475,83 @@ def bench_precision(torch, P, iters):
     return out
 
 
+def bench_bc_variants(torch, P, F, H, E, p, iters=ITERS, steps=500, reps=100):
+    """The comparators of the paper's tables on the same 1024^2 workload at
+    the stable alpha: D-Landweber under Reflective BCs (DCT-III algebra)
+    and under Periodic BCs (FFT), FP32; and the direct Tikhonov solve of
+    the strongly symmetric (4-fold symmetrized) PSF under Anti-Reflective
+    and Reflective BCs.  Each iteration's per-phase kernel times and the
+    step-level HBM fraction use the same algorithmic bytes as the timed
+    Anti-Reflective run (36 B per pixel-iteration)."""
+    import oracle as O
+    n = p["n"]
+    out = {}
+    f = torch.from_numpy(F).to("cuda:0", torch.float32)
+    e = torch.from_numpy(E).to("cuda:0", torch.float32)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    for bc in ("reflective", "periodic"):
+        plan = P.Plan(n, n, H, dtype="f32", bc=bc)
+        b = torch.empty_like(f)
+        plan.ar_blur_apply(f, b)
+        g = b + (p["nu"] * torch.linalg.vector_norm(b.double()) /
+                 torch.linalg.vector_norm(e.double())).float() * e
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, STABLE_ALPHA)
+        x = torch.zeros_like(g)
+        plan.ar_deblur_iterate(g, x, iters, want_resnorm=True)          # warm-up
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        done, rc = 0, 0
+        while done < steps:
+            k = min(iters, steps - done)
+            x.zero_()
+            rck, _, _, _ = plan.ar_deblur_iterate(g, x, k, want_resnorm=True)
+            rc = rc or rck
+            done += k
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t = ev0.elapsed_time(ev1) / 1e3 / steps
+        x.zero_()
+        rcq, res, rre, best = plan.ar_deblur_iterate(g, x, iters, f_true=f, want_resnorm=True,
+                                                     want_rre=True)
+        ph = plan.ar_iterate_profile(g, x, reps=reps)
+        gbs = STEP_BYTES * n * n / t / 1e9
+        out[bc] = {"value": round(n * n / t / 1e6, 1), "unit": "Mpixel-iters/s",
+                   "us_per_step": round(t * 1e6, 2), "status": rc,
+                   "best_it": best, "best_rre": finite_min(rre), "diverged": diverged(res),
+                   "phase_us": [round(v, 2) for v in ph],
+                   "step_roofline": {"bound": "hbm", "achieved": round(gbs, 2),
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+        plan.close()
+    S = O.symmetrize(H)
+    for bc in ("antireflective", "reflective"):
+        plan = P.Plan(n, n, S, dtype="f32", bc=bc)
+        b = torch.empty_like(f)
+        plan.ar_blur_apply(f, b)
+        xs = torch.empty_like(b)
+        plan.ar_tikhonov_solve(b, xs, 5e-3)                               # warm-up
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            plan.ar_tikhonov_solve(b, xs, 5e-3)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t = ev0.elapsed_time(ev1) / 1e3 / reps
+        # algorithmic bytes of one solve: read g, write x (FP32), read lambda (FP64)
+        gbs = (4 + 4 + 8) * n * n / t / 1e9
+        out[f"tikhonov_solve_{bc}"] = {
+            "us_per_solve": round(t * 1e6, 2), "value": round(n * n / t / 1e6, 1),
+            "unit": "Mpixel/s", "rre": float(torch.linalg.vector_norm(xs.double() - f.double()) /
+                                             torch.linalg.vector_norm(f.double())),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "bytes_per_pixel": 16}}
+        plan.close()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -596,6 +675,7 @@ def main():
         net_path = LR.WEIGHTS if os.path.exists(LR.WEIGHTS) else None
     stable = bench_stable(torch, P, plan, f, g, net_path)
     plan.ar_precond_set(P.AR_FILTER_TIKHONOV, a.alpha)
+    bc_variants = None if a.no_bc else bench_bc_variants(torch, P, F, H, E, p)
     batch = None if a.no_batch else bench_batch(torch, P, ITERS)
     learned = bench_learned(torch, P, a.learned_images, ITERS) if a.learned_images > 0 else None
     precision = None if a.no_precision else bench_precision(torch, P, 200)
@@ -640,6 +720,7 @@ def main():
         "kernels": rooflines,
         "blur_engines": blur_engines,
         "cpu_baseline": cpu,
+        "boundary_conditions": bc_variants,
         "batch": batch,
         "learned_vs_plain": learned,
         "precision_variant": precision,

@@ -252,9 +252,8 @@ int ar_deblur_iterate_noalloc(ar_plan_t p, const void *g, void *x, int iters, do
  *      (0 = 1); with 2, a row's (column's) butterflies and elements are
  *      dealt to 128 lanes
  *  AR_TUNE_BLUR : engine of the FP32 blur of A x and A' r: 0 = automatic
- *      (the matrix cores when q1 <= 10 and q2 <= 8 at plan creation;
- *      ar_plan_autotune replaces it by the faster engine), 1 = vector ALU,
- *      2 = matrix cores (FP16 hi/lo operands, three products,
+ *      (the matrix cores when q1 <= 10 and q2 <= 8 at plan creation; the
+ *      autotuner leaves it alone), 1 = vector ALU, 2 = matrix cores (FP16 hi/lo operands, three products,
  *      FP32 accumulation, exact power-of-two scaling; about 2^-21 relative
  *      per product against FP32's 2^-24).  This one changes results in the
  *      last bits; the batched executor always uses the vector-ALU blur. */

@@ -2,8 +2,8 @@
 //
 // The autotuner times each candidate setting of the transform tunables
 // (FFT form, lanes per sequence, waves per workgroup, CU-exclusive
-// workgroups) and of the FP32 blur engine (vector ALU or matrix cores) on
-// short runs of whole iterations with HIP events, and keeps the fastest.  Settings change the
+// workgroups) on short runs of whole iterations with HIP events, and keeps
+// the fastest.  Settings change the
 // launch geometry or the FFT factorisation only; every setting computes the
 // same transform (up to rounding).
 #include <cfloat>
@@ -135,23 +135,11 @@ extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
   if (rc == AR_OK)
     tune_axis(AR_TUNE_COL_ALGO, AR_TUNE_COL_LANES, AR_TUNE_COL_WAVES, AR_TUNE_COL_EXCL, false,
               &best_c);
-  // blur engine of FP32 plans: vector ALU or matrix cores, whichever runs the
-  // whole iteration faster (only when the engine is left automatic)
-  double best_b = 0;
-  if (rc == AR_OK && p->mfma_frag_fwd && p->tune[AR_TUNE_BLUR] == 0) {
-    double us[2] = {DBL_MAX, DBL_MAX};
-    for (int eng = 1; eng <= 2 && rc == AR_OK; ++eng) {
-      p->tune[AR_TUNE_BLUR] = eng;
-      rc = time_us(run, st, reps, &us[eng - 1]);
-    }
-    p->tune[AR_TUNE_BLUR] = us[1] <= us[0] ? 2 : 1;
-    best_b = us[1] <= us[0] ? us[1] : us[0];
-  }
   (void)hipStreamSynchronize(st);
   (void)hipFree(g);
   (void)hipFree(x);
   if (rc != AR_OK) return rc;
-  if (best_us) *best_us = (best_b > 0 ? best_b : (best_c > 0 ? best_c : best_r)) / iters;
+  if (best_us) *best_us = (best_c > 0 ? best_c : best_r) / iters;
   return AR_OK;
 }
 

@@ -248,9 +248,12 @@ int ar_deblur_iterate_noalloc(ar_plan_t p, const void *g, void *x, int iters, do
  *  AR_TUNE_ROW_ALGO / AR_TUNE_COL_ALGO   : FFT of the DST-I, 1 = mixed
  *      radix (only when every prime factor of n - 1 is <= 31), 2 = Bluestein
  *      chirp-z with a power-of-two FFT (any length); 0 = auto
- *  AR_TUNE_ROW_LANES / AR_TUNE_COL_LANES : wavefronts per sequence, 1 or 2
- *      (0 = 1); with 2, a row's (column's) butterflies and elements are
- *      dealt to 128 lanes
+ *  AR_TUNE_ROW_LANES / AR_TUNE_COL_LANES : wavefronts per sequence, 1, 2
+ *      or 4 (0 = auto: 2 for an axis of length 1024, else 1); with G of
+ *      them, a row's (column's) butterflies and elements are dealt to 64 G
+ *      lanes; an axis of length 1024 with G = 2 or 4 runs the length-1024
+ *      kernels, which deal the output pairs of the radix-31 (and, G = 4,
+ *      radix-11) butterflies to the G wavefronts
  *  AR_TUNE_BLUR : engine of the FP32 blur of A x and A' r: 0 = automatic
  *      (the matrix cores when q1 <= 10 and q2 <= 8 at plan creation; the
  *      autotuner leaves it alone), 1 = vector ALU, 2 = matrix cores (FP16 hi/lo operands, three products,

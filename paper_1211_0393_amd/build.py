@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libardeblur.so")
-SOURCES = ["ar_plan.hip", "ar_blur.hip", "ar_fft.hip", "ar_xform.hip", "ar_tune.hip", "ar_iterate.hip",
+SOURCES = ["ar_plan.hip", "ar_blur.hip", "ar_fft.hip", "ar_xform.hip", "ar_x1023.hip", "ar_tune.hip", "ar_iterate.hip",
            "ar_batch.hip", "ar_learned.hip", "ar_dense.hip", "ar_bc.hip", "ar_blur_mfma.hip"]
 ARCH = "gfx950"
 

@@ -668,7 +668,7 @@ extern "C" int ar_batch_autotune(ar_batch_t b, double *best_us, void *stream) {
       lead->tune[AR_TUNE_ROW_ALGO] = a;
       lead->tune[AR_TUNE_COL_ALGO] = a;
       const bool row_ok = wave_rows_algo(lead) == a, col_ok = wave_cols_algo(lead) == a;
-      for (int gl = 1; gl <= 2; ++gl)
+      for (int gl : {1, 2, 4})
       for (int w : waves)
         for (int xx = 0; xx < 2; ++xx) {
           double us = 0;

@@ -64,21 +64,33 @@ __device__ __forceinline__ void static_for(F &&f) {
 // and as many for the sine part.  Output k is handed to emit(K, value)
 // with K = std::integral_constant<int, k> as soon as it is formed, so a
 // caller may store it directly (inputs are only read before that point).
-template <int R, typename T, typename Emit>
-__device__ __forceinline__ void dft_odd(const V2<T> (&v)[R], Emit &&emit) {
-  constexpr int H = (R - 1) / 2;
-  V2<T> a[H], b[H];
-  static_for<H>([&](auto J) {
+// The work is in three pieces so that the output pairs can be dealt to
+// several wavefronts: the pair sums and differences (dft_odd_ab), output 0
+// (dft_odd_zero) and the output pairs k = K0+1 .. K1 (dft_odd_pairs).
+template <int R, typename T>
+__device__ __forceinline__ void dft_odd_ab(const V2<T> (&v)[R], V2<T> (&a)[(R - 1) / 2],
+                                           V2<T> (&b)[(R - 1) / 2]) {
+  static_for<(R - 1) / 2>([&](auto J) {
     constexpr int j = J + 1;
     a[J] = cadd(v[j], v[R - j]);
     b[J] = csub(v[j], v[R - j]);
   });
-  const V2<T> v0 = v[0];
+}
+
+template <int R, typename T, typename Emit>
+__device__ __forceinline__ void dft_odd_zero(const V2<T> &v0, const V2<T> (&a)[(R - 1) / 2],
+                                             Emit &&emit) {
   V2<T> s0 = v0;
-  static_for<H>([&](auto J) { s0 = cadd(s0, a[J]); });
+  static_for<(R - 1) / 2>([&](auto J) { s0 = cadd(s0, a[J]); });
   emit(std::integral_constant<int, 0>{}, s0);
-  static_for<H>([&](auto K) {
-    constexpr int k = K + 1;
+}
+
+template <int R, int K0, int K1, typename T, typename Emit>
+__device__ __forceinline__ void dft_odd_pairs(const V2<T> &v0, const V2<T> (&a)[(R - 1) / 2],
+                                              const V2<T> (&b)[(R - 1) / 2], Emit &&emit) {
+  constexpr int H = (R - 1) / 2;
+  static_for<K1 - K0>([&](auto KK) {
+    constexpr int k = K0 + KK + 1;
     V2<T> C = v0, S{T(0), T(0)};
     static_for<H>([&](auto J) {
       constexpr int j = J + 1;
@@ -99,6 +111,16 @@ __device__ __forceinline__ void dft_odd(const V2<T> (&v)[R], Emit &&emit) {
     emit(std::integral_constant<int, k>{}, V2<T>{C.x + S.y, C.y - S.x});
     emit(std::integral_constant<int, R - k>{}, V2<T>{C.x - S.y, C.y + S.x});
   });
+}
+
+template <int R, typename T, typename Emit>
+__device__ __forceinline__ void dft_odd(const V2<T> (&v)[R], Emit &&emit) {
+  constexpr int H = (R - 1) / 2;
+  V2<T> a[H], b[H];
+  dft_odd_ab<R, T>(v, a, b);
+  const V2<T> v0 = v[0];
+  dft_odd_zero<R, T>(v0, a, emit);
+  dft_odd_pairs<R, 0, H, T>(v0, a, b, emit);
 }
 
 // Forward DFT of the radices with a codelet; outputs through emit(K, value).

@@ -267,6 +267,20 @@ int wave_rows_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, i
 int wave_cols_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, int mode,
                            hipStream_t st);
 
+// length-1024 passes with two or four wavefronts per sequence (ar_x1023.hip):
+// storage / compute element sizes ts / cs, W sequences per workgroup (at
+// most x1023_cap(G)), smem bytes of dynamic LDS (>= x1023_lds(W, cs)); the
+// plan's stage twiddles and post-processing table of that axis
+size_t x1023_lds(int W, size_t csize);
+int x1023_cap(int G);
+int x1023_rows_launch(size_t ts, size_t cs, const void *in, void *out, int n1, int W, int G,
+                      size_t smem, int mode, const void *tw, const void *post, double alpha,
+                      double scale, double tau, const void *f_true, double *partial,
+                      const XJob *jobs, int count, int kit, hipStream_t st);
+int x1023_cols_launch(size_t ts, size_t cs, const void *in, void *out, int n2, int W, int G,
+                      size_t smem, int mode, const void *tw, const void *post, double alpha,
+                      double scale, const void *dT, const XJob *jobs, int count, hipStream_t st);
+
 // Reflective (DCT) and Periodic (DFT) preconditioner passes (ar_bc.hip);
 // the row and column passes take the modes of the AR passes (a periodic
 // plan's column pass only COL_FWD_D_INV, its coefficients being the

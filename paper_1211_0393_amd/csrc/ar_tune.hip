@@ -17,14 +17,14 @@ static bool tune_valid(int key, int value) {
   switch (key) {
     case AR_TUNE_ROW_WAVES:
     case AR_TUNE_COL_WAVES:
+    case AR_TUNE_ROW_LANES:
+    case AR_TUNE_COL_LANES:
       return value == 0 || value == 1 || value == 2 || value == 4;
     case AR_TUNE_ROW_EXCL:
     case AR_TUNE_COL_EXCL:
       return value == 0 || value == 1;
     case AR_TUNE_ROW_ALGO:
     case AR_TUNE_COL_ALGO:
-    case AR_TUNE_ROW_LANES:
-    case AR_TUNE_COL_LANES:
     case AR_TUNE_BLUR:
       return value == 0 || value == 1 || value == 2;
     default:
@@ -101,7 +101,7 @@ extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
       (e = hipMemsetAsync(x, 0, bytes, st)) != hipSuccess)
     rc = hip_fail(e, "hipMemsetAsync");
   const int reps = 4, iters = 3;
-  const int waves[3] = {1, 2, 4};
+  const int waves[3] = {1, 2, 4}, lanes[3] = {1, 2, 4};
   auto run = [&]() { return iterate_enqueue(p, g, x, iters, st); };
   // one axis at a time: (algo, lanes, waves, excl) keys of that axis
   auto tune_axis = [&](int k_algo, int k_lanes, int k_waves, int k_excl, bool rows,
@@ -111,7 +111,7 @@ extern "C" int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream) {
     for (int a = 1; a <= 2 && rc == AR_OK; ++a) {
       p->tune[k_algo] = a;
       if ((rows ? wave_rows_algo(p) : wave_cols_algo(p)) != a) continue;  // form not available
-      for (int gl = 1; gl <= 2 && rc == AR_OK; ++gl)
+      for (int gl : lanes)
         for (int w : waves)
           for (int xx = 0; xx < 2 && rc == AR_OK; ++xx) {
             p->tune[k_lanes] = gl;

@@ -1,0 +1,494 @@
+// Length-1024 AR transform passes (gfx950).
+//
+// Rows or columns of length m = 1024: the DST-I of length m - 2 through
+// one complex FFT of length M = 1023 = 31 * 11 * 3 on the packed odd
+// extension u_t = z_{2t} + i z_{2t+1} (Theorem 1: endpoint scaling, ramp
+// removal / restoration), the same mathematics as the general
+// wave-per-sequence engine with every size fixed at compile time and G = 2
+// or 4 wavefronts per sequence.  What differs:
+//   * the odd extension z_0 .. z_{2M-1} of a sequence (ramp removed for a
+//     forward pass) is staged in LDS in natural order, z_{2M-j} = -z_j
+//     written together with z_j; the first (radix-31) stage reads its
+//     inputs u_t from there as aligned pairs, so there is no digit-reversal
+//     table and no scattered store;
+//   * the twiddles of the radix-11 and radix-3 stages and the (cos, sin)
+//     factors of the DST post-processing of a lane's outputs are loaded
+//     into registers with the sequence: LDS holds only the data;
+//   * the radix-31 output pairs are dealt to the G wavefronts of a
+//     sequence (the radix-11 pairs to pairs of wavefronts when G = 4);
+//   * the column pass stages its filtered coefficients as the odd extension
+//     of the inverse transform's input directly.
+// Stages (radix, stride L, twiddle offset in the plan's table): (31, 1, 0),
+// (11, 31, 30), (3, 341, 340); natural input index n = 33 d0 + 3 d1 + d2
+// sits at position d0 + 31 d1 + 341 d2 of the in-place DIT order, so
+// radix-31 butterfly j reads u_t for t = 33 r + 3 (j mod 11) + j / 11.
+#include <type_traits>
+
+#include "ar_codelets.h"
+#include "ar_internal.h"
+
+namespace ar {
+namespace {
+
+using namespace cl;
+
+constexpr int kM = 1023;     // FFT length
+constexpr int kLen = 1024;   // sequence length m
+constexpr int kZ = 2 * kM;   // odd-extension length
+constexpr int kWgMax = 512;  // threads per workgroup the kernels are built for
+
+// Output pairs k = lo + 1 .. hi of part P of S (radix R).
+template <int R, int S, int P> struct Pairs {
+  static constexpr int H = (R - 1) / 2;
+  static constexpr int lo = P * H / S, hi = (P + 1) * H / S;
+};
+
+// Per-lane constants: stage twiddles and post-processing factors.
+template <typename T, int G>
+struct Regs {
+  static constexpr int SL = 64 * G, NK = kLen / SL, C3 = (341 + SL - 1) / SL;
+  V2<T> t11[10];
+  V2<T> t3[C3][2];
+  V2<T> cs[NK];
+  // j11: this lane's radix-11 butterfly; s: its index in the sequence
+  __device__ __forceinline__ void load(const V2<T> *__restrict__ tw,
+                                       const V2<T> *__restrict__ post, int j11, int s) {
+    const int jc = j11 < 93 ? j11 : 0;
+    const int k11 = jc % 31;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) t11[r] = tw[30 + 31 * r + k11];
+#pragma unroll
+    for (int c = 0; c < C3; ++c) {
+      const int j = s + SL * c;
+      const int j3 = j < 341 ? j : 0;
+      t3[c][0] = tw[340 + j3];
+      t3[c][1] = tw[340 + 341 + j3];
+    }
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+      const int k = s + SL * c;
+      cs[c] = post[k < 1 ? 1 : (k > kM - 1 ? kM - 1 : k)];
+    }
+  }
+};
+
+// z_j of the odd extension from the raw value x_j, 0 <= j <= M (ramp
+// removed if asked); zero at j = 0 and j = M
+template <typename T>
+__device__ __forceinline__ T zval(T x, int j, bool ramp, T e0, T e1) {
+  const T invM = T(1) / T(kM);
+  if (ramp) x -= e0 * (T(kM - j) * invM) + e1 * (T(j) * invM);
+  return (j == 0 || j == kM) ? T(0) : x;
+}
+
+// Stage the odd extension value of index j (0 <= j <= M) of a sequence.
+template <typename T>
+__device__ __forceinline__ void zstore(T *Z, int j, T z) {
+  Z[j] = z;
+  if (j >= 1 && j <= kM - 1) Z[kZ - j] = -z;
+}
+
+// Radix-31 stage (stride 1) from the staged odd extension: butterfly j
+// (lane j < 33 of every wavefront of the sequence), output pairs of part g.
+template <typename T, int G>
+__device__ __forceinline__ void st31(V2<T> *U, const V2<T> *Zv, int g, int l64) {
+  const bool ok = l64 < 33;
+  const int j = ok ? l64 : 0;
+  const int jp = 3 * (j % 11) + j / 11;
+  V2<T> v[31];
+  static_for<31>([&](auto r) { v[r] = Zv[jp + 33 * decltype(r)::value]; });
+  V2<T> a[15], b[15];
+  dft_odd_ab<31, T>(v, a, b);
+  const V2<T> v0 = v[0];
+  auto emit = [&](auto K, V2<T> x) {
+    if (ok) U[31 * j + decltype(K)::value] = x;
+  };
+  static_for<G>([&](auto Pc) {
+    constexpr int P = decltype(Pc)::value;
+    if (g == P) {
+      if constexpr (P == 0) dft_odd_zero<31, T>(v0, a, emit);
+      dft_odd_pairs<31, Pairs<31, G, P>::lo, Pairs<31, G, P>::hi, T>(v0, a, b, emit);
+    }
+  });
+}
+
+// Radix-11 stage (stride 31), in place; butterfly j < 93 of this lane.  With
+// G = 4 the output pairs are split over the two halves of the sequence's
+// wavefronts, and a barrier separates all reads from the stores.
+template <typename T, int G>
+__device__ __forceinline__ void st11(V2<T> *U, const Regs<T, G> &R, int j, int part) {
+  const bool ok = j < 93;
+  const int jc = ok ? j : 0;
+  const int grp = jc / 31, k = jc - 31 * grp;
+  const int base = 341 * grp + k;
+  V2<T> v[11];
+  static_for<11>([&](auto r) { v[r] = U[base + 31 * decltype(r)::value]; });
+  static_for<10>([&](auto r) {
+    constexpr int q = decltype(r)::value;
+    v[q + 1] = cmul(v[q + 1], R.t11[q]);
+  });
+  auto emit = [&](auto K, V2<T> x) {
+    if (ok) U[base + 31 * decltype(K)::value] = x;
+  };
+  if constexpr (G == 4) {
+    V2<T> a[5], b[5];
+    dft_odd_ab<11, T>(v, a, b);
+    const V2<T> v0 = v[0];
+    __syncthreads();
+    if (part == 0) {
+      dft_odd_zero<11, T>(v0, a, emit);
+      dft_odd_pairs<11, Pairs<11, 2, 0>::lo, Pairs<11, 2, 0>::hi, T>(v0, a, b, emit);
+    } else {
+      dft_odd_pairs<11, Pairs<11, 2, 1>::lo, Pairs<11, 2, 1>::hi, T>(v0, a, b, emit);
+    }
+  } else {
+    dft_emit<11, T>(v, emit);
+  }
+}
+
+// Radix-3 stage (stride 341), in place; butterflies s + 64 G c.
+template <typename T, int G>
+__device__ __forceinline__ void st3(V2<T> *U, const Regs<T, G> &R, int s) {
+  constexpr int SL = 64 * G, C3 = Regs<T, G>::C3;
+  V2<T> v[C3][3];
+#pragma unroll
+  for (int c = 0; c < C3; ++c) {
+    const int j = s + SL * c;
+    const int jc = j < 341 ? j : 0;
+    v[c][0] = U[jc];
+    v[c][1] = cmul(U[jc + 341], R.t3[c][0]);
+    v[c][2] = cmul(U[jc + 682], R.t3[c][1]);
+  }
+#pragma unroll
+  for (int c = 0; c < C3; ++c) {
+    const int j = s + SL * c;
+    if (j < 341)
+      dft_emit<3, T>(v[c], [&](auto K, V2<T> x) { U[j + 341 * decltype(K)::value] = x; });
+  }
+}
+
+// The FFT of the staged sequence into U (natural order); ends at a barrier.
+template <typename T, int G>
+__device__ __forceinline__ void fft1023(V2<T> *U, const T *Z, const Regs<T, G> &R, int g,
+                                        int l64, int s) {
+  st31<T, G>(U, reinterpret_cast<const V2<T> *>(Z), g, l64);
+  __syncthreads();
+  if constexpr (G == 4) st11<T, G>(U, R, l64 + 64 * (g & 1), g >> 1);
+  else st11<T, G>(U, R, s, 0);
+  __syncthreads();
+  st3<T, G>(U, R, s);
+  __syncthreads();
+}
+
+// Output k of a forward (INV = false) or inverse (INV = true) pass:
+// endpoints from e0 / e1, interior from U_k and U_{M-k} (plus the ramp for
+// the inverse).
+template <typename T, bool INV>
+__device__ __forceinline__ T coef(const V2<T> *U, int k, V2<T> cs, T scale, T alpha, T e0, T e1) {
+  const int kc = k < 1 ? 1 : (k > kM - 1 ? kM - 1 : k);
+  const V2<T> A = U[kc], C = U[kM - kc];
+  const T d = scale * ((C.y - A.y) + cs.x * (A.x - C.x) + cs.y * (A.y + C.y));
+  if (!INV) return k == 0 ? alpha * e0 : (k == kM ? alpha * e1 : d);
+  const T invM = T(1) / T(kM);
+  const T y0 = e0 / alpha, y1 = e1 / alpha;
+  const T in = d + y0 * (T(kM - k) * invM) + y1 * (T(k) * invM);
+  return k == 0 ? y0 : (k == kM ? y1 : in);
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+  return t;
+}
+
+// LDS of one sequence: U (1024 complex), then the staged odd extension with
+// a row pitch that spreads the W sequences of a block over the banks.
+__host__ __device__ inline int zpitch(int W) { return 2048 + 64 / W; }
+
+template <typename T>
+struct Lds {
+  V2<T> *U;
+  T *Z;
+  __device__ Lds(unsigned char *raw, int W, int seq) {
+    U = reinterpret_cast<V2<T> *>(raw) + (size_t)seq * 1024;
+    Z = reinterpret_cast<T *>(raw + (size_t)W * 1024 * sizeof(V2<T>)) + (size_t)seq * zpitch(W);
+  }
+};
+
+// ---------------------------------------------------------------- rows
+
+template <typename TS, typename T, int MODE, int G>
+__global__ __launch_bounds__(kWgMax) void rows1023_kernel(
+    const TS *__restrict__ in, TS *__restrict__ out, int n1, const V2<T> *__restrict__ tw,
+    const V2<T> *__restrict__ post, T alpha, T scale, T tau, const TS *__restrict__ f_true,
+    double *__restrict__ partial, const XJob *__restrict__ jobs, int kit) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (jobs) {  // batched launch: problem blockIdx.y
+    const XJob J = jobs[blockIdx.y];
+    in = static_cast<const TS *>(J.in);
+    out = static_cast<TS *>(J.out);
+    f_true = static_cast<const TS *>(J.aux);
+    partial = J.part ? J.part + (size_t)kit * J.nblk : nullptr;
+  }
+  constexpr int SL = 64 * G, NK = kLen / SL;
+  const int W = (blockDim.x >> 6) / G;
+  const int wv = threadIdx.x >> 6;
+  const int seq = wv / G;
+  const int g = __builtin_amdgcn_readfirstlane(wv % G);  // wavefront within the sequence
+  const int l64 = threadIdx.x & 63;
+  const int s = 64 * g + l64;                             // thread within the sequence
+  const int row = xcd_remap(blockIdx.x, gridDim.x) * W + seq;
+  const bool active = row < n1;
+  const Lds<T> L(smem_raw, W, seq);
+  const Gl<TS> *src = gmem(in) + (size_t)(active ? row : 0) * kLen;
+  Gl<TS> *dst = gmem(out) + (size_t)(active ? row : 0) * kLen;
+  const Gl<TS> *fr = f_true ? gmem(f_true) + (size_t)(active ? row : 0) * kLen : nullptr;
+  // every global load first: the row, its endpoints, x and f (update), the
+  // lane's constants
+  TS xv[NK], xo[NK], fo[NK];
+#pragma unroll
+  for (int c = 0; c < NK; ++c) xv[c] = src[s + SL * c];
+  const T e0 = T(src[0]), e1 = T(src[kLen - 1]);
+  if (MODE == ROW_INV_UPDATE) {
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+      xo[c] = dst[s + SL * c];
+      fo[c] = fr ? fr[s + SL * c] : TS(0);
+    }
+  }
+  Regs<T, G> R;
+  R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
+#pragma unroll
+  for (int c = 0; c < NK; ++c) {
+    const int j = s + SL * c;
+    zstore<T>(L.Z, j, zval<T>(T(xv[c]), j, MODE == ROW_FWD, e0, e1));
+  }
+  __syncthreads();
+  fft1023<T, G>(L.U, L.Z, R, g, l64, s);
+  double ss = 0.0;
+  T val[NK];
+#pragma unroll
+  for (int c = 0; c < NK; ++c)
+    val[c] = coef<T, MODE != ROW_FWD>(L.U, s + SL * c, R.cs[c], scale, alpha, e0, e1);
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+      const int k = s + SL * c;
+      if (MODE == ROW_INV_UPDATE) {
+        const TS xn = TS(T(xo[c]) + tau * val[c]);
+        dst[k] = xn;
+        if (fr) {
+          const double df = (double)xn - (double)fo[c];
+          ss += df * df;
+        }
+      } else {
+        dst[k] = TS(val[c]);
+      }
+    }
+  }
+  if (MODE == ROW_INV_UPDATE && partial) {
+    double *red = reinterpret_cast<double *>(smem_raw);
+    const double t = block_sum(ss, red);
+    if (threadIdx.x == 0) gmem(partial)[blockIdx.x] = t;
+  }
+}
+
+// ------------------------------------------------------------- columns
+
+// Block I/O: the W columns of a workgroup move row by row, thread t serving
+// column t mod W and rows t / W + 64 G i (one batch covers the 1024 rows).
+template <typename TS, typename T, int MODE, int G>
+__global__ __launch_bounds__(kWgMax) void cols1023_kernel(
+    const TS *__restrict__ in, TS *__restrict__ out, int n2, const V2<T> *__restrict__ tw,
+    const V2<T> *__restrict__ post, T alpha, T scale, const TS *__restrict__ dT,
+    const XJob *__restrict__ jobs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (jobs) {  // batched launch: problem blockIdx.y
+    const XJob J = jobs[blockIdx.y];
+    in = static_cast<const TS *>(J.in);
+    out = static_cast<TS *>(J.out);
+    dT = static_cast<const TS *>(J.aux);
+  }
+  constexpr int SL = 64 * G, NK = kLen / SL;
+  const int W = (blockDim.x >> 6) / G;
+  const int wv = threadIdx.x >> 6;
+  const int seq = wv / G;
+  const int g = __builtin_amdgcn_readfirstlane(wv % G);
+  const int l64 = threadIdx.x & 63;
+  const int s = 64 * g + l64;
+  const int col0 = xcd_remap(blockIdx.x, gridDim.x) * W;
+  const int col = col0 + seq;
+  const bool active = col < n2;
+  const long ld = n2;
+  const Lds<T> L(smem_raw, W, seq);
+  // block I/O coordinates
+  const int bc_c = threadIdx.x % W, bc_r0 = threadIdx.x / W;
+  const bool bc_act = col0 + bc_c < n2;
+  const Gl<TS> *bsrc = gmem(in) + (bc_act ? col0 + bc_c : 0);
+  T *Zc = Lds<T>(smem_raw, W, bc_c).Z;
+  TS bv[NK];
+#pragma unroll
+  for (int i = 0; i < NK; ++i) bv[i] = bsrc[(long)(bc_r0 + SL * i) * ld];
+  const T be0 = T(bsrc[0]), be1 = T(bsrc[(long)(kLen - 1) * ld]);
+  // this sequence's endpoints and filter column
+  const Gl<TS> *src = gmem(in) + (active ? col : 0);
+  T e0 = T(src[0]), e1 = T(src[(long)(kLen - 1) * ld]);
+  TS dv[NK];
+  if (MODE == COL_FWD_D_INV) {
+    const Gl<TS> *dcol = gmem(dT) + (size_t)(active ? col : 0) * kLen;
+#pragma unroll
+    for (int c = 0; c < NK; ++c) dv[c] = dcol[s + SL * c];
+  }
+  Regs<T, G> R;
+  R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    const int r = bc_r0 + SL * i;
+    zstore<T>(Zc, r, zval<T>(T(bv[i]), r, MODE != COL_INV, be0, be1));
+  }
+  __syncthreads();
+  fft1023<T, G>(L.U, L.Z, R, g, l64, s);
+  if constexpr (MODE == COL_FWD_D_INV) {
+    // d_k (T~ y)_k, staged as the odd extension of the inverse pass's input;
+    // its endpoints go to the two spare words past the extension
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+      const int k = s + SL * c;
+      const T cf = T(dv[c]) * coef<T, false>(L.U, k, R.cs[c], scale, alpha, e0, e1);
+      zstore<T>(L.Z, k, (k == 0 || k == kM) ? T(0) : cf);
+      if (k == 0) L.Z[kZ] = cf;
+      if (k == kM) L.Z[kZ + 1] = cf;
+    }
+    __syncthreads();
+    e0 = L.Z[kZ];
+    e1 = L.Z[kZ + 1];
+    fft1023<T, G>(L.U, L.Z, R, g, l64, s);
+  }
+  // outputs in natural order over the staging row, then row by row
+#pragma unroll
+  for (int c = 0; c < NK; ++c) {
+    const int k = s + SL * c;
+    L.Z[k] = coef<T, MODE != COL_FWD>(L.U, k, R.cs[c], scale, alpha, e0, e1);
+  }
+  __syncthreads();
+  if (bc_act) {
+    Gl<TS> *bdst = gmem(out) + col0 + bc_c;
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      const int r = bc_r0 + SL * i;
+      bdst[(long)r * ld] = TS(Zc[r]);
+    }
+  }
+}
+
+template <typename TS, typename T, int G>
+int rows_t(const void *in, void *out, int n1, int W, int blocks, size_t smem, int mode,
+           const void *tw, const void *post, double alpha, double scale, double tau,
+           const void *f_true, double *partial, const XJob *jobs, int count, int kit,
+           hipStream_t st) {
+  const dim3 grid(blocks, count), block(64 * G * W);
+  auto ti = static_cast<const TS *>(in);
+  auto to = static_cast<TS *>(out);
+  auto tf = static_cast<const TS *>(f_true);
+  auto ttw = static_cast<const V2<T> *>(tw);
+  auto tp = static_cast<const V2<T> *>(post);
+  hipError_t e = hipSuccess;
+#define AR_X(MODE)                                                                             \
+  e = smem > 64 * 1024 ? hipFuncSetAttribute(                                                  \
+                             reinterpret_cast<const void *>(rows1023_kernel<TS, T, MODE, G>), \
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)           \
+                       : hipSuccess;                                                           \
+  if (e == hipSuccess) {                                                                       \
+    hipLaunchKernelGGL((rows1023_kernel<TS, T, MODE, G>), grid, block, smem, st, ti, to, n1,   \
+                       ttw, tp, T(alpha), T(scale), T(tau), tf, partial, jobs, kit);           \
+    e = hipGetLastError();                                                                     \
+  }
+  switch (mode) {
+    case ROW_FWD: AR_X(ROW_FWD) break;
+    case ROW_INV: AR_X(ROW_INV) break;
+    default: AR_X(ROW_INV_UPDATE) break;
+  }
+#undef AR_X
+  return e == hipSuccess ? AR_OK : hip_fail(e, "rows1023_kernel launch");
+}
+
+template <typename TS, typename T, int G>
+int cols_t(const void *in, void *out, int n2, int W, int blocks, size_t smem, int mode,
+           const void *tw, const void *post, double alpha, double scale, const void *dT,
+           const XJob *jobs, int count, hipStream_t st) {
+  const dim3 grid(blocks, count), block(64 * G * W);
+  auto ti = static_cast<const TS *>(in);
+  auto to = static_cast<TS *>(out);
+  auto td = static_cast<const TS *>(dT);
+  auto ttw = static_cast<const V2<T> *>(tw);
+  auto tp = static_cast<const V2<T> *>(post);
+  hipError_t e = hipSuccess;
+#define AR_X(MODE)                                                                             \
+  e = smem > 64 * 1024 ? hipFuncSetAttribute(                                                  \
+                             reinterpret_cast<const void *>(cols1023_kernel<TS, T, MODE, G>), \
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)           \
+                       : hipSuccess;                                                           \
+  if (e == hipSuccess) {                                                                       \
+    hipLaunchKernelGGL((cols1023_kernel<TS, T, MODE, G>), grid, block, smem, st, ti, to, n2,   \
+                       ttw, tp, T(alpha), T(scale), td, jobs);                                 \
+    e = hipGetLastError();                                                                     \
+  }
+  switch (mode) {
+    case COL_FWD: AR_X(COL_FWD) break;
+    case COL_INV: AR_X(COL_INV) break;
+    default: AR_X(COL_FWD_D_INV) break;
+  }
+#undef AR_X
+  return e == hipSuccess ? AR_OK : hip_fail(e, "cols1023_kernel launch");
+}
+
+}  // namespace
+
+size_t x1023_lds(int W, size_t csize) {
+  return (size_t)W * (1024 * 2 * csize + (size_t)zpitch(W) * csize);
+}
+
+int x1023_cap(int G) { return kWgMax / (64 * G); }
+
+int x1023_rows_launch(size_t ts, size_t cs, const void *in, void *out, int n1, int W, int G,
+                      size_t smem, int mode, const void *tw, const void *post, double alpha,
+                      double scale, double tau, const void *f_true, double *partial,
+                      const XJob *jobs, int count, int kit, hipStream_t st) {
+  if ((G != 2 && G != 4) || W < 1 || W * G * 64 > kWgMax)
+    return fail(AR_EUNSUPPORTED, "length-1024 row pass: bad launch shape");
+  const int blocks = (n1 + W - 1) / W;
+#define AR_D(TS, T)                                                                              \
+  return G == 4 ? rows_t<TS, T, 4>(in, out, n1, W, blocks, smem, mode, tw, post, alpha, scale,  \
+                                   tau, f_true, partial, jobs, count, kit, st)                   \
+                : rows_t<TS, T, 2>(in, out, n1, W, blocks, smem, mode, tw, post, alpha, scale,  \
+                                   tau, f_true, partial, jobs, count, kit, st)
+  if (ts == 8) { AR_D(double, double); }
+  if (cs == 8) { AR_D(float, double); }
+  AR_D(float, float);
+#undef AR_D
+}
+
+int x1023_cols_launch(size_t ts, size_t cs, const void *in, void *out, int n2, int W, int G,
+                      size_t smem, int mode, const void *tw, const void *post, double alpha,
+                      double scale, const void *dT, const XJob *jobs, int count, hipStream_t st) {
+  if ((G != 2 && G != 4) || W < 1 || W * G * 64 > kWgMax)
+    return fail(AR_EUNSUPPORTED, "length-1024 column pass: bad launch shape");
+  const int blocks = (n2 + W - 1) / W;
+#define AR_D(TS, T)                                                                               \
+  return G == 4 ? cols_t<TS, T, 4>(in, out, n2, W, blocks, smem, mode, tw, post, alpha, scale,   \
+                                   dT, jobs, count, st)                                          \
+                : cols_t<TS, T, 2>(in, out, n2, W, blocks, smem, mode, tw, post, alpha, scale,   \
+                                   dT, jobs, count, st)
+  if (ts == 8) { AR_D(double, double); }
+  if (cs == 8) { AR_D(float, double); }
+  AR_D(float, float);
+#undef AR_D
+}
+
+}  // namespace ar

@@ -437,8 +437,18 @@ __device__ __forceinline__ void pack_all(V2<T> *U, const int *s_drev,
 
 // ---------------------------------------------------------------- rows
 
+// Threads per workgroup the kernels are compiled for: 64 G per sequence,
+// up to four sequences; with four wavefronts per sequence, two sequences
+// (and so 256 registers per lane) unless the kernel computes in FP32 and
+// is a Bluestein one, which then needs fewer than 128 registers.
+template <typename T, int G, int MASK> struct WgMax {
+  static constexpr int value =
+      G < 4 ? 256 * G : (sizeof(T) == 4 && MASK != kMaskAll ? 1024 : 512);
+};
+
+
 template <typename TS, typename T, int MODE, bool BS, int G, int MASK>
-__global__ __launch_bounds__(256 * G) void rows_w_kernel(
+__global__ __launch_bounds__((WgMax<T, G, MASK>::value)) void rows_w_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int n1, int m, WDesc wd,
     const V2<T> *__restrict__ tw, const int *__restrict__ drev, const V2<T> *__restrict__ post,
     const V2<T> *__restrict__ chirp, const V2<T> *__restrict__ bhat, T alpha, T scale, T tau,
@@ -605,10 +615,13 @@ __device__ __forceinline__ void block_scatter(V2<T> *Uc, const int *s_drev,
   }
 }
 
-constexpr int kBlockChunk = 16;  // rows per thread per batch of block I/O
+// Rows per thread per batch of block I/O: a column block moves in rows of
+// 64 G threads (one per row and column of the block), so 16 / G rows per
+// thread cover 1024 rows in one batch with no clamped duplicate loads.
+template <int G> struct BlockRows { static constexpr int value = 16 / G; };
 
 template <typename TS, typename T, int MODE, bool BS, int G, int MASK>
-__global__ __launch_bounds__(256 * G) void cols_w_kernel(
+__global__ __launch_bounds__((WgMax<T, G, MASK>::value)) void cols_w_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int m, int n2, WDesc wd,
     const V2<T> *__restrict__ tw, const int *__restrict__ drev, const V2<T> *__restrict__ post,
     const V2<T> *__restrict__ chirp, const V2<T> *__restrict__ bhat, T alpha, T scale,
@@ -649,7 +662,7 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
   V2<T> *const U0 = Ly.U - (size_t)wave * N;
   T *const S0 = reinterpret_cast<T *>(Ly.aux - (size_t)wave * auxb);
   T be0 = T(0), be1 = T(0);
-  BlockChunk<TS, kBlockChunk> bch;
+  BlockChunk<TS, BlockRows<G>::value> bch;
   PackChunk<TS, T, BS, G> pc;
   TabChunk<T> tb;
   // the filter of this wave's column: one contiguous row of the transposed
@@ -697,11 +710,11 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
   if constexpr (BIO) {
     V2<T> *Uc = U0 + (size_t)bc_c * N;
     const bool ramp = MODE != COL_INV;
-    block_scatter<TS, T, kBlockChunk>(Uc, Ly.drev, bch, bc_r0, bc_step, M, bc_act, ramp, be0, be1,
+    block_scatter<TS, T, BlockRows<G>::value>(Uc, Ly.drev, bch, bc_r0, bc_step, M, bc_act, ramp, be0, be1,
                                       invM);
-    for (int r0 = bc_r0 + bc_step * kBlockChunk; r0 < m; r0 += bc_step * kBlockChunk) {
+    for (int r0 = bc_r0 + bc_step * BlockRows<G>::value; r0 < m; r0 += bc_step * BlockRows<G>::value) {
       bch.load(bsrc, ld, r0, bc_step, m);
-      block_scatter<TS, T, kBlockChunk>(Uc, Ly.drev, bch, r0, bc_step, M, bc_act, ramp, be0, be1,
+      block_scatter<TS, T, BlockRows<G>::value>(Uc, Ly.drev, bch, r0, bc_step, M, bc_act, ramp, be0, be1,
                                         invM);
     }
   } else {
@@ -763,15 +776,15 @@ __global__ __launch_bounds__(256 * G) void cols_w_kernel(
     const T *Sc = S0 + (size_t)bc_c * m;
     Gl<TS> *bdst = gmem(out) + col0 + bc_c;
     if (bc_act) {
-      for (int r0 = bc_r0; r0 < m; r0 += bc_step * kBlockChunk) {
-        T v[kBlockChunk];
+      for (int r0 = bc_r0; r0 < m; r0 += bc_step * BlockRows<G>::value) {
+        T v[BlockRows<G>::value];
 #pragma unroll
-        for (int i = 0; i < kBlockChunk; ++i) {
+        for (int i = 0; i < BlockRows<G>::value; ++i) {
           const int r = r0 + bc_step * i;
           v[i] = Sc[r < m ? r : m - 1];
         }
 #pragma unroll
-        for (int i = 0; i < kBlockChunk; ++i) {
+        for (int i = 0; i < BlockRows<G>::value; ++i) {
           const int r = r0 + bc_step * i;
           if (r < m) bdst[(long)r * ld] = TS(v[i]);
         }
@@ -802,14 +815,14 @@ __global__ void wtables_kernel(V2<T> *tw, const int *R, const int *L, const int 
 constexpr size_t kMaxLdsW = 150 * 1024;
 
 // Waves (sequences) per workgroup: `forced` if it fits, else the largest
-// power of two <= 4 whose LDS fits.
-int wave_count(size_t fixed, size_t per_wave, int nseq, int forced) {
+// power of two <= 4 whose LDS fits; never more than `cap`.
+int wave_count(size_t fixed, size_t per_wave, int nseq, int forced, int cap) {
   if (forced == 1 || forced == 2 || forced == 4) {
-    int W = forced;
+    int W = forced < cap ? forced : cap;
     while (W > 1 && fixed + (size_t)W * per_wave > kMaxLdsW) W >>= 1;
     return W;
   }
-  int W = 4;
+  int W = cap;
   while (W > 1 && fixed + (size_t)W * per_wave > kMaxLdsW) W >>= 1;
   while (W > 1 && W / 2 >= nseq) W >>= 1;
   return W;
@@ -1010,6 +1023,9 @@ static bool is_plan1023(const WavePlan &w) {
          w.tw_off[1] == 30 && w.tw_off[2] == 340;
 }
 
+// Wavefronts per sequence from the lanes tunable (0 = one).
+static int lanes_of(int v) { return v == 2 || v == 4 ? v : 1; }
+
 static size_t rows_aux(const ar_plan_s *p) { return 2 * (size_t)p->n2 * p->esize; }
 static size_t cols_aux(const ar_plan_s *p) { return (size_t)p->n1 * p->csize; }
 
@@ -1033,15 +1049,45 @@ static const WavePlan *col_plan(const ar_plan_s *p) {
   return pick(p->fft_col, p->tune[AR_TUNE_COL_ALGO], p, cols_aux(p));
 }
 
+// Wavefronts per sequence of an axis from its lanes tunable: 0 (auto) is two
+// for the mixed-radix plan of length 1023, one otherwise.
+static int axis_lanes(const WavePlan &w, int tune) {
+  return tune == 0 ? (is_plan1023(w) ? 2 : 1) : lanes_of(tune);
+}
+
+// The length-1024 kernels (two or four wavefronts per sequence) serve the
+// mixed-radix plan of length 1023.
+static bool use_x1023(const WavePlan &w, int lanes) {
+  return is_plan1023(w) && axis_lanes(w, lanes) >= 2;
+}
+
+// Sequences per workgroup the kernel of a plan axis was compiled for (the
+// host side of WgMax): two with four wavefronts per sequence unless the
+// FFT is a Bluestein plan computed in FP32.  The same for every compute
+// type of a plan, so that all its row passes share one grid.
+static int seq_cap(const ar_plan_s *p, const WavePlan &w, int lanes) {
+  if (use_x1023(w, lanes)) return x1023_cap(axis_lanes(w, lanes));
+  if (axis_lanes(w, lanes) < 4) return 4;
+  return p->csize == 4 && w.bs ? 4 : 2;
+}
+
 static int rows_waves(const ar_plan_s *p, const WavePlan &w) {
+  const int lanes = p->tune[AR_TUNE_ROW_LANES];
+  if (use_x1023(w, lanes))
+    return wave_count(0, x1023_lds(1, p->csize), p->n1, p->tune[AR_TUNE_ROW_WAVES],
+                      seq_cap(p, w, lanes));
   const size_t fixed = wlds_bytes(w.twn, w.M, w.N, 0, p->csize, 0);
   return wave_count(fixed, (size_t)w.N * 2 * p->csize + rows_aux(p), p->n1,
-                    p->tune[AR_TUNE_ROW_WAVES]);
+                    p->tune[AR_TUNE_ROW_WAVES], seq_cap(p, w, lanes));
 }
 static int cols_waves(const ar_plan_s *p, const WavePlan &w) {
+  const int lanes = p->tune[AR_TUNE_COL_LANES];
+  if (use_x1023(w, lanes))
+    return wave_count(0, x1023_lds(1, p->csize), p->n2, p->tune[AR_TUNE_COL_WAVES],
+                      seq_cap(p, w, lanes));
   const size_t fixed = wlds_bytes(w.twn, w.M, w.N, 0, p->csize, 0);
   return wave_count(fixed, (size_t)w.N * 2 * p->csize + cols_aux(p), p->n2,
-                    p->tune[AR_TUNE_COL_WAVES]);
+                    p->tune[AR_TUNE_COL_WAVES], seq_cap(p, w, lanes));
 }
 
 bool wave_rows_ok(const ar_plan_s *p) { return row_plan(p) != nullptr; }
@@ -1110,23 +1156,38 @@ static int wave_rows_d(const ar_plan_s *p, const FftPlan &fp, const void *in, vo
                        int count, int kit, hipStream_t st) {
   // the FFT form chosen for the plan, from the tables `fp`
   const WavePlan &w = row_plan(p)->bs ? fp.wb : fp.w;
-  const bool g2 = p->tune[AR_TUNE_ROW_LANES] == 2;
-#define AR_R(BS_, G_, MASK_)                                                                   \
-  wave_rows_t<TS, T, BS_, G_, MASK_>(p, fp, w, in, out, mode, tau, f_true, partial, jobs,     \
-                                     count, kit, st)
+  const int gl = axis_lanes(w, p->tune[AR_TUNE_ROW_LANES]);
+#define AR_R(BS_, MASK_)                                                                       \
+  (gl == 4   ? wave_rows_t<TS, T, BS_, 4, MASK_>(p, fp, w, in, out, mode, tau, f_true, partial, \
+                                                 jobs, count, kit, st)                         \
+   : gl == 2 ? wave_rows_t<TS, T, BS_, 2, MASK_>(p, fp, w, in, out, mode, tau, f_true, partial, \
+                                                 jobs, count, kit, st)                         \
+             : wave_rows_t<TS, T, BS_, 1, MASK_>(p, fp, w, in, out, mode, tau, f_true, partial, \
+                                                 jobs, count, kit, st))
   if (w.bs) {
     if constexpr (std::is_same<T, float>::value) {
       switch (bs_static_mask(w)) {
-        case -8: return g2 ? AR_R(true, 2, -8) : AR_R(true, 1, -8);
-        case -9: return g2 ? AR_R(true, 2, -9) : AR_R(true, 1, -9);
-        case -10: return g2 ? AR_R(true, 2, -10) : AR_R(true, 1, -10);
+        case -8: return AR_R(true, -8);
+        case -9: return AR_R(true, -9);
+        case -10: return AR_R(true, -10);
         default: break;
       }
     }
-    return g2 ? AR_R(true, 2, 0) : AR_R(true, 1, 0);
+    return AR_R(true, 0);
   }
-  if (is_plan1023(w)) return g2 ? AR_R(false, 2, kPlan1023) : AR_R(false, 1, kPlan1023);
-  return g2 ? AR_R(false, 2, kMaskAll) : AR_R(false, 1, kMaskAll);
+  if (is_plan1023(w)) {
+    if (gl == 1)
+      return wave_rows_t<TS, T, false, 1, kPlan1023>(p, fp, w, in, out, mode, tau, f_true,
+                                                     partial, jobs, count, kit, st);
+    const int W = rows_waves(p, *row_plan(p));
+    const size_t smem = excl_pad(x1023_lds(W, sizeof(T)), p->tune[AR_TUNE_ROW_EXCL]);
+    const double m = p->n2, M = w.M;
+    return x1023_rows_launch(sizeof(TS), sizeof(T), in, out, p->n1, W, gl, smem, mode, w.tw,
+                             fp.post, std::sqrt(m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))),
+                             std::sqrt(2.0 / M) / 4.0, tau, f_true, partial, jobs, count, kit,
+                             st);
+  }
+  return AR_R(false, kMaskAll);
 #undef AR_R
 }
 
@@ -1204,21 +1265,32 @@ template <typename TS, typename T>
 static int wave_cols_d(const ar_plan_s *p, const void *in, void *out, int mode, const XJob *jobs,
                        int count, hipStream_t st) {
   const WavePlan &w = *col_plan(p);
-  const bool g2 = p->tune[AR_TUNE_COL_LANES] == 2;
-#define AR_C(BS_, G_, MASK_) wave_cols_t<TS, T, BS_, G_, MASK_>(p, w, in, out, mode, jobs, count, st)
+  const int gl = axis_lanes(w, p->tune[AR_TUNE_COL_LANES]);
+#define AR_C(BS_, MASK_)                                                                       \
+  (gl == 4   ? wave_cols_t<TS, T, BS_, 4, MASK_>(p, w, in, out, mode, jobs, count, st)          \
+   : gl == 2 ? wave_cols_t<TS, T, BS_, 2, MASK_>(p, w, in, out, mode, jobs, count, st)          \
+             : wave_cols_t<TS, T, BS_, 1, MASK_>(p, w, in, out, mode, jobs, count, st))
   if (w.bs) {
     if constexpr (std::is_same<T, float>::value) {
       switch (bs_static_mask(w)) {
-        case -8: return g2 ? AR_C(true, 2, -8) : AR_C(true, 1, -8);
-        case -9: return g2 ? AR_C(true, 2, -9) : AR_C(true, 1, -9);
-        case -10: return g2 ? AR_C(true, 2, -10) : AR_C(true, 1, -10);
+        case -8: return AR_C(true, -8);
+        case -9: return AR_C(true, -9);
+        case -10: return AR_C(true, -10);
         default: break;
       }
     }
-    return g2 ? AR_C(true, 2, 0) : AR_C(true, 1, 0);
+    return AR_C(true, 0);
   }
-  if (is_plan1023(w)) return g2 ? AR_C(false, 2, kPlan1023) : AR_C(false, 1, kPlan1023);
-  return g2 ? AR_C(false, 2, kMaskAll) : AR_C(false, 1, kMaskAll);
+  if (is_plan1023(w)) {
+    if (gl == 1) return wave_cols_t<TS, T, false, 1, kPlan1023>(p, w, in, out, mode, jobs, count, st);
+    const int W = cols_waves(p, w);
+    const size_t smem = excl_pad(x1023_lds(W, sizeof(T)), p->tune[AR_TUNE_COL_EXCL]);
+    const double m = p->n1, M = w.M;
+    return x1023_cols_launch(sizeof(TS), sizeof(T), in, out, p->n2, W, gl, smem, mode, w.tw,
+                             p->fft_col.post, std::sqrt(m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))),
+                             std::sqrt(2.0 / M) / 4.0, p->dT, jobs, count, st);
+  }
+  return AR_C(false, kMaskAll);
 #undef AR_C
 }
 

@@ -438,17 +438,21 @@ def test_batch_sizes_transform_and_blur():
 
 
 @pytest.mark.parametrize("dt", DTS)
-@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("n1,n2", [(1024, 1024), (192, 385), (33, 2048)])
-def test_transform_two_waves_per_sequence(n1, n2, lanes, dt):
-    """Transforms with one or two wavefronts per row / column against the
-    oracle (the default FFT form of each length)."""
+def test_transform_waves_per_sequence(n1, n2, lanes, dt):
+    """Transforms and the fused preconditioner column pass with one, two or
+    four wavefronts per row / column against the oracle (the default FFT
+    form of each length; at 1024 the length-1023 plan, whose radix-31 and
+    radix-11 output pairs are dealt to the wavefronts)."""
     say(f"lanes {lanes} n=({n1},{n2}) {dt}")
     rng = np.random.default_rng(n1 * 3 + n2)
     X = rng.standard_normal((n1, n2)).astype(NDT[dt]).astype(np.float64)
-    with P.Plan(n1, n2, np.ones((1, 1)), dtype=dt) as plan:
+    H = synth.psf_random(2, 3, seed=7)
+    with P.Plan(n1, n2, H, dtype=dt) as plan:
         plan.ar_plan_tune(P.AR_TUNE_ROW_LANES, lanes)
         plan.ar_plan_tune(P.AR_TUNE_COL_LANES, lanes)
+        assert plan.ar_plan_get_tune(P.AR_TUNE_ROW_LANES) == lanes
         x = dev(X, TDT[dt])
         c = torch.empty_like(x)
         plan.ar_transform(x, c)
@@ -458,6 +462,12 @@ def test_transform_two_waves_per_sequence(n1, n2, lanes, dt):
         plan.ar_transform_inv(c, xr)
         e = rel(host(xr), X)
         assert e <= 4 * TOL_T[dt], e
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, 1e-2)
+        plan.ar_precond_solve(x, xr)
+        d = O.tikhonov(O.eigenvalues(H, n1, n2), 1e-2)
+        e = rel(host(xr), O.precond_apply(X, d))
+        say(f"  solve rel err {e:.2e}")
+        assert e <= TOL_D[dt], e
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -499,7 +509,7 @@ def test_transform_fft_forms(n1, n2, algo, dt):
 def test_tunables_do_not_change_results(dt):
     """For a fixed FFT form and one wavefront per sequence every launch
     setting of the transform engine gives bitwise the same preconditioner
-    output (two wavefronts per sequence: equal to rounding); the autotuner
+    output (two or four wavefronts per sequence: equal to rounding); the autotuner
     picks one of the settings (and either FFT form)."""
     n1, n2 = 300, 256          # n - 1 = 299 = 13 * 23 and 255 = 3 * 5 * 17
     H = synth.psf_random(3, 4, seed=2)
@@ -517,7 +527,7 @@ def test_tunables_do_not_change_results(dt):
                 plan.ar_plan_tune(key, 0)
             plan.ar_precond_solve(y, z)
             ref = refs[algo] = host(z)
-            for g in (1, 2):
+            for g in (1, 2, 4):
                 plan.ar_plan_tune(P.AR_TUNE_ROW_LANES, g)
                 plan.ar_plan_tune(P.AR_TUNE_COL_LANES, g)
                 for w in (1, 2, 4):
@@ -546,3 +556,5 @@ def test_tunables_do_not_change_results(dt):
             plan.ar_plan_tune(P.AR_TUNE_ROW_WAVES, 3)
         with pytest.raises(P.ArError):
             plan.ar_plan_tune(P.AR_TUNE_COL_ALGO, 3)
+        with pytest.raises(P.ArError):
+            plan.ar_plan_tune(P.AR_TUNE_ROW_LANES, 3)

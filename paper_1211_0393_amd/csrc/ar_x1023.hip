@@ -12,8 +12,12 @@
 //     inputs u_t from there as aligned pairs, so there is no digit-reversal
 //     table and no scattered store;
 //   * the twiddles of the radix-11 and radix-3 stages and the (cos, sin)
-//     factors of the DST post-processing of a lane's outputs are loaded
-//     into registers with the sequence: LDS holds only the data;
+//     factors of the DST post-processing of a lane's outputs sit in
+//     registers: one table value per kind is loaded and the others follow
+//     by products with compile-time roots of unity (angle addition), so LDS
+//     holds only the data and few loads are issued;
+//   * rows and columns move as 4-element (rows) or W-column (column
+//     blocks) vectors;
 //   * the radix-31 output pairs are dealt to the G wavefronts of a
 //     sequence (the radix-11 pairs to pairs of wavefronts when G = 4);
 //   * the column pass stages its filtered coefficients as the odd extension
@@ -43,34 +47,101 @@ template <int R, int S, int P> struct Pairs {
   static constexpr int lo = P * H / S, hi = (P + 1) * H / S;
 };
 
-// Per-lane constants: stage twiddles and post-processing factors.
+// Per-lane constants: stage twiddles and post-processing factors.  The
+// radix-11 twiddles e^{-2 pi i k r / 341} of butterfly j11 (k = j11 mod 31)
+// for r = 1..5 are loaded and r = 6..10 formed as products; the radix-3
+// twiddles e^{-2 pi i j / M} (and their squares) of butterflies
+// j = s + 64 G c, and the factors (cos, sin)(pi k / M) of outputs
+// k = 4 (s + 64 G c) + i, follow from one table value each and
+// compile-time roots.
 template <typename T, int G>
 struct Regs {
-  static constexpr int SL = 64 * G, NK = kLen / SL, C3 = (341 + SL - 1) / SL;
+  static constexpr int SL = 64 * G, NQ = 256 / SL, NK = 4 * NQ, C3 = (341 + SL - 1) / SL;
   V2<T> t11[10];
   V2<T> t3[C3][2];
   V2<T> cs[NK];
-  // j11: this lane's radix-11 butterfly; s: its index in the sequence
   __device__ __forceinline__ void load(const V2<T> *__restrict__ tw,
                                        const V2<T> *__restrict__ post, int j11, int s) {
-    const int jc = j11 < 93 ? j11 : 0;
-    const int k11 = jc % 31;
+    const int k11 = (j11 < 93 ? j11 : 0) % 31;
 #pragma unroll
-    for (int r = 0; r < 10; ++r) t11[r] = tw[30 + 31 * r + k11];
+    for (int r = 0; r < 5; ++r) t11[r] = tw[30 + 31 * r + k11];
+    const V2<T> w3 = tw[340 + s];  // e^{-2 pi i s / M}
+    const V2<T> p4 = post[4 * s];  // e^{i pi 4 s / M}
 #pragma unroll
-    for (int c = 0; c < C3; ++c) {
-      const int j = s + SL * c;
-      const int j3 = j < 341 ? j : 0;
-      t3[c][0] = tw[340 + j3];
-      t3[c][1] = tw[340 + 341 + j3];
-    }
-#pragma unroll
-    for (int c = 0; c < NK; ++c) {
-      const int k = s + SL * c;
-      cs[c] = post[k < 1 ? 1 : (k > kM - 1 ? kM - 1 : k)];
-    }
+    for (int r = 5; r < 10; ++r) t11[r] = cmul(t11[4], t11[r - 5]);
+    static_for<C3>([&](auto Cc) {
+      constexpr int c = decltype(Cc)::value;
+      if constexpr (c == 0) {
+        t3[c][0] = w3;
+      } else {
+        constexpr T fx = T(cos2pi(SL * c, kM)), fy = T(-sin2pi(SL * c, kM));
+        t3[c][0] = cmul(w3, V2<T>{fx, fy});
+      }
+      t3[c][1] = cmul(t3[c][0], t3[c][0]);
+    });
+    static_for<NK>([&](auto Ic) {
+      constexpr int idx = decltype(Ic)::value;
+      constexpr int q = 4 * SL * (idx / 4) + idx % 4;
+      if constexpr (q == 0) {
+        cs[idx] = p4;
+      } else {
+        constexpr T ex = T(cos2pi(q, 2 * kM)), ey = T(sin2pi(q, 2 * kM));
+        cs[idx] = cmul(p4, V2<T>{ex, ey});
+      }
+    });
   }
 };
+
+// N consecutive elements from / to global memory: one vector access when
+// `vec` (the address is aligned to N elements), else N scalar ones.  The
+// image pointers of a call decide `vec` for the whole grid, so the branch
+// is uniform.
+template <int N, typename T>
+__device__ __forceinline__ void vload(T (&d)[N], const Gl<T> *p, bool vec) {
+  if constexpr (N == 1) {
+    d[0] = p[0];
+  } else {
+    typedef T V __attribute__((ext_vector_type(N)));
+    if (vec) {
+      const V v = *(const Gl<V> *)p;
+#pragma unroll
+      for (int i = 0; i < N; ++i) d[i] = v[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) d[i] = p[i];
+    }
+  }
+}
+template <int N, typename T>
+__device__ __forceinline__ void vstore(Gl<T> *p, const T (&d)[N], bool vec) {
+  if constexpr (N == 1) {
+    p[0] = d[0];
+  } else {
+    typedef T V __attribute__((ext_vector_type(N)));
+    if (vec) {
+      V v;
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = d[i];
+      *(Gl<V> *)p = v;
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) p[i] = d[i];
+    }
+  }
+}
+template <typename T>
+__device__ __forceinline__ bool aligned_to(const void *p, int bytes) {
+  return ((size_t)p & (size_t)(bytes - 1)) == 0;
+}
+// four consecutive LDS words at a 4-aligned index
+template <typename T>
+__device__ __forceinline__ void lstore4(T *p, const T (&d)[4]) {
+  typedef T V __attribute__((ext_vector_type(4)));
+  V v;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = d[i];
+  *reinterpret_cast<V *>(p) = v;
+}
 
 // z_j of the odd extension from the raw value x_j, 0 <= j <= M (ramp
 // removed if asked); zero at j = 0 and j = M
@@ -86,6 +157,14 @@ template <typename T>
 __device__ __forceinline__ void zstore(T *Z, int j, T z) {
   Z[j] = z;
   if (j >= 1 && j <= kM - 1) Z[kZ - j] = -z;
+}
+// The same for j = j0 .. j0 + 3 (j0 a multiple of 4)
+template <typename T>
+__device__ __forceinline__ void zstore4(T *Z, int j0, const T (&z)[4]) {
+  lstore4<T>(Z + j0, z);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (j0 + i >= 1 && j0 + i <= kM - 1) Z[kZ - j0 - i] = -z[i];
 }
 
 // Radix-31 stage (stride 1) from the staged odd extension: butterfly j
@@ -223,6 +302,8 @@ struct Lds {
 
 // ---------------------------------------------------------------- rows
 
+// Elements of a row are dealt to the 64 G threads of its sequence in groups
+// of four: thread s holds k = 4 (s + 64 G c) + i.
 template <typename TS, typename T, int MODE, int G>
 __global__ __launch_bounds__(kWgMax) void rows1023_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int n1, const V2<T> *__restrict__ tw,
@@ -236,7 +317,7 @@ __global__ __launch_bounds__(kWgMax) void rows1023_kernel(
     f_true = static_cast<const TS *>(J.aux);
     partial = J.part ? J.part + (size_t)kit * J.nblk : nullptr;
   }
-  constexpr int SL = 64 * G, NK = kLen / SL;
+  constexpr int SL = 64 * G, NQ = 256 / SL;
   const int W = (blockDim.x >> 6) / G;
   const int wv = threadIdx.x >> 6;
   const int seq = wv / G;
@@ -251,46 +332,55 @@ __global__ __launch_bounds__(kWgMax) void rows1023_kernel(
   const Gl<TS> *fr = f_true ? gmem(f_true) + (size_t)(active ? row : 0) * kLen : nullptr;
   // every global load first: the row, its endpoints, x and f (update), the
   // lane's constants
-  TS xv[NK], xo[NK], fo[NK];
+  constexpr int VB = 4 * sizeof(TS);
+  const bool va_in = aligned_to<TS>(in, VB);
+  const bool va_out = aligned_to<TS>(out, VB) && (!f_true || aligned_to<TS>(f_true, VB));
+  TS xv[NQ][4], xo[NQ][4], fo[NQ][4];
 #pragma unroll
-  for (int c = 0; c < NK; ++c) xv[c] = src[s + SL * c];
+  for (int c = 0; c < NQ; ++c) vload<4>(xv[c], src + 4 * (s + SL * c), va_in);
   const T e0 = T(src[0]), e1 = T(src[kLen - 1]);
   if (MODE == ROW_INV_UPDATE) {
 #pragma unroll
-    for (int c = 0; c < NK; ++c) {
-      xo[c] = dst[s + SL * c];
-      fo[c] = fr ? fr[s + SL * c] : TS(0);
+    for (int c = 0; c < NQ; ++c) {
+      vload<4>(xo[c], dst + 4 * (s + SL * c), va_out);
+      if (fr) vload<4>(fo[c], fr + 4 * (s + SL * c), va_out);
     }
   }
   Regs<T, G> R;
   R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
 #pragma unroll
-  for (int c = 0; c < NK; ++c) {
-    const int j = s + SL * c;
-    zstore<T>(L.Z, j, zval<T>(T(xv[c]), j, MODE == ROW_FWD, e0, e1));
+  for (int c = 0; c < NQ; ++c) {
+    const int j0 = 4 * (s + SL * c);
+    T z[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z[i] = zval<T>(T(xv[c][i]), j0 + i, MODE == ROW_FWD, e0, e1);
+    zstore4<T>(L.Z, j0, z);
   }
   __syncthreads();
   fft1023<T, G>(L.U, L.Z, R, g, l64, s);
   double ss = 0.0;
-  T val[NK];
+  TS o[NQ][4];
 #pragma unroll
-  for (int c = 0; c < NK; ++c)
-    val[c] = coef<T, MODE != ROW_FWD>(L.U, s + SL * c, R.cs[c], scale, alpha, e0, e1);
-  if (active) {
+  for (int c = 0; c < NQ; ++c)
 #pragma unroll
-    for (int c = 0; c < NK; ++c) {
-      const int k = s + SL * c;
+    for (int i = 0; i < 4; ++i) {
+      const T v = coef<T, MODE != ROW_FWD>(L.U, 4 * (s + SL * c) + i, R.cs[4 * c + i], scale,
+                                           alpha, e0, e1);
       if (MODE == ROW_INV_UPDATE) {
-        const TS xn = TS(T(xo[c]) + tau * val[c]);
-        dst[k] = xn;
+        o[c][i] = TS(T(xo[c][i]) + tau * v);
         if (fr) {
-          const double df = (double)xn - (double)fo[c];
+          const double df = (double)o[c][i] - (double)fo[c][i];
           ss += df * df;
         }
       } else {
-        dst[k] = TS(val[c]);
+        o[c][i] = TS(v);
       }
     }
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) vstore<4>(dst + 4 * (s + SL * c), o[c], va_out);
+  } else {
+    ss = 0.0;
   }
   if (MODE == ROW_INV_UPDATE && partial) {
     double *red = reinterpret_cast<double *>(smem_raw);
@@ -301,9 +391,11 @@ __global__ __launch_bounds__(kWgMax) void rows1023_kernel(
 
 // ------------------------------------------------------------- columns
 
-// Block I/O: the W columns of a workgroup move row by row, thread t serving
-// column t mod W and rows t / W + 64 G i (one batch covers the 1024 rows).
-template <typename TS, typename T, int MODE, int G>
+// Block I/O: the W columns of a workgroup move as W-element vectors, one
+// per row, thread t serving rows t + 64 G W i (one batch covers the 1024
+// rows).  Filter values and outputs of a column are dealt like a row's
+// elements (k = 4 (s + 64 G c) + i).
+template <typename TS, typename T, int MODE, int G, int W>
 __global__ __launch_bounds__(kWgMax) void cols1023_kernel(
     const TS *__restrict__ in, TS *__restrict__ out, int n2, const V2<T> *__restrict__ tw,
     const V2<T> *__restrict__ post, T alpha, T scale, const TS *__restrict__ dT,
@@ -315,8 +407,7 @@ __global__ __launch_bounds__(kWgMax) void cols1023_kernel(
     out = static_cast<TS *>(J.out);
     dT = static_cast<const TS *>(J.aux);
   }
-  constexpr int SL = 64 * G, NK = kLen / SL;
-  const int W = (blockDim.x >> 6) / G;
+  constexpr int SL = 64 * G, NQ = 256 / SL, BT = 64 * G * W, NR = kLen / BT;
   const int wv = threadIdx.x >> 6;
   const int seq = wv / G;
   const int g = __builtin_amdgcn_readfirstlane(wv % G);
@@ -327,30 +418,40 @@ __global__ __launch_bounds__(kWgMax) void cols1023_kernel(
   const bool active = col < n2;
   const long ld = n2;
   const Lds<T> L(smem_raw, W, seq);
-  // block I/O coordinates
-  const int bc_c = threadIdx.x % W, bc_r0 = threadIdx.x / W;
-  const bool bc_act = col0 + bc_c < n2;
-  const Gl<TS> *bsrc = gmem(in) + (bc_act ? col0 + bc_c : 0);
-  T *Zc = Lds<T>(smem_raw, W, bc_c).Z;
-  TS bv[NK];
+  // the block's rows (W columns each), its first and last rows (ramps)
+  const int t = threadIdx.x;
+  const Gl<TS> *blk = gmem(in) + col0;
+  const bool va_in = aligned_to<TS>(in, W * sizeof(TS));
+  const bool va_out = aligned_to<TS>(out, W * sizeof(TS));
+  const bool va_d = aligned_to<TS>(dT, 4 * sizeof(TS));
+  TS bv[NR][W], b0[W], b1[W];
 #pragma unroll
-  for (int i = 0; i < NK; ++i) bv[i] = bsrc[(long)(bc_r0 + SL * i) * ld];
-  const T be0 = T(bsrc[0]), be1 = T(bsrc[(long)(kLen - 1) * ld]);
-  // this sequence's endpoints and filter column
-  const Gl<TS> *src = gmem(in) + (active ? col : 0);
-  T e0 = T(src[0]), e1 = T(src[(long)(kLen - 1) * ld]);
-  TS dv[NK];
+  for (int i = 0; i < NR; ++i) vload<W>(bv[i], blk + (long)(t + BT * i) * ld, va_in);
+  vload<W>(b0, blk, va_in);
+  vload<W>(b1, blk + (long)(kLen - 1) * ld, va_in);
+  TS dv[NQ][4];
   if (MODE == COL_FWD_D_INV) {
     const Gl<TS> *dcol = gmem(dT) + (size_t)(active ? col : 0) * kLen;
 #pragma unroll
-    for (int c = 0; c < NK; ++c) dv[c] = dcol[s + SL * c];
+    for (int c = 0; c < NQ; ++c) vload<4>(dv[c], dcol + 4 * (s + SL * c), va_d);
   }
   Regs<T, G> R;
   R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
+  T e0 = T(0), e1 = T(0);
 #pragma unroll
-  for (int i = 0; i < NK; ++i) {
-    const int r = bc_r0 + SL * i;
-    zstore<T>(Zc, r, zval<T>(T(bv[i]), r, MODE != COL_INV, be0, be1));
+  for (int c = 0; c < W; ++c)
+    if (seq == c) {
+      e0 = T(b0[c]);
+      e1 = T(b1[c]);
+    }
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    T *Zc = Lds<T>(smem_raw, W, c).Z;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int r = t + BT * i;
+      zstore<T>(Zc, r, zval<T>(T(bv[i][c]), r, MODE != COL_INV, T(b0[c]), T(b1[c])));
+    }
   }
   __syncthreads();
   fft1023<T, G>(L.U, L.Z, R, g, l64, s);
@@ -358,12 +459,18 @@ __global__ __launch_bounds__(kWgMax) void cols1023_kernel(
     // d_k (T~ y)_k, staged as the odd extension of the inverse pass's input;
     // its endpoints go to the two spare words past the extension
 #pragma unroll
-    for (int c = 0; c < NK; ++c) {
-      const int k = s + SL * c;
-      const T cf = T(dv[c]) * coef<T, false>(L.U, k, R.cs[c], scale, alpha, e0, e1);
-      zstore<T>(L.Z, k, (k == 0 || k == kM) ? T(0) : cf);
-      if (k == 0) L.Z[kZ] = cf;
-      if (k == kM) L.Z[kZ + 1] = cf;
+    for (int c = 0; c < NQ; ++c) {
+      const int k0 = 4 * (s + SL * c);
+      T z[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + i;
+        const T cf = T(dv[c][i]) * coef<T, false>(L.U, k, R.cs[4 * c + i], scale, alpha, e0, e1);
+        z[i] = (k == 0 || k == kM) ? T(0) : cf;
+        if (k == 0) L.Z[kZ] = cf;
+        if (k == kM) L.Z[kZ + 1] = cf;
+      }
+      zstore4<T>(L.Z, k0, z);
     }
     __syncthreads();
     e0 = L.Z[kZ];
@@ -372,18 +479,22 @@ __global__ __launch_bounds__(kWgMax) void cols1023_kernel(
   }
   // outputs in natural order over the staging row, then row by row
 #pragma unroll
-  for (int c = 0; c < NK; ++c) {
-    const int k = s + SL * c;
-    L.Z[k] = coef<T, MODE != COL_FWD>(L.U, k, R.cs[c], scale, alpha, e0, e1);
+  for (int c = 0; c < NQ; ++c) {
+    const int k0 = 4 * (s + SL * c);
+    T o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      o[i] = coef<T, MODE != COL_FWD>(L.U, k0 + i, R.cs[4 * c + i], scale, alpha, e0, e1);
+    lstore4<T>(L.Z + k0, o);
   }
   __syncthreads();
-  if (bc_act) {
-    Gl<TS> *bdst = gmem(out) + col0 + bc_c;
 #pragma unroll
-    for (int i = 0; i < NK; ++i) {
-      const int r = bc_r0 + SL * i;
-      bdst[(long)r * ld] = TS(Zc[r]);
-    }
+  for (int i = 0; i < NR; ++i) {
+    const int r = t + BT * i;
+    TS v[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) v[c] = TS(Lds<T>(smem_raw, W, c).Z[r]);
+    vstore<W>(gmem(out) + col0 + (long)r * ld, v, va_out);
   }
 }
 
@@ -418,10 +529,10 @@ int rows_t(const void *in, void *out, int n1, int W, int blocks, size_t smem, in
   return e == hipSuccess ? AR_OK : hip_fail(e, "rows1023_kernel launch");
 }
 
-template <typename TS, typename T, int G>
-int cols_t(const void *in, void *out, int n2, int W, int blocks, size_t smem, int mode,
-           const void *tw, const void *post, double alpha, double scale, const void *dT,
-           const XJob *jobs, int count, hipStream_t st) {
+template <typename TS, typename T, int G, int W>
+int cols_t(const void *in, void *out, int n2, int blocks, size_t smem, int mode, const void *tw,
+           const void *post, double alpha, double scale, const void *dT, const XJob *jobs,
+           int count, hipStream_t st) {
   const dim3 grid(blocks, count), block(64 * G * W);
   auto ti = static_cast<const TS *>(in);
   auto to = static_cast<TS *>(out);
@@ -430,13 +541,14 @@ int cols_t(const void *in, void *out, int n2, int W, int blocks, size_t smem, in
   auto tp = static_cast<const V2<T> *>(post);
   hipError_t e = hipSuccess;
 #define AR_X(MODE)                                                                             \
-  e = smem > 64 * 1024 ? hipFuncSetAttribute(                                                  \
-                             reinterpret_cast<const void *>(cols1023_kernel<TS, T, MODE, G>), \
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)           \
-                       : hipSuccess;                                                           \
+  e = smem > 64 * 1024                                                                         \
+          ? hipFuncSetAttribute(                                                               \
+                reinterpret_cast<const void *>(cols1023_kernel<TS, T, MODE, G, W>),            \
+                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)                         \
+          : hipSuccess;                                                                        \
   if (e == hipSuccess) {                                                                       \
-    hipLaunchKernelGGL((cols1023_kernel<TS, T, MODE, G>), grid, block, smem, st, ti, to, n2,   \
-                       ttw, tp, T(alpha), T(scale), td, jobs);                                 \
+    hipLaunchKernelGGL((cols1023_kernel<TS, T, MODE, G, W>), grid, block, smem, st, ti, to,    \
+                       n2, ttw, tp, T(alpha), T(scale), td, jobs);                             \
     e = hipGetLastError();                                                                     \
   }
   switch (mode) {
@@ -446,6 +558,18 @@ int cols_t(const void *in, void *out, int n2, int W, int blocks, size_t smem, in
   }
 #undef AR_X
   return e == hipSuccess ? AR_OK : hip_fail(e, "cols1023_kernel launch");
+}
+
+template <typename TS, typename T>
+int cols_d(const void *in, void *out, int n2, int W, int G, int blocks, size_t smem, int mode,
+           const void *tw, const void *post, double alpha, double scale, const void *dT,
+           const XJob *jobs, int count, hipStream_t st) {
+#define AR_C(G_, W_)                                                                          \
+  cols_t<TS, T, G_, W_>(in, out, n2, blocks, smem, mode, tw, post, alpha, scale, dT, jobs,   \
+                        count, st)
+  if (G == 4) return W == 2 ? AR_C(4, 2) : AR_C(4, 1);
+  return W == 4 ? AR_C(2, 4) : W == 2 ? AR_C(2, 2) : AR_C(2, 1);
+#undef AR_C
 }
 
 }  // namespace
@@ -477,18 +601,17 @@ int x1023_rows_launch(size_t ts, size_t cs, const void *in, void *out, int n1, i
 int x1023_cols_launch(size_t ts, size_t cs, const void *in, void *out, int n2, int W, int G,
                       size_t smem, int mode, const void *tw, const void *post, double alpha,
                       double scale, const void *dT, const XJob *jobs, int count, hipStream_t st) {
-  if ((G != 2 && G != 4) || W < 1 || W * G * 64 > kWgMax)
+  if ((G != 2 && G != 4) || (W != 1 && W != 2 && W != 4) || W * G * 64 > kWgMax || n2 % W)
     return fail(AR_EUNSUPPORTED, "length-1024 column pass: bad launch shape");
-  const int blocks = (n2 + W - 1) / W;
-#define AR_D(TS, T)                                                                               \
-  return G == 4 ? cols_t<TS, T, 4>(in, out, n2, W, blocks, smem, mode, tw, post, alpha, scale,   \
-                                   dT, jobs, count, st)                                          \
-                : cols_t<TS, T, 2>(in, out, n2, W, blocks, smem, mode, tw, post, alpha, scale,   \
-                                   dT, jobs, count, st)
-  if (ts == 8) { AR_D(double, double); }
-  if (cs == 8) { AR_D(float, double); }
-  AR_D(float, float);
-#undef AR_D
+  const int blocks = n2 / W;
+  if (ts == 8)
+    return cols_d<double, double>(in, out, n2, W, G, blocks, smem, mode, tw, post, alpha, scale,
+                                  dT, jobs, count, st);
+  if (cs == 8)
+    return cols_d<float, double>(in, out, n2, W, G, blocks, smem, mode, tw, post, alpha, scale,
+                                 dT, jobs, count, st);
+  return cols_d<float, float>(in, out, n2, W, G, blocks, smem, mode, tw, post, alpha, scale, dT,
+                              jobs, count, st);
 }
 
 }  // namespace ar

@@ -1082,9 +1082,13 @@ static int rows_waves(const ar_plan_s *p, const WavePlan &w) {
 }
 static int cols_waves(const ar_plan_s *p, const WavePlan &w) {
   const int lanes = p->tune[AR_TUNE_COL_LANES];
-  if (use_x1023(w, lanes))
-    return wave_count(0, x1023_lds(1, p->csize), p->n2, p->tune[AR_TUNE_COL_WAVES],
-                      seq_cap(p, w, lanes));
+  if (use_x1023(w, lanes)) {
+    // the column blocks of the length-1024 kernels move whole: W divides n2
+    int W = wave_count(0, x1023_lds(1, p->csize), p->n2, p->tune[AR_TUNE_COL_WAVES],
+                       seq_cap(p, w, lanes));
+    while (W > 1 && p->n2 % W) W >>= 1;
+    return W;
+  }
   const size_t fixed = wlds_bytes(w.twn, w.M, w.N, 0, p->csize, 0);
   return wave_count(fixed, (size_t)w.N * 2 * p->csize + cols_aux(p), p->n2,
                     p->tune[AR_TUNE_COL_WAVES], seq_cap(p, w, lanes));

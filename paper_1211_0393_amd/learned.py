@@ -7,13 +7,24 @@ ar_precond_set_gains, ar_gains_label and ar_fnet_*.  This module only
 orders the calls, moves tensors and keeps the bookkeeping.
 
 Label of a problem: among 16 Tikhonov parameters (log-spaced in
-[1e-4, 1e-1]) and 16 threshold parameters (log-spaced in [1e-3, 0.3]) the
+[1e-3, 1]) and 16 threshold parameters (log-spaced in [1e-2, 0.9]) the
 plain filter whose D-Landweber run reaches the smallest relative
 restoration error within K iterations; its label (ar_gains_label) is the
 per-eigenvalue-bin Tikhonov parameter that reproduces that filter.  The
-fallback filter is Tikhonov at the sweep's lower-median parameter.
+fallback filter is Tikhonov at the sweep's 13th parameter (about 0.25), the
+Tikhonov parameter most often best on the 256^2 and 1024^2 training labels.
 
-    python -m paper_1211_0393_amd.learned --tuples 20000 --out weights.npy
+The committed weights (fnet_weights.npy) come from
+
+    python -m paper_1211_0393_amd.learned --tuples 8000 --n 256 --steps 0 \
+        --save-data learned_256.npz
+    python -m paper_1211_0393_amd.learned --tuples 2800 --n 1024 --chunk 4 \
+        --steps 0 --save-data learned_1024.npz
+    python -m paper_1211_0393_amd.learned --data learned_256.npz learned_1024.npz \
+        --limit 0 2400 --repeat 1 3 --steps 8000 --seed 3
+
+(training problems 5,000,000 + i; the last 400 problems at 1024^2 were kept
+out of training for validation).
 """
 
 from __future__ import annotations
@@ -25,11 +36,11 @@ import numpy as np
 
 from . import _lib as L
 
-ALPHAS = np.logspace(-4, -1, 16)
-THRESHOLDS = np.logspace(-3, np.log10(0.3), 16)
+ALPHAS = np.logspace(-3, 0, 16)
+THRESHOLDS = np.logspace(-2, np.log10(0.9), 16)
 SETTINGS = [(L.AR_FILTER_TIKHONOV, float(a)) for a in ALPHAS] + \
            [(L.AR_FILTER_THRESHOLD, float(t)) for t in THRESHOLDS]
-FALLBACK = (L.AR_FILTER_TIKHONOV, float(ALPHAS[(len(ALPHAS) - 1) // 2]))
+FALLBACK = (L.AR_FILTER_TIKHONOV, float(ALPHAS[12]))
 WEIGHTS = __file__.rsplit("/", 1)[0] + "/fnet_weights.npy"
 
 
@@ -193,6 +204,11 @@ def main(argv=None):
     ap.add_argument("--first", type=int, default=0, help="index of the first problem")
     ap.add_argument("--data", nargs="*", default=[],
                     help="train on saved features/labels (.npz) instead of sweeping")
+    ap.add_argument("--limit", nargs="*", type=int, default=[],
+                    help="per --data file: use its first N examples (0 = all)")
+    ap.add_argument("--repeat", nargs="*", type=int, default=[],
+                    help="per --data file: how many times its examples enter the set")
+    ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--save-data", default=None, help="also save features/labels (.npz)")
     a = ap.parse_args(argv)
@@ -203,9 +219,15 @@ def main(argv=None):
 
     torch = _torch()
     if a.data:
-        parts = [np.load(f, allow_pickle=False) for f in a.data]
-        feats = torch.from_numpy(np.concatenate([p["feats"] for p in parts])).to("cuda:0")
-        labels = torch.from_numpy(np.concatenate([p["labels"] for p in parts])).to("cuda:0")
+        fs, ls = [], []
+        for k, f in enumerate(a.data):
+            part = np.load(f, allow_pickle=False)
+            lim = a.limit[k] if k < len(a.limit) and a.limit[k] > 0 else None
+            rep = a.repeat[k] if k < len(a.repeat) else 1
+            fs += [part["feats"][:lim]] * rep
+            ls += [part["labels"][:lim]] * rep
+        feats = torch.from_numpy(np.concatenate(fs)).to("cuda:0")
+        labels = torch.from_numpy(np.concatenate(ls)).to("cuda:0")
         log(f"{feats.shape[0]} saved examples loaded")
     else:
         probs = Problems(a.tuples, a.n, a.seed0, first=a.first)
@@ -217,7 +239,7 @@ def main(argv=None):
                      best=best, sel=sel)
     if a.steps <= 0:
         return
-    net = train(feats, labels, steps=a.steps, batch=a.batch, lr=a.lr, log=log)
+    net = train(feats, labels, steps=a.steps, batch=a.batch, lr=a.lr, seed=a.seed, log=log)
     save_params(a.out, net.ar_fnet_get_params())
     log(f"saved {a.out}")
 

@@ -470,6 +470,24 @@ def bench_precision(torch, P, iters):
     out.update(errs)
     out.update({"best_rre": finite_min(rre_b), "best_it": best_b,
                 "f64_best_rre": finite_min(rre_r), "f64_best_it": best_r})
+    # per operator, on the phantom: T~ f, T (T~ f) and the preconditioner
+    # solve, each against the FP64 plan on the same FP32 input
+    ops = {}
+    cb, cr = torch.empty_like(f), torch.empty_like(f64)
+    plan.ar_transform(f, cb)
+    ref.ar_transform(f64, cr)
+    ops["transform_rel_err_vs_f64"] = float(torch.linalg.vector_norm(cb.double() - cr) /
+                                            torch.linalg.vector_norm(cr))
+    yb, yr = torch.empty_like(f), torch.empty_like(f64)
+    plan.ar_transform_inv(cb, yb)
+    ref.ar_transform_inv(cb.double(), yr)
+    ops["transform_inv_rel_err_vs_f64"] = float(torch.linalg.vector_norm(yb.double() - yr) /
+                                                torch.linalg.vector_norm(yr))
+    plan.ar_precond_solve(f, yb)
+    ref.ar_precond_solve(f64, yr)
+    ops["precond_solve_rel_err_vs_f64"] = float(torch.linalg.vector_norm(yb.double() - yr) /
+                                                torch.linalg.vector_norm(yr))
+    out["per_operator"] = ops
     plan.close()
     ref.close()
     return out

@@ -10,12 +10,14 @@
 // applied in the epilogue of the forward column GEMM and the update
 // x += tau w in the epilogue of the inverse row GEMM.
 //
-// GEMM: 128 x 128 output tile per workgroup (4 waves, 64 x 64 each), K step
-// 32, v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Every FP32 operand
-// is split on the fly into hi = bf16(a) and lo = bf16(a - hi) and the
-// product is hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-18 relative, is
-// dropped), giving ~1e-5 relative accuracy per product.  The matrices are
-// built in FP64 on the device and stored as FP32.
+// Operands are BF16 pairs hi = bf16(a), lo = bf16(a - hi): the matrices are
+// built in FP64 on the device and split once when the plan is made; an
+// image operand is split once per pass (transposed for the column passes,
+// so that both GEMM operands are K-contiguous).  GEMM: 128 x 128 output
+// tile per workgroup (4 waves, 64 x 64 each), K step 32, double-buffered
+// LDS, three v_mfma_f32_16x16x32_bf16 products per tile pair with FP32
+// accumulation.
+#include <algorithm>
 #include <cmath>
 
 #include "ar_internal.h"
@@ -25,127 +27,160 @@ namespace {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
 
 constexpr int BM = 128, BN = 128, BK = 32;
 constexpr int PK = BK + 8;  // LDS row pitch in bf16 (80 bytes)
+constexpr int KPAD = 32;    // operand rows are padded with zeros to a multiple of this
+constexpr int NBUF = 2;     // LDS buffers of the GEMM pipeline
+constexpr size_t kGemmLds = (size_t)NBUF * 4 * BM * PK * sizeof(unsigned short) + 4 * sizeof(double);
 
-__device__ __forceinline__ unsigned short bf16_bits(float f) {
+__host__ __device__ inline int kpad(int k) { return (k + KPAD - 1) / KPAD * KPAD; }
+
+__device__ __forceinline__ u16 bf16_bits(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+  return (u16)(u >> 16);
 }
-__device__ __forceinline__ float bf16_val(unsigned short h) {
-  return __uint_as_float((unsigned)h << 16);
-}
+__device__ __forceinline__ float bf16_val(u16 h) { return __uint_as_float((unsigned)h << 16); }
 
 enum Epi { EPI_STORE = 0, EPI_DMUL = 1, EPI_UPDATE = 2 };
 
-// C (M x N) = A (M x K) B (K x N), row-major with leading dimensions.
+// Split an R x C FP32 matrix (leading dimension ldi) into BF16 planes
+// hi = bf16(a), lo = bf16(a - hi) with rows of ldo >= C elements (zeros past
+// C), as is (trans = 0, R rows) or transposed (trans = 1, C rows of R).
+// 32 x 32 tiles through LDS; grid (ceil(ldo_cols / 32), ceil(rows / 32)).
+__global__ __launch_bounds__(256) void split_kernel(const float *__restrict__ in, long ldi, int R,
+                                                    int C, u16 *__restrict__ hi,
+                                                    u16 *__restrict__ lo, long ldo, int trans) {
+  __shared__ float t[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  // output tile: rows orow0 .. +31, columns ocol0 .. +31
+  const int ocol0 = blockIdx.x * 32, orow0 = blockIdx.y * 32;
+  const int orows = trans ? C : R, ocols = trans ? R : C;
+  if (!trans) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = orow0 + ty + 8 * u, c = ocol0 + tx;
+      if (r >= orows || c >= ldo) continue;
+      const float v = c < ocols ? in[(long)r * ldi + c] : 0.f;
+      const u16 h = bf16_bits(v);
+      hi[(long)r * ldo + c] = h;
+      lo[(long)r * ldo + c] = bf16_bits(v - bf16_val(h));
+    }
+    return;
+  }
+  // transposed: input rows ocol0 .. +31 (< R), input columns orow0 .. +31 (< C)
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int ir = ocol0 + ty + 8 * u, ic = orow0 + tx;
+    t[ty + 8 * u][tx] = (ir < R && ic < C) ? in[(long)ir * ldi + ic] : 0.f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = orow0 + ty + 8 * u, c = ocol0 + tx;
+    if (r >= orows || c >= ldo) continue;
+    const float v = t[tx][ty + 8 * u];
+    const u16 h = bf16_bits(v);
+    hi[(long)r * ldo + c] = h;
+    lo[(long)r * ldo + c] = bf16_bits(v - bf16_val(h));
+  }
+}
+
+// C (M x N) = A B with A given as BF16 planes [M][K] and B as planes [N][K]
+// (both K-contiguous, K a multiple of BK with zero padding), row-major C.
+// The product is hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-18 relative,
+// is dropped), ~1e-5 relative per product, FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16.  128 x 128 tile per workgroup (4 waves, 64 x 64
+// each); the tiles of K-step s + 1 travel global -> registers while step s
+// runs from LDS, then go to the other LDS buffer (one barrier per step).
 // EPI_DMUL: C = d .* (A B) with d laid out like C.  EPI_UPDATE: C += tau (A B)
 // and, with f, per-workgroup FP64 partial sums of (C - f)^2.
+struct Planes {
+  const u16 *hi, *lo;
+  long ld;
+};
+
 template <int EPI>
-__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(
-    const float *__restrict__ A, long lda, const float *__restrict__ B, long ldb,
-    float *__restrict__ C, long ldc, int M, int N, int K, const float *__restrict__ d, float tau,
-    const float *__restrict__ f, double *__restrict__ partial, int tiles_n) {
-  __shared__ __align__(16) unsigned short Ah[BM * PK], Al[BM * PK], Bh[BN * PK], Bl[BN * PK];
-  __shared__ double red[4];
+__global__ __launch_bounds__(256) void gemm_b3_kernel(Planes A, Planes B, float *__restrict__ C,
+                                                      long ldc, int M, int N, int K,
+                                                      const float *__restrict__ d, float tau,
+                                                      const float *__restrict__ f,
+                                                      double *__restrict__ partial, int tiles_n) {
+  extern __shared__ __align__(16) unsigned char gsm[];
+  u16(*sm)[4][BM * PK] = reinterpret_cast<u16(*)[4][BM * PK]>(gsm);  // [buffer][Ah, Al, Bh, Bl]
+  double *red = reinterpret_cast<double *>(gsm + (size_t)NBUF * 4 * BM * PK * sizeof(u16));
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int tm = blockIdx.x / tiles_n, tn = blockIdx.x - tm * tiles_n;
   const int i0 = tm * BM, j0 = tn * BN;
   const int wr = wave >> 1, wc = wave & 1;
+  // this thread's 16-byte chunks: tile rows tid / 4 and 64 + tid / 4, k
+  // offset 8 (tid % 4), of each of the four planes
+  const int lrow = tid >> 2, lk8 = (tid & 3) * 8;
+  const u16 *src[4][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int ra = min(i0 + lrow + 64 * h, M - 1), rb = min(j0 + lrow + 64 * h, N - 1);
+    src[0][h] = A.hi + (long)ra * A.ld + lk8;
+    src[1][h] = A.lo + (long)ra * A.ld + lk8;
+    src[2][h] = B.hi + (long)rb * B.ld + lk8;
+    src[3][h] = B.lo + (long)rb * B.ld + lk8;
+  }
+  uint4 stage[4][2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) stage[q][h] = *reinterpret_cast<const uint4 *>(src[q][h] + k0);
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        *reinterpret_cast<uint4 *>(&sm[buf][q][(lrow + 64 * h) * PK + lk8]) = stage[q][h];
+  };
+  // lane l: A[i = l % 16][k = 8 (l / 16) + e], B[k = 8 (l / 16) + e][j = l % 16]
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+  struct Frags { bf8 ah[4], al[4], bh[4], bl[4]; };
+  auto frags = [&](int buf, Frags &F) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int r = (wr * 64 + t * 16 + lr) * PK + lk;
+      const int c = (wc * 64 + t * 16 + lr) * PK + lk;
+      F.ah[t] = *reinterpret_cast<const bf8 *>(&sm[buf][0][r]);
+      F.al[t] = *reinterpret_cast<const bf8 *>(&sm[buf][1][r]);
+      F.bh[t] = *reinterpret_cast<const bf8 *>(&sm[buf][2][c]);
+      F.bl[t] = *reinterpret_cast<const bf8 *>(&sm[buf][3][c]);
+    }
+  };
   f4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-
-  // tile loads: A as 128 rows x 32 k (thread: row tid / 8 + 32 u, 4
-  // consecutive k), B as 32 k x 128 columns (thread: column tid % 128, 16
-  // consecutive k), so that the split halves go to LDS as packed 8- and
-  // 16-byte stores ([row][k] for A, [column][k] for B)
-  const int bn = tid & 127, bkq = (tid >> 7) * 16;
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // global -> registers (clamped addresses, zero outside), all loads first
-    float av[16], bv[16];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int idx = tid + 256 * u;
-      const int row = idx >> 3, c = (idx & 7) * 4;
-      const int gi = i0 + row;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gk = k0 + c + e;
-        const bool ok = gi < M && gk < K;
-        const float v = A[(long)(ok ? gi : 0) * lda + (ok ? gk : 0)];
-        av[4 * u + e] = ok ? v : 0.f;
-      }
-    }
-    {
-      const int gj = j0 + bn;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int gk = k0 + bkq + e;
-        const bool ok = gk < K && gj < N;
-        const float v = B[(long)(ok ? gk : 0) * ldb + (ok ? gj : 0)];
-        bv[e] = ok ? v : 0.f;
-      }
-    }
-    __syncthreads();  // the previous step's fragments have been read
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int idx = tid + 256 * u;
-      const int row = idx >> 3, c = (idx & 7) * 4;
-      unsigned hw[2], lw[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const float v0 = av[4 * u + 2 * q], v1 = av[4 * u + 2 * q + 1];
-        const unsigned short h0 = bf16_bits(v0), h1 = bf16_bits(v1);
-        hw[q] = (unsigned)h0 | ((unsigned)h1 << 16);
-        lw[q] = (unsigned)bf16_bits(v0 - bf16_val(h0)) |
-                ((unsigned)bf16_bits(v1 - bf16_val(h1)) << 16);
-      }
-      *reinterpret_cast<uint2 *>(&Ah[row * PK + c]) = make_uint2(hw[0], hw[1]);
-      *reinterpret_cast<uint2 *>(&Al[row * PK + c]) = make_uint2(lw[0], lw[1]);
-    }
-    {
-      unsigned hw[8], lw[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const float v0 = bv[2 * q], v1 = bv[2 * q + 1];
-        const unsigned short h0 = bf16_bits(v0), h1 = bf16_bits(v1);
-        hw[q] = (unsigned)h0 | ((unsigned)h1 << 16);
-        lw[q] = (unsigned)bf16_bits(v0 - bf16_val(h0)) |
-                ((unsigned)bf16_bits(v1 - bf16_val(h1)) << 16);
-      }
-      uint4 *bh4 = reinterpret_cast<uint4 *>(&Bh[bn * PK + bkq]);  // transposed: [n][k]
-      uint4 *bl4 = reinterpret_cast<uint4 *>(&Bl[bn * PK + bkq]);
-      bh4[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-      bh4[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
-      bl4[0] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
-      bl4[1] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
-    }
-    __syncthreads();
-    // lane l: A[i = l % 16][k = 8 (l / 16) + e], B[k = 8 (l / 16) + e][j = l % 16]
-    const int lr = lane & 15, lk = (lane >> 4) * 8;
-    bf8 ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int r = wr * 64 + t * 16 + lr;
-      ah[t] = *reinterpret_cast<const bf8 *>(&Ah[r * PK + lk]);
-      al[t] = *reinterpret_cast<const bf8 *>(&Al[r * PK + lk]);
-      const int cc = wc * 64 + t * 16 + lr;
-      bh[t] = *reinterpret_cast<const bf8 *>(&Bh[cc * PK + lk]);
-      bl[t] = *reinterpret_cast<const bf8 *>(&Bl[cc * PK + lk]);
-    }
+  // two LDS buffers: the tiles of step s + 1 travel global -> registers
+  // while step s runs from LDS, then go to the other buffer
+  const int nk = K / BK;
+  fetch(0);
+  put(0);
+  __syncthreads();
+  for (int s = 0; s < nk; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nk) fetch((s + 1) * BK);
+    Frags cur;
+    frags(buf, cur);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.al[a], cur.bh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ah[a], cur.bl[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ah[a], cur.bh[b], acc[a][b], 0, 0, 0);
       }
+    if (s + 1 < nk) put(buf ^ 1);
+    __syncthreads();
   }
   // epilogue: lane l holds D[i = 4 (l / 16) + e][j = l % 16] of each 16 x 16 tile
   double ss = 0.0;
@@ -223,14 +258,32 @@ __global__ __launch_bounds__(256) void ar_matrix_kernel(float *__restrict__ out,
 }
 
 template <int EPI>
-int gemm_launch(const float *A, long lda, const float *B, long ldb, float *C, long ldc, int M,
-                int N, int K, const float *d, float tau, const float *f, double *partial,
-                hipStream_t st) {
+int gemm_launch(Planes A, Planes B, float *C, long ldc, int M, int N, int K, const float *d,
+                float tau, const float *f, double *partial, hipStream_t st) {
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
-  hipLaunchKernelGGL(gemm_bf16x3_kernel<EPI>, dim3(tiles_m * tiles_n), dim3(256), 0, st, A, lda,
-                     B, ldb, C, ldc, M, N, K, d, tau, f, partial, tiles_n);
+  AR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(gemm_b3_kernel<EPI>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds));
+  hipLaunchKernelGGL(gemm_b3_kernel<EPI>, dim3(tiles_m * tiles_n), dim3(256), kGemmLds, st, A, B,
+                     C, ldc, M, N, K, d, tau, f, partial, tiles_n);
   AR_HIP(hipGetLastError());
   return AR_OK;
+}
+
+// FP32 R x C (leading dimension ldi) -> BF16 planes at `planes` (hi, then lo
+// after rows * ldo elements), as is or transposed.
+int split_launch(const float *in, long ldi, int R, int C, void *planes, int ldo, bool trans,
+                 hipStream_t st) {
+  const int orows = trans ? C : R;
+  u16 *hi = static_cast<u16 *>(planes), *lo = hi + (size_t)orows * ldo;
+  hipLaunchKernelGGL(split_kernel, dim3((ldo + 31) / 32, (orows + 31) / 32), dim3(256), 0, st, in,
+                     ldi, R, C, hi, lo, (long)ldo, trans ? 1 : 0);
+  AR_HIP(hipGetLastError());
+  return AR_OK;
+}
+
+Planes planes_of(const void *p, int rows, int ld) {
+  const u16 *hi = static_cast<const u16 *>(p);
+  return Planes{hi, hi + (size_t)rows * ld, (long)ld};
 }
 
 }  // namespace
@@ -239,61 +292,76 @@ int dense_blocks(const ar_plan_s *p) {
   return ((p->n1 + BM - 1) / BM) * ((p->n2 + BN - 1) / BN);
 }
 
+// The four transform matrices as BF16 planes (split once, here): T~_{n1}
+// and T_{n1} for the column passes (A operands, [n1][kpad(n1)]), T~_{n2}
+// and T_{n2} for the row passes (B operands [N][K] = the matrices
+// themselves, [n2][kpad(n2)]); scratch: the FP32 n1 x n2 filter product and
+// the planes of one image operand.
 int dense_setup(ar_plan_s *p, hipStream_t st) {
-  const size_t b1 = (size_t)p->n1 * p->n1 * sizeof(float);
-  const size_t b2 = (size_t)p->n2 * p->n2 * sizeof(float);
-  AR_HIP(hipMalloc((void **)&p->mat_fwd_col, b1));
-  AR_HIP(hipMalloc((void **)&p->mat_inv_col, b1));
-  AR_HIP(hipMalloc((void **)&p->mat_fwdT_row, b2));
-  AR_HIP(hipMalloc((void **)&p->mat_invT_row, b2));
-  AR_HIP(hipMalloc(&p->dscr, (size_t)p->n1 * p->n2 * sizeof(float)));
-  hipLaunchKernelGGL(ar_matrix_kernel, dim3(1024), dim3(256), 0, st, p->mat_fwd_col, p->n1, 0, 0);
-  hipLaunchKernelGGL(ar_matrix_kernel, dim3(1024), dim3(256), 0, st, p->mat_inv_col, p->n1, 1, 0);
-  hipLaunchKernelGGL(ar_matrix_kernel, dim3(1024), dim3(256), 0, st, p->mat_fwdT_row, p->n2, 0, 1);
-  hipLaunchKernelGGL(ar_matrix_kernel, dim3(1024), dim3(256), 0, st, p->mat_invT_row, p->n2, 1, 1);
-  AR_HIP(hipGetLastError());
+  const int n1 = p->n1, n2 = p->n2, l1 = kpad(n1), l2 = kpad(n2);
+  const size_t b1 = 2 * (size_t)n1 * l1 * sizeof(u16), b2 = 2 * (size_t)n2 * l2 * sizeof(u16);
+  AR_HIP(hipMalloc(&p->mat_fwd_col, b1));
+  AR_HIP(hipMalloc(&p->mat_inv_col, b1));
+  AR_HIP(hipMalloc(&p->mat_fwd_row, b2));
+  AR_HIP(hipMalloc(&p->mat_inv_row, b2));
+  AR_HIP(hipMalloc(&p->dscr, (size_t)n1 * n2 * sizeof(float)));
+  const size_t sp = 2 * std::max((size_t)n1 * l2, (size_t)n2 * l1) * sizeof(u16);
+  AR_HIP(hipMalloc(&p->dsplit, sp));
+  const int mmax = std::max(n1, n2);
+  float *tmp = nullptr;
+  AR_HIP(hipMalloc((void **)&tmp, (size_t)mmax * mmax * sizeof(float)));
+  int rc = AR_OK;
+  struct Job { void *dst; int m, inv; } jobs[4] = {
+      {p->mat_fwd_col, n1, 0}, {p->mat_inv_col, n1, 1}, {p->mat_fwd_row, n2, 0},
+      {p->mat_inv_row, n2, 1}};
+  for (const Job &j : jobs) {
+    hipLaunchKernelGGL(ar_matrix_kernel, dim3(1024), dim3(256), 0, st, tmp, j.m, j.inv, 0);
+    if ((rc = split_launch(tmp, j.m, j.m, j.m, j.dst, kpad(j.m), false, st)) != AR_OK) break;
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  (void)hipFree(tmp);
+  if (rc != AR_OK) return rc;
+  if (e != hipSuccess) return hip_fail(e, "dense_setup");
   return AR_OK;
 }
 
 // Row passes: out = in T~^T (ROW_FWD), in T^T (ROW_INV), x += tau in T^T
-// (ROW_INV_UPDATE, out = x).  in == out goes through the dense scratch.
+// (ROW_INV_UPDATE, out = x).  The input is split into planes first, so
+// in == out is allowed.
 int dense_rows_launch(const ar_plan_s *p, const void *in, void *out, int mode, double tau,
                       const void *f_true, double *partial, hipStream_t st) {
-  const int n1 = p->n1, n2 = p->n2;
-  const float *A = static_cast<const float *>(in);
-  const float *B = mode == ROW_FWD ? p->mat_fwdT_row : p->mat_invT_row;
+  const int n1 = p->n1, n2 = p->n2, l2 = kpad(n2);
+  int rc = split_launch(static_cast<const float *>(in), n2, n1, n2, p->dsplit, l2, false, st);
+  if (rc != AR_OK) return rc;
+  const Planes A = planes_of(p->dsplit, n1, l2);
+  const Planes B = planes_of(mode == ROW_FWD ? p->mat_fwd_row : p->mat_inv_row, n2, l2);
+  float *C = static_cast<float *>(out);
   if (mode == ROW_INV_UPDATE)
-    return gemm_launch<EPI_UPDATE>(A, n2, B, n2, static_cast<float *>(out), n2, n1, n2, n2,
-                                   nullptr, (float)tau, static_cast<const float *>(f_true),
-                                   partial, st);
-  float *C = in == out ? static_cast<float *>(p->dscr) : static_cast<float *>(out);
-  int rc = gemm_launch<EPI_STORE>(A, n2, B, n2, C, n2, n1, n2, n2, nullptr, 0.f, nullptr, nullptr,
-                                  st);
-  if (rc != AR_OK || in != out) return rc;
-  AR_HIP(hipMemcpyAsync(out, C, (size_t)n1 * n2 * sizeof(float), hipMemcpyDeviceToDevice, st));
-  return AR_OK;
+    return gemm_launch<EPI_UPDATE>(A, B, C, n2, n1, n2, l2, nullptr, (float)tau,
+                                   static_cast<const float *>(f_true), partial, st);
+  return gemm_launch<EPI_STORE>(A, B, C, n2, n1, n2, l2, nullptr, 0.f, nullptr, nullptr, st);
 }
 
 // Column passes: out = T~ in (COL_FWD), T in (COL_INV), T (d .* (T~ in))
-// (COL_FWD_D_INV, through the dense scratch).
+// (COL_FWD_D_INV, the filter product through the FP32 scratch).
 int dense_cols_launch(const ar_plan_s *p, const void *in, void *out, int mode, hipStream_t st) {
-  const int n1 = p->n1, n2 = p->n2;
-  const float *B = static_cast<const float *>(in);
-  float *S = static_cast<float *>(p->dscr);
+  const int n1 = p->n1, n2 = p->n2, l1 = kpad(n1);
+  int rc = split_launch(static_cast<const float *>(in), n2, n1, n2, p->dsplit, l1, true, st);
+  if (rc != AR_OK) return rc;
+  const Planes B = planes_of(p->dsplit, n2, l1);
   if (mode == COL_FWD_D_INV) {
-    int rc = gemm_launch<EPI_DMUL>(p->mat_fwd_col, n1, B, n2, S, n2, n1, n2, n1,
-                                   static_cast<const float *>(p->d), 0.f, nullptr, nullptr, st);
+    float *S = static_cast<float *>(p->dscr);
+    rc = gemm_launch<EPI_DMUL>(planes_of(p->mat_fwd_col, n1, l1), B, S, n2, n1, n2, l1,
+                               static_cast<const float *>(p->d), 0.f, nullptr, nullptr, st);
     if (rc != AR_OK) return rc;
-    return gemm_launch<EPI_STORE>(p->mat_inv_col, n1, S, n2, static_cast<float *>(out), n2, n1,
-                                  n2, n1, nullptr, 0.f, nullptr, nullptr, st);
+    if ((rc = split_launch(S, n2, n1, n2, p->dsplit, l1, true, st)) != AR_OK) return rc;
+    return gemm_launch<EPI_STORE>(planes_of(p->mat_inv_col, n1, l1), B,
+                                  static_cast<float *>(out), n2, n1, n2, l1, nullptr, 0.f,
+                                  nullptr, nullptr, st);
   }
-  const float *Mx = mode == COL_FWD ? p->mat_fwd_col : p->mat_inv_col;
-  float *C = in == out ? S : static_cast<float *>(out);
-  int rc = gemm_launch<EPI_STORE>(Mx, n1, B, n2, C, n2, n1, n2, n1, nullptr, 0.f, nullptr,
-                                  nullptr, st);
-  if (rc != AR_OK || in != out) return rc;
-  AR_HIP(hipMemcpyAsync(out, C, (size_t)n1 * n2 * sizeof(float), hipMemcpyDeviceToDevice, st));
-  return AR_OK;
+  const void *Mx = mode == COL_FWD ? p->mat_fwd_col : p->mat_inv_col;
+  return gemm_launch<EPI_STORE>(planes_of(Mx, n1, l1), B, static_cast<float *>(out), n2, n1, n2,
+                                l1, nullptr, 0.f, nullptr, nullptr, st);
 }
 
 }  // namespace ar

@@ -147,11 +147,12 @@ struct ar_plan_s {
   double filter_param = 1e-2;
   // launch tunables (0 = automatic), set by ar_plan_tune / ar_plan_autotune
   int tune[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  // dense transform matrices of AR_F32_BF16X3 (FP32, m x m): T~_{n1}, T_{n1},
-  // T~_{n2}^T, T_{n2}^T, and an n1 x n2 scratch
-  float *mat_fwd_col = nullptr, *mat_inv_col = nullptr;
-  float *mat_fwdT_row = nullptr, *mat_invT_row = nullptr;
-  void *dscr = nullptr;
+  // dense transform matrices of AR_F32_BF16X3 as BF16 hi / lo planes (m
+  // rows of m padded to a multiple of 32): T~_{n1}, T_{n1}, T~_{n2}, T_{n2};
+  // an FP32 n1 x n2 scratch and the planes of one image operand
+  void *mat_fwd_col = nullptr, *mat_inv_col = nullptr;
+  void *mat_fwd_row = nullptr, *mat_inv_row = nullptr;
+  void *dscr = nullptr, *dsplit = nullptr;
   int q1cap = 0, q2cap = 0;    // half-widths the PSF buffers were sized for
   bool strong_sym = false;     // h_{|s1|,|s2|} = h_{s1,s2} (then P(s) = A and the
                                // eigenvalues lambda are those of A itself)

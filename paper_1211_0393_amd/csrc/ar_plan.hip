@@ -491,8 +491,8 @@ static void plan_free(ar_plan_s *p) {
                   p->lambda,      p->d64,         p->d,            p->r,
                   p->y,           p->c,           p->ext,          p->partials,
                   p->scalars,     p->gains,       p->lscr,         p->mat_fwd_col,
-                  p->mat_inv_col, p->mat_fwdT_row, p->mat_invT_row, p->dscr,
-                  p->dT,          p->mfma_frag_fwd, p->mfma_frag_rev};
+                  p->mat_inv_col, p->mat_fwd_row, p->mat_inv_row,  p->dscr,
+                  p->dsplit,      p->dT,          p->mfma_frag_fwd, p->mfma_frag_rev};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   fft_plan_free(p->fft_row);

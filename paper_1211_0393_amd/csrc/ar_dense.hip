@@ -14,7 +14,7 @@
 // built in FP64 on the device and split once when the plan is made; an
 // image operand is split once per pass (transposed for the column passes,
 // so that both GEMM operands are K-contiguous).  GEMM: 128 x 128 output
-// tile per workgroup (4 waves, 64 x 64 each), K step 32, double-buffered
+// tile per workgroup (8 waves, 64 x 32 each), K step 32, double-buffered
 // LDS, three v_mfma_f32_16x16x32_bf16 products per tile pair with FP32
 // accumulation.
 #include <algorithm>
@@ -33,7 +33,9 @@ constexpr int BM = 128, BN = 128, BK = 32;
 constexpr int PK = BK + 8;  // LDS row pitch in bf16 (80 bytes)
 constexpr int KPAD = 32;    // operand rows are padded with zeros to a multiple of this
 constexpr int NBUF = 2;     // LDS buffers of the GEMM pipeline
-constexpr size_t kGemmLds = (size_t)NBUF * 4 * BM * PK * sizeof(unsigned short) + 4 * sizeof(double);
+constexpr int GT = 512;     // threads of a GEMM workgroup (8 waves of 64 x 32 outputs)
+constexpr int GROUP_M = 4;  // row tiles per group of the workgroup order
+constexpr size_t kGemmLds = (size_t)NBUF * 4 * BM * PK * sizeof(unsigned short) + 8 * sizeof(double);
 
 __host__ __device__ inline int kpad(int k) { return (k + KPAD - 1) / KPAD * KPAD; }
 
@@ -92,9 +94,10 @@ __global__ __launch_bounds__(256) void split_kernel(const float *__restrict__ in
 // (both K-contiguous, K a multiple of BK with zero padding), row-major C.
 // The product is hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-18 relative,
 // is dropped), ~1e-5 relative per product, FP32 accumulation on
-// v_mfma_f32_16x16x32_bf16.  128 x 128 tile per workgroup (4 waves, 64 x 64
-// each); the tiles of K-step s + 1 travel global -> registers while step s
-// runs from LDS, then go to the other LDS buffer (one barrier per step).
+// v_mfma_f32_16x16x32_bf16.  128 x 128 tile per workgroup (8 waves, 64 x 32
+// each, two per SIMD); the tiles of K-step s + 1 travel global -> registers
+// while step s runs from LDS, then go to the other LDS buffer (one barrier
+// per step).
 // EPI_DMUL: C = d .* (A B) with d laid out like C.  EPI_UPDATE: C += tau (A B)
 // and, with f, per-workgroup FP64 partial sums of (C - f)^2.
 struct Planes {
@@ -103,7 +106,7 @@ struct Planes {
 };
 
 template <int EPI>
-__global__ __launch_bounds__(256) void gemm_b3_kernel(Planes A, Planes B, float *__restrict__ C,
+__global__ __launch_bounds__(GT) void gemm_b3_kernel(Planes A, Planes B, float *__restrict__ C,
                                                       long ldc, int M, int N, int K,
                                                       const float *__restrict__ d, float tau,
                                                       const float *__restrict__ f,
@@ -112,87 +115,126 @@ __global__ __launch_bounds__(256) void gemm_b3_kernel(Planes A, Planes B, float 
   u16(*sm)[4][BM * PK] = reinterpret_cast<u16(*)[4][BM * PK]>(gsm);  // [buffer][Ah, Al, Bh, Bl]
   double *red = reinterpret_cast<double *>(gsm + (size_t)NBUF * 4 * BM * PK * sizeof(u16));
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x - tm * tiles_n;
-  const int i0 = tm * BM, j0 = tn * BN;
-  const int wr = wave >> 1, wc = wave & 1;
-  // this thread's 16-byte chunks: tile rows tid / 4 and 64 + tid / 4, k
-  // offset 8 (tid % 4), of each of the four planes
-  const int lrow = tid >> 2, lk8 = (tid & 3) * 8;
-  const u16 *src[4][2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int ra = min(i0 + lrow + 64 * h, M - 1), rb = min(j0 + lrow + 64 * h, N - 1);
-    src[0][h] = A.hi + (long)ra * A.ld + lk8;
-    src[1][h] = A.lo + (long)ra * A.ld + lk8;
-    src[2][h] = B.hi + (long)rb * B.ld + lk8;
-    src[3][h] = B.lo + (long)rb * B.ld + lk8;
+  // tile of this workgroup: consecutive logical ids run on one XCD (ids are
+  // dealt round-robin over the 8 XCDs) and walk groups of GROUP_M row tiles
+  // column by column, so that the workgroups of an XCD share A rows and B
+  // columns in its L2
+  int tm, tn;
+  {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int x = b & 7, q = b >> 3, g8 = nb >> 3, rem = nb & 7;
+    const int L = x * g8 + (x < rem ? x : rem) + q;
+    const int tiles_m = nb / tiles_n;
+    const int per_group = GROUP_M * tiles_n, grp = L / per_group;
+    const int first = grp * GROUP_M, gsize = min(tiles_m - first, GROUP_M);
+    const int r = L - grp * per_group;
+    tm = first + r % gsize;
+    tn = r / gsize;
   }
-  uint4 stage[4][2];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) stage[q][h] = *reinterpret_cast<const uint4 *>(src[q][h] + k0);
-  };
-  auto put = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-        *reinterpret_cast<uint4 *>(&sm[buf][q][(lrow + 64 * h) * PK + lk8]) = stage[q][h];
-  };
+  const int i0 = tm * BM, j0 = tn * BN;
+  const int wr = wave >> 2, wc = wave & 3;  // 64-row half, 32-column quarter
+  // this thread's 16-byte chunk of each of the four planes: tile row
+  // tid / 4, k offset 8 (tid % 4)
+  const int lrow = tid >> 2, lk8 = (tid & 3) * 8;
+  const u16 *src[4];
+  {
+    const int ra = min(i0 + lrow, M - 1), rb = min(j0 + lrow, N - 1);
+    src[0] = A.hi + (long)ra * A.ld + lk8;
+    src[1] = A.lo + (long)ra * A.ld + lk8;
+    src[2] = B.hi + (long)rb * B.ld + lk8;
+    src[3] = B.lo + (long)rb * B.ld + lk8;
+  }
+  // two register stages: the loads of step s + 2 are in flight while step
+  // s runs, step s + 1 waits in the other stage for its LDS buffer
+  uint4 sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3;
+#define AR_FETCH(S, k0)                                             \
+  S##0 = *reinterpret_cast<const uint4 *>(src[0] + (k0));           \
+  S##1 = *reinterpret_cast<const uint4 *>(src[1] + (k0));           \
+  S##2 = *reinterpret_cast<const uint4 *>(src[2] + (k0));           \
+  S##3 = *reinterpret_cast<const uint4 *>(src[3] + (k0))
+#define AR_PUT(S, buf)                                                     \
+  *reinterpret_cast<uint4 *>(&sm[buf][0][lrow * PK + lk8]) = S##0;         \
+  *reinterpret_cast<uint4 *>(&sm[buf][1][lrow * PK + lk8]) = S##1;         \
+  *reinterpret_cast<uint4 *>(&sm[buf][2][lrow * PK + lk8]) = S##2;         \
+  *reinterpret_cast<uint4 *>(&sm[buf][3][lrow * PK + lk8]) = S##3
   // lane l: A[i = l % 16][k = 8 (l / 16) + e], B[k = 8 (l / 16) + e][j = l % 16]
   const int lr = lane & 15, lk = (lane >> 4) * 8;
-  struct Frags { bf8 ah[4], al[4], bh[4], bl[4]; };
+  struct Frags { bf8 ah[4], al[4], bh[2], bl[2]; };
   auto frags = [&](int buf, Frags &F) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int r = (wr * 64 + t * 16 + lr) * PK + lk;
-      const int c = (wc * 64 + t * 16 + lr) * PK + lk;
       F.ah[t] = *reinterpret_cast<const bf8 *>(&sm[buf][0][r]);
       F.al[t] = *reinterpret_cast<const bf8 *>(&sm[buf][1][r]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int c = (wc * 32 + t * 16 + lr) * PK + lk;
       F.bh[t] = *reinterpret_cast<const bf8 *>(&sm[buf][2][c]);
       F.bl[t] = *reinterpret_cast<const bf8 *>(&sm[buf][3][c]);
     }
   };
-  f4 acc[4][4];
+  f4 acc[4][2];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-  // two LDS buffers: the tiles of step s + 1 travel global -> registers
-  // while step s runs from LDS, then go to the other buffer
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  // two LDS buffers (step s in buffer s % 2) and two register stages (step
+  // s in stage s % 2): step s computes while step s + 1 goes from its stage
+  // to the other buffer and step s + 2 is fetched into the freed stage
   const int nk = K / BK;
-  fetch(0);
-  put(0);
+  AR_FETCH(sa, 0);
+  AR_PUT(sa, 0);
+  if (nk > 1) {
+    AR_FETCH(sb, BK);
+  }
   __syncthreads();
-  for (int s = 0; s < nk; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < nk) fetch((s + 1) * BK);
+  auto mma = [&](int buf) {
     Frags cur;
     frags(buf, cur);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < 2; ++b) {
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.al[a], cur.bh[b], acc[a][b], 0, 0, 0);
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ah[a], cur.bl[b], acc[a][b], 0, 0, 0);
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ah[a], cur.bh[b], acc[a][b], 0, 0, 0);
       }
-    if (s + 1 < nk) put(buf ^ 1);
+  };
+  for (int s = 0; s < nk; s += 2) {
+    // step s (stage a, buffer 0)
+    if (s + 2 < nk) {
+      AR_FETCH(sa, (s + 2) * BK);
+    }
+    mma(0);
+    if (s + 1 < nk) {
+      AR_PUT(sb, 1);
+    }
+    __syncthreads();
+    if (s + 1 >= nk) break;
+    // step s + 1 (stage b, buffer 1)
+    if (s + 3 < nk) {
+      AR_FETCH(sb, (s + 3) * BK);
+    }
+    mma(1);
+    if (s + 2 < nk) {
+      AR_PUT(sa, 0);
+    }
     __syncthreads();
   }
+#undef AR_FETCH
+#undef AR_PUT
   // epilogue: lane l holds D[i = 4 (l / 16) + e][j = l % 16] of each 16 x 16 tile
   double ss = 0.0;
   const int lj = lane & 15, li = (lane >> 4) * 4;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int i = i0 + wr * 64 + a * 16 + li + e;
-        const int j = j0 + wc * 64 + b * 16 + lj;
+        const int j = j0 + wc * 32 + b * 16 + lj;
         if (i >= M || j >= N) continue;
         const long o = (long)i * ldc + j;
         const float v = acc[a][b][e];
@@ -213,7 +255,11 @@ __global__ __launch_bounds__(256) void gemm_b3_kernel(Planes A, Planes B, float 
     for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
-    if (tid == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < GT / 64; ++w) t += red[w];
+      partial[blockIdx.x] = t;
+    }
   }
 }
 
@@ -263,7 +309,7 @@ int gemm_launch(Planes A, Planes B, float *C, long ldc, int M, int N, int K, con
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
   AR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(gemm_b3_kernel<EPI>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds));
-  hipLaunchKernelGGL(gemm_b3_kernel<EPI>, dim3(tiles_m * tiles_n), dim3(256), kGemmLds, st, A, B,
+  hipLaunchKernelGGL(gemm_b3_kernel<EPI>, dim3(tiles_m * tiles_n), dim3(GT), kGemmLds, st, A, B,
                      C, ldc, M, N, K, d, tau, f, partial, tiles_n);
   AR_HIP(hipGetLastError());
   return AR_OK;

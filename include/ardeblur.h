@@ -259,10 +259,16 @@ int ar_deblur_iterate_noalloc(ar_plan_t p, const void *g, void *x, int iters, do
  *      autotuner leaves it alone), 1 = vector ALU, 2 = matrix cores (FP16 hi/lo operands, three products,
  *      FP32 accumulation, exact power-of-two scaling; about 2^-21 relative
  *      per product against FP32's 2^-24).  This one changes results in the
- *      last bits; the batched executor always uses the vector-ALU blur. */
+ *      last bits; the batched executor always uses the vector-ALU blur.
+ *  AR_TUNE_FUSE : with the matrix-core blur and the reblurring transpose, 1 =
+ *      one kernel computes r = g - A x on the reblur's halo and y = A' r
+ *      (Anti-Reflective and Reflective plans), 0 = two kernels (default).
+ *      Same products; the residual's scale comes from a wider halo, so
+ *      results can differ in the last bits of the smallest values. */
 enum ar_tune_key { AR_TUNE_ROW_WAVES = 0, AR_TUNE_COL_WAVES = 1, AR_TUNE_ROW_EXCL = 2,
                    AR_TUNE_COL_EXCL = 3, AR_TUNE_ROW_ALGO = 4, AR_TUNE_COL_ALGO = 5,
-                   AR_TUNE_ROW_LANES = 6, AR_TUNE_COL_LANES = 7, AR_TUNE_BLUR = 8 };
+                   AR_TUNE_ROW_LANES = 6, AR_TUNE_COL_LANES = 7, AR_TUNE_BLUR = 8,
+                   AR_TUNE_FUSE = 9 };
 
 /* Set one tunable (value 0 restores the automatic choice).  Errors:
  * AR_EINVAL for an unknown key or value. */
@@ -285,8 +291,10 @@ int ar_plan_autotune(ar_plan_t p, double *best_us, void *stream);
  * kernel is launched `reps` times back to back between two HIP events on
  * `stream`; phase_us[0..4] receives the average duration per launch in
  * microseconds:
- *   0: r = g - A x (residual blur with FP64 norm partials)
- *   1: y = A' r or A^T r (transpose blur; correlation + fold for A^T)
+ *   0: r = g - A x (residual blur with FP64 norm partials); with the fused
+ *      residual and reblur (AR_TUNE_FUSE = 1), y = A' (g - A x) in one kernel
+ *   1: y = A' r or A^T r (transpose blur; correlation + fold for A^T); 0
+ *      with the fused kernel
  *   2: row pass of T~ (0 when precondition == 0)
  *   3: column pass T~ / d / T (0 when precondition == 0)
  *   4: row pass of T fused with x += tau w (the plain update when

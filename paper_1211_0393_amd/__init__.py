@@ -25,6 +25,7 @@ from ._lib import (  # noqa: F401
     AR_FILTER_TIKHONOV,
     AR_REBLUR,
     AR_TUNE_BLUR,
+    AR_TUNE_FUSE,
     AR_TUNE_COL_ALGO,
     AR_TUNE_COL_EXCL,
     AR_TUNE_COL_LANES,

@@ -28,6 +28,7 @@ AR_FNET_BINS, AR_FNET_IN, AR_FNET_HIDDEN, AR_FNET_NPARAM = 64, 65, 128, 33216
 AR_TUNE_ROW_WAVES, AR_TUNE_COL_WAVES, AR_TUNE_ROW_EXCL, AR_TUNE_COL_EXCL = 0, 1, 2, 3
 AR_TUNE_ROW_ALGO, AR_TUNE_COL_ALGO, AR_TUNE_ROW_LANES, AR_TUNE_COL_LANES = 4, 5, 6, 7
 AR_TUNE_BLUR = 8
+AR_TUNE_FUSE = 9
 
 STATUS = {
     0: "AR_OK", -1: "AR_EINVAL", -2: "AR_ESHAPE", -3: "AR_EPSF", -4: "AR_EALIAS",

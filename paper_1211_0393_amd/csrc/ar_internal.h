@@ -146,7 +146,7 @@ struct ar_plan_s {
   int filter = AR_FILTER_TIKHONOV;
   double filter_param = 1e-2;
   // launch tunables (0 = automatic), set by ar_plan_tune / ar_plan_autotune
-  int tune[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int tune[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // dense transform matrices of AR_F32_BF16X3 as BF16 hi / lo planes (m
   // rows of m padded to a multiple of 32): T~_{n1}, T_{n1}, T~_{n2}, T_{n2};
   // an FP32 n1 x n2 scratch and the planes of one image operand
@@ -232,6 +232,11 @@ int conv_mfma_blocks(int m1, int m2);
 int mfma_frag_build(ar_plan_s *p, double hmax, hipStream_t st);
 int conv_mfma_launch(const ar_plan_s *p, const void *in, void *out, bool reverse,
                      const void *gsub, double *partial, hipStream_t st);
+// the residual and the reblur in one matrix-core kernel: y = A' (g - A x)
+// with the ||r||^2 partials of conv_mfma_blocks tiles (AR / Reflective plans)
+bool conv2_mfma_ok(const ar_plan_s *p);
+int conv2_mfma_launch(const ar_plan_s *p, const void *x, const void *g, void *y, double *partial,
+                      hipStream_t st);
 // batched fold of the extended-grid correlation (in = ext, out = y)
 int fold_batch_launch(int dtype, const ConvJob *jobs, int count, int n1max, int n2max,
                       int qmax, hipStream_t st);

@@ -78,19 +78,23 @@ struct IterArgs {
 int enqueue(ar_plan_s *p, const IterArgs &a, hipStream_t st) {
   int rc = AR_OK;
   if (a.want_rre && (rc = sumsq_launch(p, a.f, a.f_part, nullptr, st)) != AR_OK) return rc;
+  const bool fused = a.tmode == AR_REBLUR && conv2_mfma_ok(p);
   for (int k = 0; k < a.iters; ++k) {
-    // r = g - A x_k   (+ ||r||^2 partials)
-    rc = conv_launch(p, a.x, p->r, p->w_fwd, 0, 0, p->n1, p->n2, false, a.g,
-                     a.res_part ? a.res_part + (size_t)k * a.bc : nullptr, nullptr, st);
-    if (rc != AR_OK) return rc;
-    // y = A' r  or  A^T r
-    if (a.tmode == AR_REBLUR) {
-      rc = conv_launch(p, p->r, p->y, p->w_rev, 0, 0, p->n1, p->n2, false, nullptr, nullptr,
-                       nullptr, st);
+    double *rp = a.res_part ? a.res_part + (size_t)k * a.bc : nullptr;
+    if (fused) {
+      // y = A' (g - A x_k) in one kernel (+ ||r||^2 partials)
+      rc = conv2_mfma_launch(p, a.x, a.g, p->y, rp, st);
     } else {
-      rc = conv_launch(p, p->r, p->ext, p->w_rev, -p->q1, -p->q2, p->n1 + 2 * p->q1,
-                       p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st, true);
-      if (rc == AR_OK) rc = fold_launch(p, p->ext, p->y, st);
+      // r = g - A x_k   (+ ||r||^2 partials), then y = A' r  or  A^T r
+      rc = conv_launch(p, a.x, p->r, p->w_fwd, 0, 0, p->n1, p->n2, false, a.g, rp, nullptr, st);
+      if (rc == AR_OK && a.tmode == AR_REBLUR) {
+        rc = conv_launch(p, p->r, p->y, p->w_rev, 0, 0, p->n1, p->n2, false, nullptr, nullptr,
+                         nullptr, st);
+      } else if (rc == AR_OK) {
+        rc = conv_launch(p, p->r, p->ext, p->w_rev, -p->q1, -p->q2, p->n1 + 2 * p->q1,
+                         p->n2 + 2 * p->q2, true, nullptr, nullptr, nullptr, st, true);
+        if (rc == AR_OK) rc = fold_launch(p, p->ext, p->y, st);
+      }
     }
     if (rc != AR_OK) return rc;
     double *up = a.rre_part ? a.rre_part + (size_t)k * a.bu : nullptr;

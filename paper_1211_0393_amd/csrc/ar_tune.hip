@@ -22,6 +22,7 @@ static bool tune_valid(int key, int value) {
       return value == 0 || value == 1 || value == 2 || value == 4;
     case AR_TUNE_ROW_EXCL:
     case AR_TUNE_COL_EXCL:
+    case AR_TUNE_FUSE:
       return value == 0 || value == 1;
     case AR_TUNE_ROW_ALGO:
     case AR_TUNE_COL_ALGO:
@@ -35,7 +36,7 @@ static bool tune_valid(int key, int value) {
 extern "C" int ar_plan_tune(ar_plan_t p, int key, int value) {
   if (!p) return fail(AR_EINVAL, "ar_plan_tune: null plan");
   if (!tune_valid(key, value)) return fail(AR_EINVAL, "ar_plan_tune: bad key or value");
-  if (p->bc != AR_BC_ANTIREFLECTIVE && key != AR_TUNE_BLUR)
+  if (p->bc != AR_BC_ANTIREFLECTIVE && key != AR_TUNE_BLUR && key != AR_TUNE_FUSE)
     return fail(AR_EUNSUPPORTED, "ar_plan_tune: transform tunables are Anti-Reflective only");
   if (key == AR_TUNE_BLUR && value == 2 && !p->mfma_frag_fwd)
     return fail(AR_EUNSUPPORTED, "ar_plan_tune: the matrix-core blur needs an FP32 plan created "
@@ -46,7 +47,7 @@ extern "C" int ar_plan_tune(ar_plan_t p, int key, int value) {
 
 extern "C" int ar_plan_get_tune(ar_plan_t p, int key, int *value) {
   if (!p || !value) return fail(AR_EINVAL, "ar_plan_get_tune: null argument");
-  if (key < 0 || key > AR_TUNE_BLUR) return fail(AR_EINVAL, "ar_plan_get_tune: bad key");
+  if (key < 0 || key > AR_TUNE_FUSE) return fail(AR_EINVAL, "ar_plan_get_tune: bad key");
   *value = p->tune[key];
   return AR_OK;
 }
@@ -161,12 +162,16 @@ extern "C" int ar_iterate_profile(ar_plan_t p, const void *g, const void *x, int
   // the five phases of one iteration; each is timed as `reps` back-to-back
   // launches between two events (its inputs are left in place by one
   // untimed iteration first, and no timed launch overwrites its own input)
+  // with the fused residual and reblur, phase 0 is that kernel and phase 1 empty
+  const bool fused = tmode == AR_REBLUR && conv2_mfma_ok(p);
   auto phase = [&](int k) -> int {
     switch (k) {
       case 0:
+        if (fused) return conv2_mfma_launch(p, xw, g, p->y, nullptr, st);
         return conv_launch(p, xw, p->r, p->w_fwd, 0, 0, p->n1, p->n2, false, g, nullptr, nullptr,
                            st);
       case 1:
+        if (fused) return AR_OK;
         if (tmode == AR_REBLUR)
           return conv_launch(p, p->r, p->y, p->w_rev, 0, 0, p->n1, p->n2, false, nullptr,
                              nullptr, nullptr, st);

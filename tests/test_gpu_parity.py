@@ -124,6 +124,47 @@ def test_blur_engines_fp32(n1, n2, q1, q2, engine):
     assert max(e1, e2, e3, e4) <= 1e-6
 
 
+@pytest.mark.parametrize("bc", ["antireflective", "reflective"])
+@pytest.mark.parametrize("n1,n2,q1,q2", [(33, 40, 3, 4), (64, 64, 7, 7), (100, 77, 5, 2),
+                                         (130, 200, 10, 8), (1024, 1024, 7, 7), (17, 9, 0, 3)])
+def test_fused_residual_reblur(n1, n2, q1, q2, bc):
+    """The fused matrix-core kernel y = A' (g - A x) (AR_TUNE_FUSE 1) against
+    the two separate kernels over three preconditioned iterations: the same
+    products, but the residual's power-of-two scale comes from the fused
+    kernel's wider x halo, which moves FP16 rounding of the smallest values
+    (bitwise equal on most shapes): iterates within 1e-6 relative max-abs,
+    residual norms within 1e-6; one fused plain step against the oracle at
+    1e-6."""
+    H = synth.psf_random(q1, q2, seed=n1 + 7 * n2 + q1)
+    X = image(n1, n2, seed=n1 * 3 + n2, dt="f32")
+    G = image(n1, n2, seed=n1 + 5 * n2, dt="f32")
+    out = {}
+    with P.Plan(n1, n2, H, dtype="f32", bc=bc) as plan:
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, 0.2)
+        g = dev(G, torch.float32)
+        for fuse in (1, 0):
+            plan.ar_plan_tune(P.AR_TUNE_FUSE, fuse)
+            x = dev(X, torch.float32)
+            rc, res, _, _ = plan.ar_deblur_iterate(g, x, 3, want_resnorm=True)
+            assert rc == 0
+            out[fuse] = (host(x), res)
+        plan.ar_plan_tune(P.AR_TUNE_FUSE, 1)
+        xf = dev(X, torch.float32)
+        rc, res1, _, _ = plan.ar_deblur_iterate(g, xf, 1, precondition=False, want_resnorm=True)
+    (x1, r1), (x0, r0) = out[1], out[0]
+    d = np.max(np.abs(x0 - x1)) / np.max(np.abs(x1))
+    say(f"  fused vs two kernels {n1}x{n2} q=({q1},{q2}) {bc}: max-abs {d:.2e}, "
+        f"bitwise {np.array_equal(x0, x1)}")
+    assert d <= 1e-6
+    assert np.max(np.abs(r0 - r1) / r1) <= 1e-6
+    refl = bc == "reflective"
+    blur = (lambda A: O.bc.blur_bc(A, H, "reflective")) if refl else (lambda A: O.blur(A, H))
+    reb = (lambda A: O.bc.reblur_bc(A, H, "reflective")) if refl else (lambda A: O.reblur(A, H))
+    R = G - blur(X)
+    assert rel(host(xf), X + reb(R)) <= 1e-6
+    assert abs(res1[0] - np.linalg.norm(R)) <= 1e-6 * np.linalg.norm(R)
+
+
 def test_blur_matrix_core_scaling_extremes():
     """Per-tile power-of-two scaling keeps the FP16 operands in range for
     tiny, huge and mixed-magnitude images (relative error 1e-6), and

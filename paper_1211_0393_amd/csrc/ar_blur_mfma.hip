@@ -14,8 +14,8 @@
 // weight, chosen at plan time); the output is multiplied back by
 // 2^-(ex + ew).
 //
-// A workgroup owns a 64 x 32 output tile (four waves of 16 rows, two
-// column blocks each).  It stages the (64 + 2 q1) x 48 halo in LDS as two
+// A workgroup owns a 128 x 32 output tile (eight waves of 16 rows, two
+// column blocks each).  It stages the (128 + 2 q1) x 48 halo in LDS as two
 // FP16 planes (hi, lo) after applying the plan's extension rule on load;
 // the weight fragments W_a (hi and lo) are prepared once per PSF and staged
 // in LDS by each workgroup, and the A fragment of PSF row a + 1 is obtained
@@ -42,7 +42,9 @@ __device__ __forceinline__ i4 row_up(i4 x) {
   return y;
 }
 
-constexpr int MT_H = 64;               // output rows per tile (4 waves x 16)
+constexpr int MW = 8;                  // wavefronts per workgroup
+constexpr int MT_THREADS = 64 * MW;
+constexpr int MT_H = 16 * MW;          // output rows per tile (16 per wavefront)
 constexpr int MT_W = 32;               // output columns per tile (2 blocks of 16)
 constexpr int MHW = MT_W - 16 + 32;    // halo columns: the last block's 32-wide window
 constexpr int MPITCH = MHW + 8;        // 56 halves = 112 bytes: 8 rows hit 8 distinct 16-byte slots
@@ -81,22 +83,22 @@ __global__ void mfma_frag_kernel(const double *__restrict__ H, int q1, int q2, i
 }
 
 template <int Q1>
-__global__ __launch_bounds__(256) void conv_mfma_kernel(
+__global__ __launch_bounds__(MT_THREADS) void conv_mfma_kernel(
     const float *__restrict__ in, float *__restrict__ out, const h8 *__restrict__ frag, int n1,
     int n2, int q2, int ext_mode, float wscale_inv, const float *__restrict__ gsub,
     double *__restrict__ partial, int tiles_x) {
   constexpr int K1 = 2 * Q1 + 1;
   constexpr int LH = MT_H + 2 * Q1;
   constexpr int HP = MHW / 2;                  // column pairs per halo row
-  constexpr int NP = (LH * HP + 255) / 256;    // pairs per thread
+  constexpr int NP = (LH * HP + MT_THREADS - 1) / MT_THREADS;    // pairs per thread
   constexpr int NB = 2 * K1 * 64;              // weight fragments (h8) of the tile
-  constexpr int NF = (NB + 255) / 256;
+  constexpr int NF = (NB + MT_THREADS - 1) / MT_THREADS;
   // hi plane and lo plane of the halo (border tiles stage FP32 values here
-  // first), and the weight fragments shared by the four waves
+  // first), and the weight fragments shared by the eight waves
   __shared__ __align__(16) _Float16 sbuf[2 * LH * MPITCH];
   __shared__ __align__(16) h8 sfrag[NB];
-  __shared__ float redf[4];
-  __shared__ double redd[4];
+  __shared__ float redf[MW];
+  __shared__ double redd[MW];
   _Float16 *shi = sbuf, *slo = sbuf + LH * MPITCH;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int logical = mfma_xcd_remap(blockIdx.x, gridDim.x);
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
   h8 fr[NF];
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     fr[i] = gf[e < NB ? e : 0];
   }
   float gv[2][4];
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
     const bool pairs = (n2 & 1) == 0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + MT_THREADS * i;
       const int rr0 = e / HP, cc = 2 * (e - rr0 * HP);
       int ii = ib1 + (rr0 < LH ? rr0 : LH - 1);
       ii = ii < 0 ? 0 : (ii > n1 - 1 ? n1 - 1 : ii);
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
   } else {
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + MT_THREADS * i;
       const int rr0 = e / HP, cc = 2 * (e - rr0 * HP);
       const int rr = rr0 < LH ? rr0 : LH - 1;
 #pragma unroll
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
   }
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     if (e < NB) sfrag[e] = fr[i];
   }
 
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
     float *stage = reinterpret_cast<float *>(sbuf);
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + MT_THREADS * i;
       if (e < LH * HP) {
         const int rr = e / HP, cc = 2 * (e - rr * HP);
         stage[rr * MHW + cc] = v[i][0];
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
     };
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + MT_THREADS * i;
       const int rr0 = e / HP, cc0 = 2 * (e - rr0 * HP);
       const int rr = rr0 < LH ? rr0 : LH - 1;
 #pragma unroll
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
   float mx = 0.f;
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     const int cc0 = 2 * (e % HP);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -238,7 +240,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
   for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
   if (lane == 0) redf[wave] = mx;
   __syncthreads();
-  mx = fmaxf(fmaxf(redf[0], redf[1]), fmaxf(redf[2], redf[3]));
+  mx = redf[0];
+  for (int w = 1; w < MW; ++w) mx = fmaxf(mx, redf[w]);
   int ex = 0;
   if (mx > 0.f && mx <= 3.0e38f) {
     int E;
@@ -250,7 +253,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
   typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     if (e < LH * HP) {
       const int rr = e / HP, cc = 2 * (e - rr * HP);
       h2 hh, ll;
@@ -327,11 +330,15 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
     for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
     if (lane == 0) redd[wave] = ss;
     __syncthreads();
-    if (tid == 0) gmem(partial)[blockIdx.x] = ((redd[0] + redd[1]) + redd[2]) + redd[3];
+    if (tid == 0) {
+      double t = redd[0];
+      for (int w = 1; w < MW; ++w) t += redd[w];
+      gmem(partial)[blockIdx.x] = t;
+    }
   }
 }
 
-// Residual and reblur fused: y = A' (g - A x) for one 64 x 32 tile of y,
+// Residual and reblur fused: y = A' (g - A x) for one 128 x 32 tile of y,
 // with the residual's ||r||^2 partial over the tile.  The reblur needs r on
 // its (64 + 2 q1) x 48 halo; the kernel computes r there itself, in 16 x 16
 // blocks of the same banded Toeplitz products (the region [r0 - q1, r0 - q1
@@ -343,7 +350,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
 // order of the ||r||^2 partial differs.  Anti-Reflective and Reflective
 // extensions only (a periodic ghost lies across the image).
 template <int Q1>
-__global__ __launch_bounds__(256) void conv2_mfma_kernel(
+__global__ __launch_bounds__(MT_THREADS) void conv2_mfma_kernel(
     const float *__restrict__ in, const float *__restrict__ gsub, float *__restrict__ out,
     const h8 *__restrict__ frag_fwd, const h8 *__restrict__ frag_rev, int n1, int n2, int q2,
     int ext_mode, float wscale_inv, double *__restrict__ partial, int tiles_x) {
@@ -351,16 +358,16 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   constexpr int RB = (MT_H + 2 * Q1 + 15) / 16;  // 16-row blocks of the r region
   constexpr int RH = 16 * RB;                    // rows of the r region
   constexpr int NBLK = 3 * RB;                   // 16 x 16 blocks of the r region
-  constexpr int MB = (NBLK + 3) / 4;             // blocks per wave
+  constexpr int MB = (NBLK + MW - 1) / MW;       // blocks per wave
   constexpr int LH1 = RH + 2 * Q1;               // x halo rows
   constexpr int W1 = 64, P1 = W1 + 8;            // x halo columns and pitch (halves)
   constexpr int HP1 = W1 / 2;
-  constexpr int NP1 = (LH1 * HP1 + 255) / 256;
+  constexpr int NP1 = (LH1 * HP1 + MT_THREADS - 1) / MT_THREADS;
   constexpr int LH2 = MT_H + 2 * Q1;             // rows of the reblur's halo
   constexpr int HP2 = MHW / 2;
-  constexpr int NP2 = (LH2 * HP2 + 255) / 256;
+  constexpr int NP2 = (LH2 * HP2 + MT_THREADS - 1) / MT_THREADS;
   constexpr int NB = 2 * K1 * 64;
-  constexpr int NF = (NB + 255) / 256;
+  constexpr int NF = (NB + MT_THREADS - 1) / MT_THREADS;
   // LDS: the x planes, later (after the r products) the FP32 r region and
   // the reblur's planes; the weight fragments of the current product
   constexpr int XPL = 2 * LH1 * P1 * 2;
@@ -369,8 +376,8 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   constexpr int UA = XPL > RST + RPL ? XPL : RST + RPL;
   __shared__ __align__(16) unsigned char sA[UA];
   __shared__ __align__(16) h8 sfrag[NB];
-  __shared__ float redf[4];
-  __shared__ double redd[4];
+  __shared__ float redf[MW];
+  __shared__ double redd[MW];
   _Float16 *xhi = reinterpret_cast<_Float16 *>(sA), *xlo = xhi + LH1 * P1;
   float *rs = reinterpret_cast<float *>(sA);
   _Float16 *shi = reinterpret_cast<_Float16 *>(sA + RST), *slo = shi + LH2 * MPITCH;
@@ -391,14 +398,14 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   h8 ff[NF], fb[NF];
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     ff[i] = gff[e < NB ? e : 0];
     fb[i] = gfr[e < NB ? e : 0];
   }
   float gv[MB][4];
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
-    const int id = wave + 4 * m;
+    const int id = wave + MW * m;
     const int rb = (id < NBLK ? id : 0) / 3, cb = (id < NBLK ? id : 0) % 3;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -415,7 +422,7 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
     const bool pairs = (n2 & 1) == 0;
 #pragma unroll
     for (int i = 0; i < NP1; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + MT_THREADS * i;
       const int rw = e / HP1, cc = 2 * (e - rw * HP1);
       int ii = xb1 + (rw < LH1 ? rw : LH1 - 1);
       ii = ii < 0 ? 0 : (ii > n1 - 1 ? n1 - 1 : ii);
@@ -438,7 +445,7 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   }
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     if (e < NB) sfrag[e] = ff[i];
   }
   // window position of an image row (column) a rule references; the clamp
@@ -452,7 +459,7 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
     float *stage = reinterpret_cast<float *>(sA);
 #pragma unroll
     for (int i = 0; i < NP1; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + MT_THREADS * i;
       if (e < LH1 * HP1) {
         const int rw = e / HP1, cc = 2 * (e - rw * HP1);
         stage[rw * W1 + cc] = v[i][0];
@@ -462,7 +469,7 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NP1; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + MT_THREADS * i;
       const int rw0 = e / HP1, cc0 = 2 * (e - rw0 * HP1);
       const int rw = rw0 < LH1 ? rw0 : LH1 - 1;
 #pragma unroll
@@ -485,7 +492,7 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   float mx = 0.f;
 #pragma unroll
   for (int i = 0; i < NP1; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     const int cc0 = 2 * (e % HP1);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -496,7 +503,8 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
   if (lane == 0) redf[wave] = mx;
   __syncthreads();
-  mx = fmaxf(fmaxf(redf[0], redf[1]), fmaxf(redf[2], redf[3]));
+  mx = redf[0];
+  for (int w = 1; w < MW; ++w) mx = fmaxf(mx, redf[w]);
   auto scale_exp = [](float m) {
     int ex = 0;
     if (m > 0.f && m <= 3.0e38f) {
@@ -511,7 +519,7 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int i = 0; i < NP1; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     if (e < LH1 * HP1) {
       const int rw = e / HP1, cc = 2 * (e - rw * HP1);
       h2 hh, ll;
@@ -529,11 +537,11 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   __syncthreads();
 
   // r = g - A x on this wave's 16 x 16 blocks of the r region (block id =
-  // wave + 4 m: row block id / 3, column block id % 3)
+  // wave + MW m: row block id / 3, column block id % 3)
   float rv[MB][4];
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
-    const int id = wave + 4 * m;
+    const int id = wave + MW * m;
     if (id >= NBLK) break;
     const int rb = id / 3, cb = id % 3;
     const _Float16 *hrow = xhi + (16 * rb + lr) * P1 + 16 * cb + kg * 8;
@@ -563,7 +571,7 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   // r to its FP32 region; the reblur's weights to LDS
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
-    const int id = wave + 4 * m;
+    const int id = wave + MW * m;
     if (id >= NBLK) break;
     const int rb = id / 3, cb = id % 3;
 #pragma unroll
@@ -571,14 +579,14 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   }
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     if (e < NB) sfrag[e] = fb[i];
   }
   __syncthreads();
   // ||r||^2 over the tile's own pixels (rows Q1.., columns 8.. of the region)
   if (partial) {
     double ss = 0.0;
-    for (int e = tid; e < MT_H * MT_W; e += 256) {
+    for (int e = tid; e < MT_H * MT_W; e += MT_THREADS) {
       const int i = e / MT_W, j = e - i * MT_W;
       if (r0 + i < n1 && c0 + j < n2) {
         const double t = (double)rs[(Q1 + i) * MHW + 8 + j];
@@ -594,7 +602,7 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   float w[NP2][2];
 #pragma unroll
   for (int i = 0; i < NP2; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     const int rw0 = e / HP2, cc0 = 2 * (e - rw0 * HP2);
     const int rw = rw0 < LH2 ? rw0 : LH2 - 1;
 #pragma unroll
@@ -625,12 +633,17 @@ __global__ __launch_bounds__(256) void conv2_mfma_kernel(
   __syncthreads();  // redf reuse
   if (lane == 0) redf[wave] = mx;
   __syncthreads();
-  mx = fmaxf(fmaxf(redf[0], redf[1]), fmaxf(redf[2], redf[3]));
+  mx = redf[0];
+  for (int w = 1; w < MW; ++w) mx = fmaxf(mx, redf[w]);
   const int ex2 = scale_exp(mx);
-  if (partial && tid == 0) gmem(partial)[blockIdx.x] = ((redd[0] + redd[1]) + redd[2]) + redd[3];
+  if (partial && tid == 0) {
+    double t = redd[0];
+    for (int w = 1; w < MW; ++w) t += redd[w];
+    gmem(partial)[blockIdx.x] = t;
+  }
 #pragma unroll
   for (int i = 0; i < NP2; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + MT_THREADS * i;
     if (e < LH2 * HP2) {
       const int rw = e / HP2, cc = 2 * (e - rw * HP2);
       h2 hh, ll;
@@ -717,7 +730,7 @@ int conv2_mfma_launch(const ar_plan_s *p, const void *x, const void *g, void *y,
     return fail(AR_EUNSUPPORTED, "fused matrix-core residual and reblur: AR or Reflective only");
 #define AR_MFMA2_CASE(QQ)                                                                     \
   case QQ:                                                                                    \
-    hipLaunchKernelGGL((conv2_mfma_kernel<QQ>), dim3(blocks), dim3(256), 0, st, tx, tg, ty,   \
+    hipLaunchKernelGGL((conv2_mfma_kernel<QQ>), dim3(blocks), dim3(MT_THREADS), 0, st, tx, tg, ty,   \
                        ff, fr, p->n1, p->n2, p->q2, em, wsi, partial, tiles_x);               \
     break;
   switch (p->q1) {
@@ -763,7 +776,7 @@ int conv_mfma_launch(const ar_plan_s *p, const void *in, void *out, bool reverse
   const int em = plan_ext_mode(p);
 #define AR_MFMA_CASE(QQ)                                                                      \
   case QQ:                                                                                    \
-    hipLaunchKernelGGL((conv_mfma_kernel<QQ>), dim3(blocks), dim3(256), 0, st, ti, to, frag,   \
+    hipLaunchKernelGGL((conv_mfma_kernel<QQ>), dim3(blocks), dim3(MT_THREADS), 0, st, ti, to, frag,   \
                        p->n1, p->n2, p->q2, em, wsi, tg, partial, tiles_x);                   \
     break;
   switch (p->q1) {

@@ -131,24 +131,20 @@ __global__ __launch_bounds__(MT_THREADS) void conv_mfma_kernel(
       }
   }
   // Halo as column pairs.  Tiles inside the image load it directly (as
-  // aligned pairs when rows have an even length); border tiles under
-  // Anti-Reflective or Reflective BCs load the window clamped to the image
-  // (every ghost pixel is a combination of pixels in that window) and apply
-  // the rule from LDS below; periodic border tiles apply the rule on load
-  // (their ghosts come from the far side of the image).
+  // aligned pairs when rows have an even length); border tiles evaluate the
+  // plan's extension rule on load, every position from its (up to four)
+  // image pixels (the same arithmetic as a rule applied to staged pixels,
+  // and measured faster than staging the window in LDS first).
   const Gl<float> *gin = gmem(in);
   const bool inside = ib1 >= 0 && ib2 + lo_c >= 0 && ib1 + LH <= n1 && ib2 + hi_c <= n2;
-  const bool wrap = !inside && ext_mode == EXT_PERIODIC;
   float v[NP][2];
-  if (!wrap) {
+  if (inside) {
     const bool pairs = (n2 & 1) == 0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       const int e = tid + MT_THREADS * i;
       const int rr0 = e / HP, cc = 2 * (e - rr0 * HP);
-      int ii = ib1 + (rr0 < LH ? rr0 : LH - 1);
-      ii = ii < 0 ? 0 : (ii > n1 - 1 ? n1 - 1 : ii);
-      const Gl<float> *row = gin + (size_t)ii * n2;
+      const Gl<float> *row = gin + (size_t)(ib1 + (rr0 < LH ? rr0 : LH - 1)) * n2;
       if (pairs) {
         int jj = ib2 + cc;
         jj = jj < 0 ? 0 : (jj > n2 - 2 ? n2 - 2 : jj);
@@ -179,52 +175,6 @@ __global__ __launch_bounds__(MT_THREADS) void conv_mfma_kernel(
   for (int i = 0; i < NF; ++i) {
     const int e = tid + MT_THREADS * i;
     if (e < NB) sfrag[e] = fr[i];
-  }
-
-  if (!inside && !wrap) {
-    // border tile: the clamped window to LDS as FP32, then every position's
-    // extension rule evaluated from it
-    float *stage = reinterpret_cast<float *>(sbuf);
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      const int e = tid + MT_THREADS * i;
-      if (e < LH * HP) {
-        const int rr = e / HP, cc = 2 * (e - rr * HP);
-        stage[rr * MHW + cc] = v[i][0];
-        stage[rr * MHW + cc + 1] = v[i][1];
-      }
-    }
-    __syncthreads();
-    // window position of an image row (column) that the rule references
-    // (it lies in the clamped window; the clamp only guards dead positions)
-    auto wr = [&](int x) { const int t = x - ib1; return t < 0 ? 0 : (t > LH - 1 ? LH - 1 : t); };
-    auto wc = [&](int x) {
-      int t = x - ib2;
-      // clamped loads put image column c at window column c - ib2 when the
-      // window is inside the image; past the image edges the staged values
-      // repeat the edge pair, which no rule reads
-      return t < 0 ? 0 : (t > MHW - 1 ? MHW - 1 : t);
-    };
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      const int e = tid + MT_THREADS * i;
-      const int rr0 = e / HP, cc0 = 2 * (e - rr0 * HP);
-      const int rr = rr0 < LH ? rr0 : LH - 1;
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int cc = cc0 + u;
-        const int ii = ib1 + rr, jj = ib2 + cc;
-        // pixels of the image keep their loaded value; only ghosts take the rule
-        if (ii < 0 || ii > n1 - 1 || jj < 0 || jj > n2 - 1) {
-          const Rule ra = ar_rule(ii, n1, Q1, ext_mode), rb = ar_rule(jj, n2, q2, ext_mode);
-          const float *s0 = stage + wr(ra.i0) * MHW, *s1 = stage + wr(ra.i1) * MHW;
-          const float x = ra.w0 * (rb.w0 * s0[wc(rb.i0)] + rb.w1 * s0[wc(rb.i1)]) +
-                          ra.w1 * (rb.w0 * s1[wc(rb.i0)] + rb.w1 * s1[wc(rb.i1)]);
-          v[i][u] = (ra.dead | rb.dead) ? 0.f : x;
-        }
-      }
-    }
-    __syncthreads();
   }
   float mx = 0.f;
 #pragma unroll

@@ -246,11 +246,18 @@ __device__ __forceinline__ void st3(V2<T> *U, const Regs<T, G> &R, int s) {
   }
 }
 
+// FP64 kernels load the per-lane constants after the radix-31 stage, whose
+// 31 inputs and 30 pair sums would otherwise share the registers with them.
+template <typename T>
+constexpr bool kLateRegs = std::is_same<T, double>::value;
+
 // The FFT of the staged sequence into U (natural order); ends at a barrier.
 template <typename T, int G>
-__device__ __forceinline__ void fft1023(V2<T> *U, const T *Z, const Regs<T, G> &R, int g,
-                                        int l64, int s) {
+__device__ __forceinline__ void fft1023(V2<T> *U, const T *Z, Regs<T, G> &R,
+                                        const V2<T> *__restrict__ tw,
+                                        const V2<T> *__restrict__ post, int g, int l64, int s) {
   st31<T, G>(U, reinterpret_cast<const V2<T> *>(Z), g, l64);
+  if constexpr (kLateRegs<T>) R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
   __syncthreads();
   if constexpr (G == 4) st11<T, G>(U, R, l64 + 64 * (g & 1), g >> 1);
   else st11<T, G>(U, R, s, 0);
@@ -347,7 +354,7 @@ __global__ __launch_bounds__(kWgMax) void rows1023_kernel(
     }
   }
   Regs<T, G> R;
-  R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
+  if constexpr (!kLateRegs<T>) R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
 #pragma unroll
   for (int c = 0; c < NQ; ++c) {
     const int j0 = 4 * (s + SL * c);
@@ -357,7 +364,7 @@ __global__ __launch_bounds__(kWgMax) void rows1023_kernel(
     zstore4<T>(L.Z, j0, z);
   }
   __syncthreads();
-  fft1023<T, G>(L.U, L.Z, R, g, l64, s);
+  fft1023<T, G>(L.U, L.Z, R, tw, post, g, l64, s);
   double ss = 0.0;
   TS o[NQ][4];
 #pragma unroll
@@ -436,7 +443,7 @@ __global__ __launch_bounds__(kWgMax) void cols1023_kernel(
     for (int c = 0; c < NQ; ++c) vload<4>(dv[c], dcol + 4 * (s + SL * c), va_d);
   }
   Regs<T, G> R;
-  R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
+  if constexpr (!kLateRegs<T>) R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
   T e0 = T(0), e1 = T(0);
 #pragma unroll
   for (int c = 0; c < W; ++c)
@@ -454,7 +461,7 @@ __global__ __launch_bounds__(kWgMax) void cols1023_kernel(
     }
   }
   __syncthreads();
-  fft1023<T, G>(L.U, L.Z, R, g, l64, s);
+  fft1023<T, G>(L.U, L.Z, R, tw, post, g, l64, s);
   if constexpr (MODE == COL_FWD_D_INV) {
     // d_k (T~ y)_k, staged as the odd extension of the inverse pass's input;
     // its endpoints go to the two spare words past the extension
@@ -475,7 +482,7 @@ __global__ __launch_bounds__(kWgMax) void cols1023_kernel(
     __syncthreads();
     e0 = L.Z[kZ];
     e1 = L.Z[kZ + 1];
-    fft1023<T, G>(L.U, L.Z, R, g, l64, s);
+    fft1023<T, G>(L.U, L.Z, R, tw, post, g, l64, s);
   }
   // outputs in natural order over the staging row, then row by row
 #pragma unroll

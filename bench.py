@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -48,6 +49,17 @@ FP32_VECTOR_TFLOPS = 157.3  # 256 CUs x 128 FP32 FMA lanes/clk x 2 flop x 2.4 GH
 # between the passes and halo re-reads are implementation traffic.
 ALG_BYTES = {"residual": 12, "reblur": 8, "row_fwd": 4, "col": 4, "row_inv": 8}
 STEP_BYTES = sum(ALG_BYTES.values())   # 36 B per pixel-iteration
+
+
+def step_flops(n1, n2, taps):
+    """Algorithmic flops per pixel-iteration: the blur and the reblur (2 P
+    each, P = PSF taps), the forward and inverse 2-D AR transforms at the
+    ideal FFT count 5 log2(2 (m - 1)) per axis and direction (m the axis
+    length: the DST-I of the interior through a length-2(m-1) real FFT),
+    and the residual, filter and update (3).  A fixed convention, like the
+    36 B: the radix-31/11/3 stages and the packing cost more than this."""
+    ft = 2 * 5 * math.log2(2 * (n1 - 1)) + 2 * 5 * math.log2(2 * (n2 - 1))
+    return 4 * taps + ft + 3
 STABLE_ALPHA = 0.2          # 1024^2 motion PSF: I - D A'A has spectral radius ~1
 BATCH_STABLE_ALPHA = 0.5    # every batched Gaussian PSF: spectral radius <= 1
 PLAIN_CAP = 3000            # iteration cap of the unpreconditioned run to its best RRE
@@ -686,6 +698,11 @@ def main():
     step_roof = {"bound": "hbm", "achieved": round(step_gbs, 2), "peak": HBM_PEAK_GBS,
                  "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                  "bytes_per_pixel_iteration": STEP_BYTES, "us_per_step": round(t_step * 1e6, 2)}
+    fpx = step_flops(n, n, P_taps)
+    step_tf = fpx * npx / t_step / 1e12
+    step_alu = {"bound": "alu", "achieved": round(step_tf, 2), "peak": alu_peak,
+                "unit": "TFLOP/s", "frac": round(step_tf / alu_peak, 4), "peak_kind": alu_kind,
+                "flops_per_pixel_iteration": round(fpx, 1)}
 
     net_path = None
     if a.learned_images >= 0:
@@ -735,6 +752,7 @@ def main():
         "tuning": dict(tuning, iteration_us=tuned_us),
         "roofline": roof,
         "step_roofline": step_roof,
+        "step_alu_roofline": step_alu,
         "kernels": rooflines,
         "blur_engines": blur_engines,
         "cpu_baseline": cpu,

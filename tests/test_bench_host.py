@@ -3,6 +3,7 @@ traffic table is used only for the kernel sources it was taken on, and a
 request for more than one GPU is refused with a message."""
 
 import json
+import math
 import os
 import subprocess
 import sys
@@ -58,3 +59,11 @@ def test_algorithmic_bytes_follow_the_per_step_convention():
     assert bench.STEP_BYTES == 36
     assert bench.ALG_BYTES["row_fwd"] + bench.ALG_BYTES["col"] + bench.ALG_BYTES["row_inv"] == 16
     assert bench.FP32_VECTOR_TFLOPS == 157.3 and bench.FP64_VECTOR_TFLOPS == 78.6
+
+
+def test_step_flops_follow_the_convention():
+    # 4 P + F_T + 3 with F_T = 2 axes x 2 directions x 5 log2(2 (n - 1)):
+    # 1,123 flops per pixel-iteration at 1024^2 with a 15 x 15 PSF
+    f = bench.step_flops(1024, 1024, 225)
+    assert abs(f - (900 + 20 * math.log2(2046) + 3)) < 1e-9
+    assert 1122 < f < 1124

@@ -279,6 +279,14 @@ int wave_cols_launch_batch(const ar_plan_s *lead, const XJob *jobs, int count, i
 // plan's stage twiddles and post-processing table of that axis
 size_t x1023_lds(int W, size_t csize);
 int x1023_cap(int G);
+// Paired row pass (two rows per complex FFT; W rows per workgroup, W even,
+// G = 4 wavefronts per pair; FP64 arithmetic, cs = 8); smem >=
+// x1023_pair_lds(W / 2, cs)
+size_t x1023_pair_lds(int P, size_t csize);
+int x1023_rows_pair_launch(size_t ts, size_t cs, const void *in, void *out, int n1, int W, int G,
+                           size_t smem, int mode, const void *tw, const void *post, double alpha,
+                           double scale, double tau, const void *f_true, double *partial,
+                           hipStream_t st);
 int x1023_rows_launch(size_t ts, size_t cs, const void *in, void *out, int n1, int W, int G,
                       size_t smem, int mode, const void *tw, const void *post, double alpha,
                       double scale, double tau, const void *f_true, double *partial,

@@ -21,7 +21,9 @@
 //   * the radix-31 output pairs are dealt to the G wavefronts of a
 //     sequence (the radix-11 pairs to pairs of wavefronts when G = 4);
 //   * the column pass stages its filtered coefficients as the odd extension
-//     of the inverse transform's input directly.
+//     of the inverse transform's input directly;
+//   * rows may also run in pairs, two per complex FFT of length M (see
+//     rows1023p_kernel), which halves the FFTs of a row pass.
 // Stages (radix, stride L, twiddle offset in the plan's table): (31, 1, 0),
 // (11, 31, 30), (3, 341, 340); natural input index n = 33 d0 + 3 d1 + d2
 // sits at position d0 + 31 d1 + 341 d2 of the in-place DIT order, so
@@ -296,6 +298,10 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // LDS of one sequence: U (1024 complex), then the staged odd extension with
 // a row pitch that spreads the W sequences of a block over the banks.
 __host__ __device__ inline int zpitch(int W) { return 2048 + 64 / W; }
+// bytes of U and the staging rows of W sequences (or pairs)
+__host__ __device__ inline size_t x1023_lds_dev(int W, size_t csize) {
+  return (size_t)W * (1024 * 2 * csize + (size_t)zpitch(W) * csize);
+}
 
 template <typename T>
 struct Lds {
@@ -505,6 +511,252 @@ __global__ __launch_bounds__(kWgMax) void cols1023_kernel(
   }
 }
 
+// ------------------------------------------------------- rows in pairs
+
+// Two rows a, b of a workgroup share one complex FFT of length n = M.  With
+// f the interior of a row (f_0 = f_n = 0) its DST-I X_k = sum_j f_j
+// sin(pi j k / n) follows from the length-n DFT Y of
+//   y_j = sin(pi j / n) (f_j + f_{n-j}) + (f_j - f_{n-j}) / 2:
+// X_{2k} = -Im Y_k, and X_{2k+1} - X_{2k-1} = Re Y_k (X_{-1} = -X_1), so
+// the odd outputs are a running sum over k.  The rows ride as the real and
+// imaginary parts of w_j = y^a_j + i y^b_j; with W = DFT(w), Y^a_k =
+// (W_k + conj W_{n-k}) / 2 and Y^b_k = (W_k - conj W_{n-k}) / (2i).  Half
+// the FFTs of the one-row-per-FFT form, no odd extension, and no
+// post-processing factors.
+//
+// sin(pi j / M) for j = j0 .. j0 + 3 from the table value at j0
+template <typename T>
+__device__ __forceinline__ void sines4(const V2<T> *__restrict__ post, int j0, T (&sv)[4]) {
+  const V2<T> p = post[j0];
+  sv[0] = p.y;
+  static_for<3>([&](auto Ic) {
+    constexpr int i = decltype(Ic)::value + 1;
+    constexpr T cx = T(cos2pi(i, 2 * kM)), sx = T(sin2pi(i, 2 * kM));
+    sv[i] = p.y * cx + p.x * sx;
+  });
+}
+
+// Inclusive running sum over the SL threads of a pair in thread order for
+// two values; `slot` holds G V2 words per pair in LDS.  Ends with the
+// pair's total in `tot`; the caller's barrier after the call is not needed
+// before the next use of a different slot.
+template <typename T, int G>
+__device__ __forceinline__ V2<T> pair_scan(V2<T> v, V2<T> *slot, int g, int l64, V2<T> &tot) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T ua = __shfl_up(v.x, off, 64), ub = __shfl_up(v.y, off, 64);
+    if (l64 >= off) {
+      v.x += ua;
+      v.y += ub;
+    }
+  }
+  if (l64 == 63) slot[g] = v;
+  __syncthreads();
+  V2<T> lo{T(0), T(0)};
+  tot = V2<T>{T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const V2<T> t = slot[q];
+    if (q < g) {
+      lo.x += t.x;
+      lo.y += t.y;
+    }
+    tot.x += t.x;
+    tot.y += t.y;
+  }
+  return V2<T>{v.x + lo.x, v.y + lo.y};
+}
+
+template <typename TS, typename T, int MODE, int G>
+__global__ __launch_bounds__(kWgMax) void rows1023p_kernel(
+    const TS *__restrict__ in, TS *__restrict__ out, int n1, const V2<T> *__restrict__ tw,
+    const V2<T> *__restrict__ post, T alpha, T scale, T tau, const TS *__restrict__ f_true,
+    double *__restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int SL = 64 * G, NQ = 256 / SL;
+  const int P = (blockDim.x >> 6) / G;  // pairs per workgroup
+  const int wv = threadIdx.x >> 6;
+  const int pr = wv / G;
+  const int g = __builtin_amdgcn_readfirstlane(wv % G);
+  const int l64 = threadIdx.x & 63;
+  const int s = 64 * g + l64;
+  const int ra = xcd_remap(blockIdx.x, gridDim.x) * 2 * P + 2 * pr;
+  const bool act_a = ra < n1, act_b = ra + 1 < n1;
+  const Lds<T> L(smem_raw, P, pr);
+  V2<T> *Wv = reinterpret_cast<V2<T> *>(L.Z);
+  V2<T> *slots = reinterpret_cast<V2<T> *>(smem_raw + x1023_lds_dev(P, sizeof(T))) + NQ * G * pr;
+  const int rowa = act_a ? ra : 0, rowb = act_b ? ra + 1 : rowa;
+  const Gl<TS> *sa = gmem(in) + (size_t)rowa * kLen;
+  const Gl<TS> *sb = gmem(in) + (size_t)rowb * kLen;
+  constexpr int VB = 4 * sizeof(TS);
+  const bool va_in = aligned_to<TS>(in, VB);
+  const bool va_out = aligned_to<TS>(out, VB) && (!f_true || aligned_to<TS>(f_true, VB));
+  TS xa[NQ][4], xb[NQ][4], ma[NQ][4], mb[NQ][4], oa[NQ][4], ob[NQ][4], fa[NQ][4], fb[NQ][4];
+#pragma unroll
+  for (int c = 0; c < NQ; ++c) {
+    const int q = s + SL * c;
+    vload<4>(xa[c], sa + 4 * q, va_in);
+    vload<4>(xb[c], sb + 4 * q, va_in);
+    vload<4>(ma[c], sa + (kLen - 4) - 4 * q, va_in);
+    vload<4>(mb[c], sb + (kLen - 4) - 4 * q, va_in);
+  }
+  const T e0a = T(sa[0]), e1a = T(sa[kLen - 1]), e0b = T(sb[0]), e1b = T(sb[kLen - 1]);
+  Gl<TS> *da = gmem(out) + (size_t)rowa * kLen;
+  Gl<TS> *db = gmem(out) + (size_t)rowb * kLen;
+  if (MODE == ROW_INV_UPDATE) {
+    const Gl<TS> *fra = f_true ? gmem(f_true) + (size_t)rowa * kLen : nullptr;
+    const Gl<TS> *frb = f_true ? gmem(f_true) + (size_t)rowb * kLen : nullptr;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) {
+      const int q = s + SL * c;
+      vload<4>(oa[c], da + 4 * q, va_out);
+      vload<4>(ob[c], db + 4 * q, va_out);
+      if (f_true) {
+        vload<4>(fa[c], fra + 4 * q, va_out);
+        vload<4>(fb[c], frb + 4 * q, va_out);
+      }
+    }
+  }
+  Regs<T, G> R;
+  if constexpr (!kLateRegs<T>) R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
+  // w_j = y^a_j + i y^b_j for the lane's j = 4 q + i (j = M is no input)
+  constexpr bool ramp = MODE == ROW_FWD;
+#pragma unroll
+  for (int c = 0; c < NQ; ++c) {
+    const int j0 = 4 * (s + SL * c);
+    T sv[4];
+    sines4<T>(post, j0, sv);
+    V2<T> w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = j0 + i;
+      const T fja = zval<T>(T(xa[c][i]), j, ramp, e0a, e1a);
+      const T fna = zval<T>(T(ma[c][3 - i]), kM - j, ramp, e0a, e1a);
+      const T fjb = zval<T>(T(xb[c][i]), j, ramp, e0b, e1b);
+      const T fnb = zval<T>(T(mb[c][3 - i]), kM - j, ramp, e0b, e1b);
+      w[i].x = sv[i] * (fja + fna) + T(0.5) * (fja - fna);
+      w[i].y = sv[i] * (fjb + fnb) + T(0.5) * (fjb - fnb);
+    }
+    if (j0 + 3 < kM) {
+      T *wp = reinterpret_cast<T *>(Wv + j0);
+      lstore4<T>(wp, {w[0].x, w[0].y, w[1].x, w[1].y});
+      lstore4<T>(wp + 4, {w[2].x, w[2].y, w[3].x, w[3].y});
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) Wv[j0 + i] = w[i];
+    }
+  }
+  __syncthreads();
+  fft1023<T, G>(L.U, L.Z, R, tw, post, g, l64, s);
+  // outputs k = 4 q + i of both rows: k = 2 kappa from W_kappa and
+  // W_{M-kappa} directly, k = 2 kappa + 1 from the running sum of
+  // t_kappa = (Re W_kappa + Re W_{M-kappa}, Im W_kappa + Im W_{M-kappa})
+  // (halved at kappa = 0).  The sum over all kappa <= 511 is X_M = 0
+  // exactly; its computed value is rounding accumulated along the sum, and
+  // is removed in proportion to the terms taken (a linear bridge), which
+  // halves the error of the longest sums.
+  const T ps = T(2) * scale;
+  const T invM = T(1) / T(kM);
+  V2<T> A0[NQ], A1[NQ], C0[NQ], C1[NQ], t0[NQ], t01[NQ], ex[NQ];
+  V2<T> carry{T(0), T(0)};
+#pragma unroll
+  for (int c = 0; c < NQ; ++c) {
+    const int q = s + SL * c;
+    const int k0 = 2 * q, k1 = 2 * q + 1;
+    A0[c] = L.U[k0];
+    A1[c] = L.U[k1];
+    C0[c] = L.U[k0 == 0 ? 0 : kM - k0];
+    C1[c] = L.U[kM - k1];
+    const T h0 = k0 == 0 ? T(0.5) : T(1);
+    t0[c] = V2<T>{h0 * (A0[c].x + C0[c].x), h0 * (A0[c].y + C0[c].y)};
+    t01[c] = V2<T>{t0[c].x + (A1[c].x + C1[c].x), t0[c].y + (A1[c].y + C1[c].y)};
+    V2<T> tot;
+    const V2<T> inc = pair_scan<T, G>(t01[c], slots + G * c, g, l64, tot);
+    ex[c] = V2<T>{carry.x + inc.x - t01[c].x, carry.y + inc.y - t01[c].y};
+    carry.x += tot.x;
+    carry.y += tot.y;
+  }
+  double ss = 0.0;
+#pragma unroll
+  for (int c = 0; c < NQ; ++c) {
+    const int q = s + SL * c;
+    const T f0 = (T(2 * q) + T(0.5)) * T(1.0 / 512), f1 = (T(2 * q + 1) + T(0.5)) * T(1.0 / 512);
+    // DST values (times 4 scale) of k = 4q .. 4q + 3, rows a (x) and b (y)
+    V2<T> dv[4];
+    dv[0] = V2<T>{ps * (C0[c].y - A0[c].y), ps * (A0[c].x - C0[c].x)};
+    dv[1] = V2<T>{ps * (ex[c].x + t0[c].x - f0 * carry.x), ps * (ex[c].y + t0[c].y - f0 * carry.y)};
+    dv[2] = V2<T>{ps * (C1[c].y - A1[c].y), ps * (A1[c].x - C1[c].x)};
+    dv[3] = V2<T>{ps * (ex[c].x + t01[c].x - f1 * carry.x), ps * (ex[c].y + t01[c].y - f1 * carry.y)};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * q + i;
+      T va, vb;
+      if (MODE == ROW_FWD) {
+        va = k == 0 ? alpha * e0a : (k == kM ? alpha * e1a : dv[i].x);
+        vb = k == 0 ? alpha * e0b : (k == kM ? alpha * e1b : dv[i].y);
+      } else {
+        const T y0a = e0a / alpha, y1a = e1a / alpha, y0b = e0b / alpha, y1b = e1b / alpha;
+        const T wl = T(kM - k) * invM, wr = T(k) * invM;
+        va = k == 0 ? y0a : (k == kM ? y1a : dv[i].x + y0a * wl + y1a * wr);
+        vb = k == 0 ? y0b : (k == kM ? y1b : dv[i].y + y0b * wl + y1b * wr);
+      }
+      if (MODE == ROW_INV_UPDATE) {
+        oa[c][i] = TS(T(oa[c][i]) + tau * va);
+        ob[c][i] = TS(T(ob[c][i]) + tau * vb);
+        if (f_true) {
+          const double dfa = (double)oa[c][i] - (double)fa[c][i];
+          const double dfb = (double)ob[c][i] - (double)fb[c][i];
+          ss += (act_a ? dfa * dfa : 0.0) + (act_b ? dfb * dfb : 0.0);
+        }
+      } else {
+        oa[c][i] = TS(va);
+        ob[c][i] = TS(vb);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NQ; ++c) {
+    const int q = s + SL * c;
+    if (act_a) vstore<4>(da + 4 * q, oa[c], va_out);
+    if (act_b) vstore<4>(db + 4 * q, ob[c], va_out);
+  }
+  if (MODE == ROW_INV_UPDATE && partial) {
+    double *red = reinterpret_cast<double *>(smem_raw);
+    const double t = block_sum(ss, red);
+    if (threadIdx.x == 0) gmem(partial)[blockIdx.x] = t;
+  }
+}
+
+template <typename TS, typename T, int G>
+int rowsp_t(const void *in, void *out, int n1, int P, size_t smem, int mode, const void *tw,
+            const void *post, double alpha, double scale, double tau, const void *f_true,
+            double *partial, hipStream_t st) {
+  const dim3 grid((n1 + 2 * P - 1) / (2 * P)), block(64 * G * P);
+  auto ti = static_cast<const TS *>(in);
+  auto to = static_cast<TS *>(out);
+  auto tf = static_cast<const TS *>(f_true);
+  auto ttw = static_cast<const V2<T> *>(tw);
+  auto tp = static_cast<const V2<T> *>(post);
+  hipError_t e = hipSuccess;
+#define AR_X(MODE)                                                                              \
+  e = smem > 64 * 1024 ? hipFuncSetAttribute(                                                   \
+                             reinterpret_cast<const void *>(rows1023p_kernel<TS, T, MODE, G>), \
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)            \
+                       : hipSuccess;                                                            \
+  if (e == hipSuccess) {                                                                        \
+    hipLaunchKernelGGL((rows1023p_kernel<TS, T, MODE, G>), grid, block, smem, st, ti, to, n1,   \
+                       ttw, tp, T(alpha), T(scale), T(tau), tf, partial);                       \
+    e = hipGetLastError();                                                                      \
+  }
+  switch (mode) {
+    case ROW_FWD: AR_X(ROW_FWD) break;
+    case ROW_INV: AR_X(ROW_INV) break;
+    default: AR_X(ROW_INV_UPDATE) break;
+  }
+#undef AR_X
+  return e == hipSuccess ? AR_OK : hip_fail(e, "rows1023p_kernel launch");
+}
+
 template <typename TS, typename T, int G>
 int rows_t(const void *in, void *out, int n1, int W, int blocks, size_t smem, int mode,
            const void *tw, const void *post, double alpha, double scale, double tau,
@@ -586,6 +838,25 @@ size_t x1023_lds(int W, size_t csize) {
 }
 
 int x1023_cap(int G) { return kWgMax / (64 * G); }
+
+// U and staging of P pairs, then 4 running-sum slots (V2) per pair
+size_t x1023_pair_lds(int P, size_t csize) { return x1023_lds_dev(P, csize) + 8 * csize * P; }
+
+int x1023_rows_pair_launch(size_t ts, size_t cs, const void *in, void *out, int n1, int W, int G,
+                           size_t smem, int mode, const void *tw, const void *post, double alpha,
+                           double scale, double tau, const void *f_true, double *partial,
+                           hipStream_t st) {
+  if (G != 4 || W < 2 || W % 2 || (W / 2) * G * 64 > kWgMax ||
+      smem < x1023_pair_lds(W / 2, cs))
+    return fail(AR_EUNSUPPORTED, "length-1024 paired row pass: bad launch shape");
+  if (cs != 8) return fail(AR_EUNSUPPORTED, "length-1024 paired row pass: FP64 arithmetic only");
+  const int P = W / 2;
+  if (ts == 8)
+    return rowsp_t<double, double, 4>(in, out, n1, P, smem, mode, tw, post, alpha, scale, tau,
+                                      f_true, partial, st);
+  return rowsp_t<float, double, 4>(in, out, n1, P, smem, mode, tw, post, alpha, scale, tau,
+                                   f_true, partial, st);
+}
 
 int x1023_rows_launch(size_t ts, size_t cs, const void *in, void *out, int n1, int W, int G,
                       size_t smem, int mode, const void *tw, const void *post, double alpha,

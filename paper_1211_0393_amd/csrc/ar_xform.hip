@@ -1184,8 +1184,21 @@ static int wave_rows_d(const ar_plan_s *p, const FftPlan &fp, const void *in, vo
       return wave_rows_t<TS, T, false, 1, kPlan1023>(p, fp, w, in, out, mode, tau, f_true,
                                                      partial, jobs, count, kit, st);
     const int W = rows_waves(p, *row_plan(p));
-    const size_t smem = excl_pad(x1023_lds(W, sizeof(T)), p->tune[AR_TUNE_ROW_EXCL]);
     const double m = p->n2, M = w.M;
+    // Rows in pairs (two per complex FFT, four wavefronts per pair) for the
+    // FP64-arithmetic passes.  Their odd DST outputs come from a running
+    // sum, which in FP32 arithmetic carries about ten times the rounding of
+    // the one-row form (inverse transform 2.7e-6 against 2.7e-7 at 1024^2),
+    // so FP32 passes keep the one-row form; in FP64 the transforms stay near
+    // 5e-15.  Workgroups of one row (the ROW_WAVES tunable at 1) keep it too.
+    if (!jobs && W % 2 == 0 && sizeof(T) == 8) {
+      const size_t psmem = excl_pad(x1023_pair_lds(W / 2, sizeof(T)), p->tune[AR_TUNE_ROW_EXCL]);
+      return x1023_rows_pair_launch(sizeof(TS), sizeof(T), in, out, p->n1, W, 4, psmem,
+                                    mode, w.tw, fp.post,
+                                    std::sqrt(m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))),
+                                    std::sqrt(2.0 / M) / 4.0, tau, f_true, partial, st);
+    }
+    const size_t smem = excl_pad(x1023_lds(W, sizeof(T)), p->tune[AR_TUNE_ROW_EXCL]);
     return x1023_rows_launch(sizeof(TS), sizeof(T), in, out, p->n1, W, gl, smem, mode, w.tw,
                              fp.post, std::sqrt(m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))),
                              std::sqrt(2.0 / M) / 4.0, tau, f_true, partial, jobs, count, kit,

@@ -512,6 +512,45 @@ def test_transform_waves_per_sequence(n1, n2, lanes, dt):
 
 
 @pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("waves", [1, 2, 4])
+@pytest.mark.parametrize("n1", [1024, 1023, 33, 6, 5])
+def test_row_passes_in_pairs(n1, waves, dt):
+    """Rows of length 1024 with an even number of rows per workgroup run in
+    pairs (two rows per complex FFT: even DST outputs from the transform
+    directly, odd ones from a running sum) in FP64-arithmetic passes; FP32
+    passes and one row per workgroup keep the one-row-per-FFT form.  Both against the oracle at the transform
+    tolerances, with an odd row count (the last pair's second row absent)
+    and in place."""
+    say(f"paired rows n1={n1} waves={waves} {dt}")
+    rng = np.random.default_rng(n1 + 11 * waves)
+    X = rng.standard_normal((n1, 1024)).astype(NDT[dt]).astype(np.float64)
+    H = synth.psf_random(2, 3, seed=5)
+    with P.Plan(n1, 1024, H, dtype=dt) as plan:
+        plan.ar_plan_tune(P.AR_TUNE_ROW_WAVES, waves)
+        x = dev(X, TDT[dt])
+        c = torch.empty_like(x)
+        plan.ar_transform(x, c)
+        e = rel(host(c), O.ar_fwd(X))
+        say(f"  fwd rel err {e:.2e}")
+        assert e <= TOL_T[dt], e
+        Cq = host(c).astype(NDT[dt]).astype(np.float64)
+        xr = torch.empty_like(x)
+        plan.ar_transform_inv(dev(Cq, TDT[dt]), xr)
+        e = rel(host(xr), O.ar_inv(Cq))
+        say(f"  inv rel err {e:.2e}")
+        assert e <= TOL_T[dt], e
+        y = dev(Cq, TDT[dt])
+        plan.ar_transform_inv(y, y)
+        assert torch.equal(y, xr)
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, 0.2)
+        plan.ar_precond_solve(x, xr)
+        d = O.tikhonov(O.eigenvalues(H, n1, 1024), 0.2)
+        e = rel(host(xr), O.precond_apply(X, d))
+        say(f"  solve rel err {e:.2e}")
+        assert e <= TOL_D[dt], e
+
+
+@pytest.mark.parametrize("dt", DTS)
 @pytest.mark.parametrize("algo", [1, 2])
 @pytest.mark.parametrize("n1,n2", [(128, 96), (256, 300), (193, 385), (1024, 1024), (512, 129)])
 def test_transform_fft_forms(n1, n2, algo, dt):

@@ -536,10 +536,10 @@ __device__ __forceinline__ void sines4(const V2<T> *__restrict__ post, int j0, T
   });
 }
 
-// Inclusive running sum over the SL threads of a pair in thread order for
-// two values; `slot` holds G V2 words per pair in LDS.  Ends with the
-// pair's total in `tot`; the caller's barrier after the call is not needed
-// before the next use of a different slot.
+// Inclusive running sum over the SL threads of a pair, in thread order, of
+// two values at once; `slot` is G V2 words of LDS for this call alone (a
+// second call takes other words, so no barrier separates the two).  Returns
+// the thread's inclusive sum and leaves the pair's total in `tot`.
 template <typename T, int G>
 __device__ __forceinline__ V2<T> pair_scan(V2<T> v, V2<T> *slot, int g, int l64, V2<T> &tot) {
 #pragma unroll
@@ -653,8 +653,8 @@ __global__ __launch_bounds__(kWgMax) void rows1023p_kernel(
   // t_kappa = (Re W_kappa + Re W_{M-kappa}, Im W_kappa + Im W_{M-kappa})
   // (halved at kappa = 0).  The sum over all kappa <= 511 is X_M = 0
   // exactly; its computed value is rounding accumulated along the sum, and
-  // is removed in proportion to the terms taken (a linear bridge), which
-  // halves the error of the longest sums.
+  // is removed in proportion to the terms taken (a linear bridge), so the
+  // accumulated error is pinned at both ends of the sum.
   const T ps = T(2) * scale;
   const T invM = T(1) / T(kM);
   V2<T> A0[NQ], A1[NQ], C0[NQ], C1[NQ], t0[NQ], t01[NQ], ex[NQ];

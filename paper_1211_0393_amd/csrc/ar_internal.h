@@ -283,6 +283,12 @@ int x1023_cap(int G);
 // G = 4 wavefronts per pair; FP64 arithmetic, cs = 8); smem >=
 // x1023_pair_lds(W / 2, cs)
 size_t x1023_pair_lds(int P, size_t csize);
+// Paired column pass (two adjacent columns per complex FFT, W in {2, 4}
+// columns per workgroup dividing n2, four wavefronts per pair; FP64
+// arithmetic); smem >= x1023_pair_lds(W / 2, cs)
+int x1023_cols_pair_launch(size_t ts, size_t cs, const void *in, void *out, int n2, int W,
+                           size_t smem, int mode, const void *tw, const void *post, double alpha,
+                           double scale, const void *dT, hipStream_t st);
 int x1023_rows_pair_launch(size_t ts, size_t cs, const void *in, void *out, int n1, int W, int G,
                            size_t smem, int mode, const void *tw, const void *post, double alpha,
                            double scale, double tau, const void *f_true, double *partial,

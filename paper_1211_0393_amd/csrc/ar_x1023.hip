@@ -727,6 +727,238 @@ __global__ __launch_bounds__(kWgMax) void rows1023p_kernel(
   }
 }
 
+// Post-processing of a paired FFT in U: the DST values (times 4 scale) of
+// outputs k = 4 q + i, i = 0..3, of both sequences (x: a, y: b), from the
+// even outputs directly and the odd ones by the bridged running sum, for the
+// pair's threads s (q = s).  `slot` holds G V2 words for this call.
+template <typename T, int G>
+__device__ __forceinline__ void pair_dst4(const V2<T> *U, int q, T ps, V2<T> *slot, int g, int l64,
+                                          V2<T> (&dv)[4]) {
+  const int k0 = 2 * q, k1 = 2 * q + 1;
+  const V2<T> A0 = U[k0], A1 = U[k1];
+  const V2<T> C0 = U[k0 == 0 ? 0 : kM - k0], C1 = U[kM - k1];
+  const T h0 = k0 == 0 ? T(0.5) : T(1);
+  const V2<T> t0{h0 * (A0.x + C0.x), h0 * (A0.y + C0.y)};
+  const V2<T> t01{t0.x + (A1.x + C1.x), t0.y + (A1.y + C1.y)};
+  V2<T> tot;
+  const V2<T> inc = pair_scan<T, G>(t01, slot, g, l64, tot);
+  const V2<T> ex{inc.x - t01.x, inc.y - t01.y};
+  const T f0 = (T(k0) + T(0.5)) * T(1.0 / 512), f1 = (T(k1) + T(0.5)) * T(1.0 / 512);
+  dv[0] = V2<T>{ps * (C0.y - A0.y), ps * (A0.x - C0.x)};
+  dv[1] = V2<T>{ps * (ex.x + t0.x - f0 * tot.x), ps * (ex.y + t0.y - f0 * tot.y)};
+  dv[2] = V2<T>{ps * (C1.y - A1.y), ps * (A1.x - C1.x)};
+  dv[3] = V2<T>{ps * (ex.x + t01.x - f1 * tot.x), ps * (ex.y + t01.y - f1 * tot.y)};
+}
+
+// w_j = y^a_j + i y^b_j (the pre-weighting above) of the chunk j0 .. j0 + 3
+// from two staged sequences Fa, Fb (1024 values each, zero at both ends),
+// to the FFT input Wv
+template <typename T>
+__device__ __forceinline__ void pair_stage4(const T *Fa, const T *Fb, const V2<T> *post, int j0,
+                                            V2<T> *Wv) {
+  T sv[4];
+  sines4<T>(post, j0, sv);
+  V2<T> w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int j = j0 + i;
+    const T fja = Fa[j], fna = Fa[kM - j], fjb = Fb[j], fnb = Fb[kM - j];
+    w[i].x = sv[i] * (fja + fna) + T(0.5) * (fja - fna);
+    w[i].y = sv[i] * (fjb + fnb) + T(0.5) * (fjb - fnb);
+  }
+  if (j0 + 3 < kM) {
+    T *wp = reinterpret_cast<T *>(Wv + j0);
+    lstore4<T>(wp, {w[0].x, w[0].y, w[1].x, w[1].y});
+    lstore4<T>(wp + 4, {w[2].x, w[2].y, w[3].x, w[3].y});
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Wv[j0 + i] = w[i];
+  }
+}
+
+// Column pass in pairs: the W columns of a workgroup (W even) as W / 2
+// pairs of adjacent columns, each pair one complex FFT per transform on G
+// wavefronts; block I/O of W-column rows as in cols1023_kernel.  LDS per
+// pair: U, whose first 2 x 1024 words also hold the two staged columns
+// before the FFT, and the staging region Z (FFT input, then the filtered
+// coefficients, then the outputs).
+template <typename TS, typename T, int MODE, int G, int W>
+__global__ __launch_bounds__(kWgMax) void cols1023p_kernel(
+    const TS *__restrict__ in, TS *__restrict__ out, int n2, const V2<T> *__restrict__ tw,
+    const V2<T> *__restrict__ post, T alpha, T scale, const TS *__restrict__ dT) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int P = W / 2, BT = 64 * G * P, NR = kLen / BT;
+  static_assert(W % 2 == 0 && G == 4, "pairs of columns on four wavefronts");
+  const int wv = threadIdx.x >> 6;
+  const int pr = wv / G;
+  const int g = __builtin_amdgcn_readfirstlane(wv % G);
+  const int l64 = threadIdx.x & 63;
+  const int s = 64 * g + l64;  // thread within the pair; chunk q = s
+  const int col0 = xcd_remap(blockIdx.x, gridDim.x) * W;
+  const long ld = n2;
+  const Lds<T> L(smem_raw, P, pr);
+  V2<T> *slots = reinterpret_cast<V2<T> *>(smem_raw + x1023_lds_dev(P, sizeof(T))) + 2 * G * pr;
+  const int t = threadIdx.x;
+  const Gl<TS> *blk = gmem(in) + col0;
+  const bool va_in = aligned_to<TS>(in, W * sizeof(TS));
+  const bool va_out = aligned_to<TS>(out, W * sizeof(TS));
+  const bool va_d = aligned_to<TS>(dT, 4 * sizeof(TS));
+  TS bv[NR][W], b0[W], b1[W];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) vload<W>(bv[i], blk + (long)(t + BT * i) * ld, va_in);
+  vload<W>(b0, blk, va_in);
+  vload<W>(b1, blk + (long)(kLen - 1) * ld, va_in);
+  const int ca = col0 + 2 * pr;  // the pair's columns ca, ca + 1 (n2 % W == 0)
+  TS da4[4], db4[4];
+  if (MODE == COL_FWD_D_INV) {
+    vload<4>(da4, gmem(dT) + (size_t)ca * kLen + 4 * s, va_d);
+    vload<4>(db4, gmem(dT) + (size_t)(ca + 1) * kLen + 4 * s, va_d);
+  }
+  Regs<T, G> R;
+  if constexpr (!kLateRegs<T>) R.load(tw, post, G == 4 ? l64 + 64 * (g & 1) : s, s);
+  T e0a = T(0), e1a = T(0), e0b = T(0), e1b = T(0);
+#pragma unroll
+  for (int c = 0; c < W; c += 2)
+    if (2 * pr == c) {
+      e0a = T(b0[c]);
+      e1a = T(b1[c]);
+      e0b = T(b0[c + 1]);
+      e1b = T(b1[c + 1]);
+    }
+  // the block's columns, ramp removed for forward passes, to the U region
+  // of their pair (column 2p at word 0, column 2p + 1 at word 1024)
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    T *Fc = reinterpret_cast<T *>(Lds<T>(smem_raw, P, c / 2).U) + (c & 1) * kLen;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int r = t + BT * i;
+      Fc[r] = zval<T>(T(bv[i][c]), r, MODE != COL_INV, T(b0[c]), T(b1[c]));
+    }
+  }
+  __syncthreads();
+  V2<T> *Wv = reinterpret_cast<V2<T> *>(L.Z);
+  {
+    const T *F = reinterpret_cast<const T *>(L.U);
+    pair_stage4<T>(F, F + kLen, post, 4 * s, Wv);
+  }
+  __syncthreads();
+  fft1023<T, G>(L.U, L.Z, R, tw, post, g, l64, s);
+  const T ps = T(2) * scale;
+  const T invM = T(1) / T(kM);
+  V2<T> dv[4];
+  pair_dst4<T, G>(L.U, s, ps, slots, g, l64, dv);
+  T oa[4], ob[4];
+  if constexpr (MODE == COL_FWD_D_INV) {
+    // filtered coefficients d_k (T~ y)_k of both columns to Z, then the
+    // inverse transform's input from them (endpoints through the words at
+    // k = 0 and k = M)
+    T *Fa = L.Z, *Fb = L.Z + kLen;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * s + i;
+      const T xa = k == 0 ? alpha * e0a : (k == kM ? alpha * e1a : dv[i].x);
+      const T xb = k == 0 ? alpha * e0b : (k == kM ? alpha * e1b : dv[i].y);
+      oa[i] = T(da4[i]) * xa;
+      ob[i] = T(db4[i]) * xb;
+    }
+    lstore4<T>(Fa + 4 * s, oa);
+    lstore4<T>(Fb + 4 * s, ob);
+    __syncthreads();
+    e0a = Fa[0];
+    e1a = Fa[kM];
+    e0b = Fb[0];
+    e1b = Fb[kM];
+    T ga[4], gb[4], gma[4], gmb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = 4 * s + i;
+      ga[i] = (j == 0 || j == kM) ? T(0) : Fa[j];
+      gb[i] = (j == 0 || j == kM) ? T(0) : Fb[j];
+      gma[i] = (j == 0 || j == kM) ? T(0) : Fa[kM - j];
+      gmb[i] = (j == 0 || j == kM) ? T(0) : Fb[kM - j];
+    }
+    __syncthreads();
+    {
+      T sv[4];
+      sines4<T>(post, 4 * s, sv);
+      V2<T> w[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        w[i].x = sv[i] * (ga[i] + gma[i]) + T(0.5) * (ga[i] - gma[i]);
+        w[i].y = sv[i] * (gb[i] + gmb[i]) + T(0.5) * (gb[i] - gmb[i]);
+      }
+      const int j0 = 4 * s;
+      if (j0 + 3 < kM) {
+        T *wp = reinterpret_cast<T *>(Wv + j0);
+        lstore4<T>(wp, {w[0].x, w[0].y, w[1].x, w[1].y});
+        lstore4<T>(wp + 4, {w[2].x, w[2].y, w[3].x, w[3].y});
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Wv[j0 + i] = w[i];
+      }
+    }
+    __syncthreads();
+    fft1023<T, G>(L.U, L.Z, R, tw, post, g, l64, s);
+    pair_dst4<T, G>(L.U, s, ps, slots + G, g, l64, dv);
+  }
+  // outputs of both columns in natural order to Z, then row by row
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = 4 * s + i;
+    if (MODE == COL_FWD) {
+      oa[i] = k == 0 ? alpha * e0a : (k == kM ? alpha * e1a : dv[i].x);
+      ob[i] = k == 0 ? alpha * e0b : (k == kM ? alpha * e1b : dv[i].y);
+    } else {
+      const T y0a = e0a / alpha, y1a = e1a / alpha, y0b = e0b / alpha, y1b = e1b / alpha;
+      const T wl = T(kM - k) * invM, wr = T(k) * invM;
+      oa[i] = k == 0 ? y0a : (k == kM ? y1a : dv[i].x + y0a * wl + y1a * wr);
+      ob[i] = k == 0 ? y0b : (k == kM ? y1b : dv[i].y + y0b * wl + y1b * wr);
+    }
+  }
+  lstore4<T>(L.Z + 4 * s, oa);
+  lstore4<T>(L.Z + kLen + 4 * s, ob);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int r = t + BT * i;
+    TS v[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) v[c] = TS(Lds<T>(smem_raw, P, c / 2).Z[(c & 1) * kLen + r]);
+    vstore<W>(gmem(out) + col0 + (long)r * ld, v, va_out);
+  }
+}
+
+template <typename TS, typename T, int W>
+int colsp_t(const void *in, void *out, int n2, size_t smem, int mode, const void *tw,
+            const void *post, double alpha, double scale, const void *dT, hipStream_t st) {
+  const dim3 grid(n2 / W), block(64 * 4 * (W / 2));
+  auto ti = static_cast<const TS *>(in);
+  auto to = static_cast<TS *>(out);
+  auto td = static_cast<const TS *>(dT);
+  auto ttw = static_cast<const V2<T> *>(tw);
+  auto tp = static_cast<const V2<T> *>(post);
+  hipError_t e = hipSuccess;
+#define AR_X(MODE)                                                                              \
+  e = smem > 64 * 1024                                                                          \
+          ? hipFuncSetAttribute(                                                                \
+                reinterpret_cast<const void *>(cols1023p_kernel<TS, T, MODE, 4, W>),            \
+                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)                          \
+          : hipSuccess;                                                                         \
+  if (e == hipSuccess) {                                                                        \
+    hipLaunchKernelGGL((cols1023p_kernel<TS, T, MODE, 4, W>), grid, block, smem, st, ti, to,    \
+                       n2, ttw, tp, T(alpha), T(scale), td);                                    \
+    e = hipGetLastError();                                                                      \
+  }
+  switch (mode) {
+    case COL_FWD: AR_X(COL_FWD) break;
+    case COL_INV: AR_X(COL_INV) break;
+    default: AR_X(COL_FWD_D_INV) break;
+  }
+#undef AR_X
+  return e == hipSuccess ? AR_OK : hip_fail(e, "cols1023p_kernel launch");
+}
+
 template <typename TS, typename T, int G>
 int rowsp_t(const void *in, void *out, int n1, int P, size_t smem, int mode, const void *tw,
             const void *post, double alpha, double scale, double tau, const void *f_true,
@@ -839,8 +1071,23 @@ size_t x1023_lds(int W, size_t csize) {
 
 int x1023_cap(int G) { return kWgMax / (64 * G); }
 
-// U and staging of P pairs, then 4 running-sum slots (V2) per pair
-size_t x1023_pair_lds(int P, size_t csize) { return x1023_lds_dev(P, csize) + 8 * csize * P; }
+// U and staging of P pairs, then 8 running-sum slots (V2) per pair
+size_t x1023_pair_lds(int P, size_t csize) { return x1023_lds_dev(P, csize) + 16 * csize * P; }
+
+int x1023_cols_pair_launch(size_t ts, size_t cs, const void *in, void *out, int n2, int W,
+                           size_t smem, int mode, const void *tw, const void *post, double alpha,
+                           double scale, const void *dT, hipStream_t st) {
+  if ((W != 2 && W != 4) || n2 % W || smem < x1023_pair_lds(W / 2, cs))
+    return fail(AR_EUNSUPPORTED, "length-1024 paired column pass: bad launch shape");
+  if (cs != 8) return fail(AR_EUNSUPPORTED, "length-1024 paired column pass: FP64 arithmetic only");
+#define AR_W(TS)                                                                               \
+  return W == 4 ? colsp_t<TS, double, 4>(in, out, n2, smem, mode, tw, post, alpha, scale, dT,  \
+                                         st)                                                   \
+                : colsp_t<TS, double, 2>(in, out, n2, smem, mode, tw, post, alpha, scale, dT, st)
+  if (ts == 8) { AR_W(double); }
+  AR_W(float);
+#undef AR_W
+}
 
 int x1023_rows_pair_launch(size_t ts, size_t cs, const void *in, void *out, int n1, int W, int G,
                            size_t smem, int mode, const void *tw, const void *post, double alpha,

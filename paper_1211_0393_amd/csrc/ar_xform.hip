@@ -1301,8 +1301,16 @@ static int wave_cols_d(const ar_plan_s *p, const void *in, void *out, int mode, 
   if (is_plan1023(w)) {
     if (gl == 1) return wave_cols_t<TS, T, false, 1, kPlan1023>(p, w, in, out, mode, jobs, count, st);
     const int W = cols_waves(p, w);
-    const size_t smem = excl_pad(x1023_lds(W, sizeof(T)), p->tune[AR_TUNE_COL_EXCL]);
     const double m = p->n1, M = w.M;
+    // columns in pairs for FP64 arithmetic (as the row passes)
+    if (!jobs && W % 2 == 0 && sizeof(T) == 8) {
+      const size_t psmem = excl_pad(x1023_pair_lds(W / 2, sizeof(T)), p->tune[AR_TUNE_COL_EXCL]);
+      return x1023_cols_pair_launch(sizeof(TS), sizeof(T), in, out, p->n2, W, psmem, mode, w.tw,
+                                    p->fft_col.post,
+                                    std::sqrt(m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))),
+                                    std::sqrt(2.0 / M) / 4.0, p->dT, st);
+    }
+    const size_t smem = excl_pad(x1023_lds(W, sizeof(T)), p->tune[AR_TUNE_COL_EXCL]);
     return x1023_cols_launch(sizeof(TS), sizeof(T), in, out, p->n2, W, gl, smem, mode, w.tw,
                              p->fft_col.post, std::sqrt(m * (2.0 * m - 1.0) / (6.0 * (m - 1.0))),
                              std::sqrt(2.0 / M) / 4.0, p->dT, jobs, count, st);

@@ -551,6 +551,40 @@ def test_row_passes_in_pairs(n1, waves, dt):
 
 
 @pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("waves", [1, 2, 4])
+@pytest.mark.parametrize("n2", [1024, 36, 34, 7])
+def test_column_passes_in_pairs(n2, waves, dt):
+    """Columns of length 1024 in workgroups of an even number of columns run
+    in pairs of adjacent columns (one complex FFT per pair and transform) in
+    FP64-arithmetic passes: the forward, inverse and fused filter passes
+    against the oracle; odd column counts keep one column per FFT."""
+    say(f"paired columns n2={n2} waves={waves} {dt}")
+    rng = np.random.default_rng(n2 + 13 * waves)
+    X = rng.standard_normal((1024, n2)).astype(NDT[dt]).astype(np.float64)
+    H = synth.psf_random(3, 2, seed=6)
+    with P.Plan(1024, n2, H, dtype=dt) as plan:
+        plan.ar_plan_tune(P.AR_TUNE_COL_WAVES, waves)
+        x = dev(X, TDT[dt])
+        c = torch.empty_like(x)
+        plan.ar_transform(x, c)
+        e = rel(host(c), O.ar_fwd(X))
+        say(f"  fwd rel err {e:.2e}")
+        assert e <= TOL_T[dt], e
+        Cq = host(c).astype(NDT[dt]).astype(np.float64)
+        xr = torch.empty_like(x)
+        plan.ar_transform_inv(dev(Cq, TDT[dt]), xr)
+        e = rel(host(xr), O.ar_inv(Cq))
+        say(f"  inv rel err {e:.2e}")
+        assert e <= TOL_T[dt], e
+        plan.ar_precond_set(P.AR_FILTER_TIKHONOV, 0.05)
+        plan.ar_precond_solve(x, xr)
+        d = O.tikhonov(O.eigenvalues(H, 1024, n2), 0.05)
+        e = rel(host(xr), O.precond_apply(X, d))
+        say(f"  solve rel err {e:.2e}")
+        assert e <= TOL_D[dt], e
+
+
+@pytest.mark.parametrize("dt", DTS)
 @pytest.mark.parametrize("algo", [1, 2])
 @pytest.mark.parametrize("n1,n2", [(128, 96), (256, 300), (193, 385), (1024, 1024), (512, 129)])
 def test_transform_fft_forms(n1, n2, algo, dt):

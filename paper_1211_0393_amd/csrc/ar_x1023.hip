@@ -22,8 +22,9 @@
 //     sequence (the radix-11 pairs to pairs of wavefronts when G = 4);
 //   * the column pass stages its filtered coefficients as the odd extension
 //     of the inverse transform's input directly;
-//   * rows may also run in pairs, two per complex FFT of length M (see
-//     rows1023p_kernel), which halves the FFTs of a row pass.
+//   * in FP64 arithmetic rows and columns may also run in pairs, two per
+//     complex FFT of length M (rows1023p_kernel, cols1023p_kernel), which
+//     halves the FFTs of a pass.
 // Stages (radix, stride L, twiddle offset in the plan's table): (31, 1, 0),
 // (11, 31, 30), (3, 341, 340); natural input index n = 33 d0 + 3 d1 + d2
 // sits at position d0 + 31 d1 + 341 d2 of the in-place DIT order, so

@@ -240,9 +240,14 @@ int ar_deblur_iterate_noalloc(ar_plan_t p, const void *g, void *x, int iters, do
                               double *resnorm_host, double *rre_host, int *best_it_host,
                               void *stream);
 
-/* Launch tunables of a plan (they change speed, never results).
+/* Launch tunables of a plan (they change speed; where they change the
+ * arithmetic, results agree to rounding, as stated below).
  *  AR_TUNE_ROW_WAVES / AR_TUNE_COL_WAVES : rows (columns) transformed per
- *      workgroup by the wave-per-sequence transform, 1, 2 or 4 (0 = auto)
+ *      workgroup by the wave-per-sequence transform, 1, 2 or 4 (0 = auto);
+ *      on an axis of length 1024, the FP64-arithmetic passes of a workgroup
+ *      with an even count take its rows (columns) in pairs, two per complex
+ *      FFT (a pre-weighted DST-I form with a running sum for the odd
+ *      outputs), equal to the one-per-FFT form up to rounding
  *  AR_TUNE_ROW_EXCL / AR_TUNE_COL_EXCL   : 1 = reserve a whole CU per
  *      workgroup of that pass (spreads few workgroups over all CUs)
  *  AR_TUNE_ROW_ALGO / AR_TUNE_COL_ALGO   : FFT of the DST-I, 1 = mixed

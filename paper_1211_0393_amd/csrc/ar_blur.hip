@@ -168,6 +168,14 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
     constexpr int KWc = 2 * Q2 + 1;
     constexpr int NV = RX + 2 * Q2;
     const T *sw = tile + (size_t)LH * pitch;
+    // FP64 tiles read their weights with scalar loads straight from the
+    // weight array (workgroup-uniform addresses), which keeps them out of
+    // the vector registers and the LDS port; FP32 tiles broadcast them from
+    // the LDS copy
+    auto wt = [&](int e) -> T {
+      if constexpr (sizeof(T) == 8) return gw[e];
+      else return sw[e];
+    };
     const int klast = 2 * q1;
     T va[NV], vb[NV], wa[KWc], wb[KWc];
     {
@@ -175,7 +183,7 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
 #pragma unroll
       for (int t = 0; t < NV; ++t) va[t] = rowp[t];
 #pragma unroll
-      for (int b = 0; b < KWc; ++b) wa[b] = sw[b];
+      for (int b = 0; b < KWc; ++b) wa[b] = wt(b);
     }
     for (int k = 0; k < krows; k += 2) {
       // row k: input in va, PSF row k in wa, PSF row k - 1 in wb
@@ -194,7 +202,7 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
       {
         const int wn = k + 1 <= klast ? k + 1 : klast;
 #pragma unroll
-        for (int b = 0; b < KWc; ++b) wb[b] = sw[wn * KWc + b];
+        for (int b = 0; b < KWc; ++b) wb[b] = wt(wn * KWc + b);
       }
 #pragma unroll
       for (int b = 0; b < KWc; ++b)
@@ -216,7 +224,7 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
       {
         const int wn = k + 2 <= klast ? k + 2 : klast;
 #pragma unroll
-        for (int b = 0; b < KWc; ++b) wa[b] = sw[wn * KWc + b];
+        for (int b = 0; b < KWc; ++b) wa[b] = wt(wn * KWc + b);
       }
       if (k + 1 <= klast) {
 #pragma unroll

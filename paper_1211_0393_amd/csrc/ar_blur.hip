@@ -7,7 +7,8 @@
 // corners: the double anti-reflection 4, -2, -2, +1 obtained by applying the
 // 1-D rule per axis).  Every thread then produces RY x RX outputs with a
 // sliding window over input rows so that one LDS row feeds two output rows;
-// PSF weights are wave-uniform and come through scalar loads.
+// PSF weights are workgroup-uniform: FP32 tiles broadcast them from an LDS
+// copy, FP64 tiles read them with scalar loads.
 //
 // The same kernel computes
 //   * A x          : weights rot180(H), AR extension, outputs on the FOV;
@@ -98,7 +99,8 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
   constexpr int WPT = 4;
   const int P = (2 * q1 + 1) * KW;
   T wpre[WPT];
-  if constexpr (!GEN) {
+  constexpr bool kLdsW = !GEN && sizeof(T) != 8;  // weights staged in LDS
+  if constexpr (kLdsW) {
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
       const int e = tid + NT * i;
@@ -136,7 +138,7 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
         }
     }
   }
-  if constexpr (!GEN) {
+  if constexpr (kLdsW) {
     T *swr = tile + (size_t)LH * pitch;
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {

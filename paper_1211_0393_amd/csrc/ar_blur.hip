@@ -93,7 +93,7 @@ __device__ __forceinline__ void conv_tile(unsigned char *smem_raw, const TS *__r
   // unconditional addresses) and then stores them, so a chunk costs one
   // memory latency instead of one per element
   const int lr = tid >> 6, lc = tid & 63;
-  constexpr int CR = 12, CC = 2;  // rows x column-sweeps per chunk
+  constexpr int CR = 6, CC = 2;  // rows x column-sweeps per chunk
   // the PSF copy for LDS is loaded first, so that its latency overlaps
   // the halo loads
   constexpr int WPT = 4;

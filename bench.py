@@ -80,6 +80,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="skip the plan autotuner")
+    ap.add_argument("--tuning", default=None,
+                    help="JSON object of launch settings (the keys of the output's 'tuning') "
+                         "to set instead of autotuning, e.g. to repeat a run's choice under a "
+                         "profiler, whose per-dispatch overhead would mislead the autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-bc", action="store_true",
                     help="skip the Reflective / Periodic and direct-solve legs")
@@ -598,13 +602,19 @@ def main():
     plan.ar_precond_set(P.AR_FILTER_TIKHONOV, a.alpha)
     n = p["n"]
     stream = torch.cuda.current_stream()
-    tuned_us = plan.ar_plan_autotune() if not a.no_tune else None
-    tuning = {k: plan.ar_plan_get_tune(v) for k, v in
-              [("row_waves", P.AR_TUNE_ROW_WAVES), ("col_waves", P.AR_TUNE_COL_WAVES),
-               ("row_excl", P.AR_TUNE_ROW_EXCL), ("col_excl", P.AR_TUNE_COL_EXCL),
-               ("row_fft", P.AR_TUNE_ROW_ALGO), ("col_fft", P.AR_TUNE_COL_ALGO),
-               ("row_lanes", P.AR_TUNE_ROW_LANES), ("col_lanes", P.AR_TUNE_COL_LANES),
-               ("blur_engine", P.AR_TUNE_BLUR)]}
+    keys = {"row_waves": P.AR_TUNE_ROW_WAVES, "col_waves": P.AR_TUNE_COL_WAVES,
+            "row_excl": P.AR_TUNE_ROW_EXCL, "col_excl": P.AR_TUNE_COL_EXCL,
+            "row_fft": P.AR_TUNE_ROW_ALGO, "col_fft": P.AR_TUNE_COL_ALGO,
+            "row_lanes": P.AR_TUNE_ROW_LANES, "col_lanes": P.AR_TUNE_COL_LANES,
+            "blur_engine": P.AR_TUNE_BLUR}
+    tuned_us = None
+    if a.tuning:
+        for k, v in json.loads(a.tuning).items():
+            if k in keys:
+                plan.ar_plan_tune(keys[k], int(v))
+    elif not a.no_tune:
+        tuned_us = plan.ar_plan_autotune()
+    tuning = {k: plan.ar_plan_get_tune(v) for k, v in keys.items()}
     x = torch.zeros_like(g)
 
     def runs(total):

@@ -157,7 +157,7 @@ int seqs_per_block(int M, size_t csize, int target) {
   return B;
 }
 int rows_per_block(int M, size_t csize) { return seqs_per_block(M, csize, 2048); }
-int cols_per_block(int M, size_t csize) { return seqs_per_block(M, csize, 4096); }
+int cols_per_block(int M, size_t csize) { return seqs_per_block(M, csize, 2048); }
 
 size_t seq_lds_bytes(int B, int M, size_t csize) {
   return 2 * (size_t)B * M * 2 * csize + 2 * (size_t)B * csize + 64;
